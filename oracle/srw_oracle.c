@@ -1,0 +1,730 @@
+/*
+ * srw_oracle.c -- plain, slow, single-threaded CPU oracle for shortest reset
+ * words.  TEST INFRASTRUCTURE ONLY: the library never links, loads or calls
+ * anything in this file; only the test suite, the smoke check and the CPU
+ * baseline of the benchmark do.  It shares no code with the GPU path.
+ *
+ * What it computes (paper: Szykula & Zyzik, "An Improved Algorithm for
+ * Finding the Shortest Synchronizing Words"):
+ *   - the reset threshold r = min |w| with |delta(Q,w)| = 1   (Section 1)
+ *   - the lexicographically least reset word of length r (letters ordered by
+ *     index); the paper returns "a" shortest word via predecessor pointers
+ *     (end of Section 2 intro) without fixing which one, so the lex-least one
+ *     is the reading taken here.
+ *
+ * Functions and the passage each follows:
+ *   orc_is_synchronizing  pair-merging test, Section 2 intro (every pair of
+ *                         states can be mapped to one state)
+ *   orc_image/preimage    the two definitions at the start of Section 2
+ *   orc_bruteforce        trivial algorithm of Section 1.3: all words of
+ *                         length 0,1,2,... in lex order
+ *   orc_exhaustive        standard power-automaton BFS over all 2^n subsets
+ *                         (Section 1.3.1), n <= 24
+ *   orc_forward           forward BFS over subsets from Q (one side of
+ *                         Alg. 1), stops at the first singleton
+ *   orc_bidir             plain bidirectional BFS (Alg. 1 with only the
+ *                         duplicate removal kept): forward images from Q,
+ *                         inverse preimages from the singletons, meet test
+ *                         X subset-of Y after every step.  The meet is either
+ *                         brute force over all pairs (the definition) or
+ *                         Alg. 2 MarkSupersets followed by a scan of the
+ *                         marked sets for the least pair.
+ *
+ * Ordering conventions (these make the returned word the lex-least one):
+ *   forward level: candidate key g = i*k + a (parent index i, letter a)
+ *   inverse level: candidate key g = a*|L| + i (letter-major; the letter
+ *                  applied last is the FIRST letter of the inverse half)
+ *   duplicates: the smallest key wins; sets already seen on an earlier level
+ *   of the same side are dropped; empty preimages are dropped.
+ *
+ * Dedup here is by lexicographic sort, the paper's own method (Alg. 1).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef uint64_t u64;
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ENOTSYNC (-2)
+#define ORC_ELIMIT (-3)
+#define ORC_ENOMEM (-4)
+#define ORC_EWORDCAP (-5)
+
+#define ORC_MAX_N 512
+
+static int nwords(int n) { return (n + 63) / 64; }
+
+static int check_input(int n, int k, const int32_t *delta) {
+    if (n < 1 || n > ORC_MAX_N || k < 1 || k > 255 || !delta) return ORC_EINVAL;
+    for (int64_t i = 0; i < (int64_t)n * k; i++)
+        if (delta[i] < 0 || delta[i] >= n) return ORC_EINVAL;
+    return ORC_OK;
+}
+
+static int getbit(const u64 *S, int q) { return (int)((S[q >> 6] >> (q & 63)) & 1u); }
+static void setbit(u64 *S, int q) { S[q >> 6] |= (u64)1 << (q & 63); }
+
+static int popcount_set(const u64 *S, int W) {
+    int c = 0;
+    for (int w = 0; w < W; w++) c += __builtin_popcountll(S[w]);
+    return c;
+}
+
+/* delta(S, a) = { delta(q, a) | q in S }  (Section 2) */
+void orc_image(int n, int k, const int32_t *delta, int a, const u64 *S, u64 *X) {
+    int W = nwords(n);
+    (void)k;
+    memset(X, 0, sizeof(u64) * W);
+    for (int q = 0; q < n; q++)
+        if (getbit(S, q)) setbit(X, delta[(int64_t)a * n + q]);
+}
+
+/* delta^-1(S, a) = { q | delta(q, a) in S }  (Section 2) */
+void orc_preimage(int n, int k, const int32_t *delta, int a, const u64 *S, u64 *Y) {
+    int W = nwords(n);
+    (void)k;
+    memset(Y, 0, sizeof(u64) * W);
+    for (int q = 0; q < n; q++)
+        if (getbit(S, delta[(int64_t)a * n + q])) setbit(Y, q);
+}
+
+/* The automaton is synchronizing iff every pair {p,q} can be mapped to a
+ * single state.  Mergeable pairs are the least fixpoint of: {p,p} is
+ * mergeable; {p,q} is mergeable if some letter maps it to a mergeable pair. */
+int orc_is_synchronizing(int n, int k, const int32_t *delta) {
+    int rc = check_input(n, k, delta);
+    if (rc) return rc;
+    unsigned char *m = calloc((size_t)n * n, 1);
+    if (!m) return ORC_ENOMEM;
+    for (int p = 0; p < n; p++) m[(size_t)p * n + p] = 1;
+    int changed = 1;
+    while (changed) {
+        changed = 0;
+        for (int p = 0; p < n; p++)
+            for (int q = p + 1; q < n; q++) {
+                if (m[(size_t)p * n + q]) continue;
+                for (int a = 0; a < k; a++) {
+                    int pp = delta[(int64_t)a * n + p], qq = delta[(int64_t)a * n + q];
+                    if (m[(size_t)pp * n + qq]) {
+                        m[(size_t)p * n + q] = m[(size_t)q * n + p] = 1;
+                        changed = 1;
+                        break;
+                    }
+                }
+            }
+    }
+    int all = 1;
+    for (int p = 0; p < n && all; p++)
+        for (int q = p + 1; q < n; q++)
+            if (!m[(size_t)p * n + q]) { all = 0; break; }
+    free(m);
+    return all;
+}
+
+/* 1 if |delta(Q, word)| = 1, 0 if not, <0 on bad input (Section 1). */
+int orc_verify(int n, int k, const int32_t *delta, const uint8_t *word, int64_t len) {
+    int rc = check_input(n, k, delta);
+    if (rc) return rc;
+    int W = nwords(n);
+    u64 S[8], X[8];
+    memset(S, 0, sizeof S);
+    for (int q = 0; q < n; q++) setbit(S, q);
+    for (int64_t i = 0; i < len; i++) {
+        if (word[i] >= k) return ORC_EINVAL;
+        orc_image(n, k, delta, word[i], S, X);
+        memcpy(S, X, sizeof(u64) * W);
+    }
+    return popcount_set(S, W) == 1;
+}
+
+/* ---------------- trivial algorithm: all words in lex order ------------- */
+
+static int bf_search(int n, int k, const int32_t *delta, int W, int depth, int len,
+                     const u64 *S, uint8_t *word) {
+    if (depth == len) return popcount_set(S, W) == 1;
+    u64 X[8];
+    for (int a = 0; a < k; a++) {
+        orc_image(n, k, delta, a, S, X);
+        word[depth] = (uint8_t)a;
+        if (bf_search(n, k, delta, W, depth + 1, len, X, word)) return 1;
+    }
+    return 0;
+}
+
+/* Checks every word of length 0,1,...,max_len in lexicographic order and
+ * returns the first reset word (Section 1.3, the trivial O(n k^r) method). */
+int orc_bruteforce(int n, int k, const int32_t *delta, int max_len,
+                   int32_t *r, uint8_t *word, int64_t word_cap) {
+    int rc = check_input(n, k, delta);
+    if (rc) return rc;
+    int W = nwords(n);
+    u64 Q[8];
+    memset(Q, 0, sizeof Q);
+    for (int q = 0; q < n; q++) setbit(Q, q);
+    uint8_t *buf = malloc((size_t)max_len + 1);
+    if (!buf) return ORC_ENOMEM;
+    for (int len = 0; len <= max_len; len++) {
+        if (bf_search(n, k, delta, W, 0, len, Q, buf)) {
+            *r = len;
+            if (word) {
+                if (word_cap < len) { free(buf); return ORC_EWORDCAP; }
+                memcpy(word, buf, (size_t)len);
+            }
+            free(buf);
+            return ORC_OK;
+        }
+    }
+    free(buf);
+    return ORC_ELIMIT;
+}
+
+/* ------------- standard power-automaton BFS over all 2^n subsets ------- */
+
+/* Breadth-first search in the power automaton from Q (Section 1.3.1).  The
+ * queue is processed first-in first-out and letters in increasing order, so
+ * the first visit of a subset is by its lex-least shortest word.  r is the
+ * least distance of a singleton; among singletons at that distance the one
+ * discovered first carries the lex-least word.  n <= 24. */
+int orc_exhaustive(int n, int k, const int32_t *delta, int32_t *r,
+                   uint8_t *word, int64_t word_cap) {
+    int rc = check_input(n, k, delta);
+    if (rc) return rc;
+    if (n > 24) return ORC_EINVAL;
+    size_t N = (size_t)1 << n;
+    int32_t *dist = malloc(N * sizeof(int32_t));
+    uint32_t *from = malloc(N * sizeof(uint32_t));
+    uint8_t *via = malloc(N);
+    uint32_t *queue = malloc(N * sizeof(uint32_t));
+    if (!dist || !from || !via || !queue) {
+        free(dist); free(from); free(via); free(queue);
+        return ORC_ENOMEM;
+    }
+    for (size_t i = 0; i < N; i++) dist[i] = -1;
+    uint32_t full = (uint32_t)(N - 1);
+    size_t head = 0, tail = 0;
+    dist[full] = 0;
+    queue[tail++] = full;
+    while (head < tail) {
+        uint32_t S = queue[head++];
+        for (int a = 0; a < k; a++) {
+            uint32_t X = 0;
+            for (int q = 0; q < n; q++)
+                if (S >> q & 1u) X |= 1u << delta[(int64_t)a * n + q];
+            if (dist[X] < 0) {
+                dist[X] = dist[S] + 1;
+                from[X] = S;
+                via[X] = (uint8_t)a;
+                queue[tail++] = X;
+            }
+        }
+    }
+    /* singletons in discovery order */
+    int best = -1;
+    uint32_t best_set = 0;
+    for (size_t i = 0; i < tail; i++) {
+        uint32_t X = queue[i];
+        if (__builtin_popcount(X) == 1) {
+            if (best < 0 || dist[X] < best) { best = dist[X]; best_set = X; }
+            break; /* BFS order is nondecreasing in distance: first is least */
+        }
+    }
+    int out = ORC_OK;
+    if (best < 0) {
+        out = ORC_ENOTSYNC;
+    } else {
+        *r = best;
+        if (word) {
+            if (word_cap < best) out = ORC_EWORDCAP;
+            else {
+                uint32_t X = best_set;
+                for (int i = best - 1; i >= 0; i--) { word[i] = via[X]; X = from[X]; }
+            }
+        }
+    }
+    free(dist); free(from); free(via); free(queue);
+    return out;
+}
+
+/* ---------------------- level lists with sorted dedup ------------------- */
+
+typedef struct {
+    int W;
+    u64 *rows;          /* all visited sets of this side, level after level */
+    int64_t *par;       /* candidate key g that produced the row (-1 at level 0) */
+    int64_t nrows, cap;
+    int64_t *off;       /* level L holds rows off[L] .. off[L+1]-1 */
+    int nlev, levcap;
+    int64_t *sorted;    /* row ids of all visited rows in row order */
+} Side;
+
+static const u64 *g_rows;
+static int g_W;
+
+static int rowcmp(const u64 *a, const u64 *b, int W) {
+    for (int w = 0; w < W; w++) {
+        if (a[w] < b[w]) return -1;
+        if (a[w] > b[w]) return 1;
+    }
+    return 0;
+}
+
+/* order candidates by (set, key) */
+static int cmp_cand(const void *pa, const void *pb) {
+    int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
+    int c = rowcmp(g_rows + a * g_W, g_rows + b * g_W, g_W);
+    if (c) return c;
+    return (a > b) - (a < b);
+}
+
+static int side_reserve(Side *s, int64_t more) {
+    if (s->nrows + more > s->cap) {
+        int64_t nc = s->cap ? s->cap : 1024;
+        while (nc < s->nrows + more) nc *= 2;
+        u64 *r = realloc(s->rows, (size_t)nc * s->W * sizeof(u64));
+        if (!r) return ORC_ENOMEM;
+        s->rows = r;
+        int64_t *p = realloc(s->par, (size_t)nc * sizeof(int64_t));
+        if (!p) return ORC_ENOMEM;
+        s->par = p;
+        int64_t *so = realloc(s->sorted, (size_t)nc * sizeof(int64_t));
+        if (!so) return ORC_ENOMEM;
+        s->sorted = so;
+        s->cap = nc;
+    }
+    if (s->nlev + 2 > s->levcap) {
+        int nl = s->levcap ? s->levcap * 2 : 64;
+        int64_t *o = realloc(s->off, (size_t)nl * sizeof(int64_t));
+        if (!o) return ORC_ENOMEM;
+        s->off = o;
+        s->levcap = nl;
+    }
+    return ORC_OK;
+}
+
+static void side_free(Side *s) {
+    free(s->rows); free(s->par); free(s->off); free(s->sorted);
+    memset(s, 0, sizeof *s);
+}
+
+static int64_t level_size(const Side *s, int L) { return s->off[L + 1] - s->off[L]; }
+static const u64 *level_row(const Side *s, int L, int64_t i) {
+    return s->rows + (s->off[L] + i) * s->W;
+}
+
+/* binary search of a set among the visited rows */
+static int visited(const Side *s, const u64 *x) {
+    int64_t lo = 0, hi = s->nrows;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        int c = rowcmp(s->rows + s->sorted[mid] * s->W, x, s->W);
+        if (c == 0) return 1;
+        if (c < 0) lo = mid + 1; else hi = mid;
+    }
+    return 0;
+}
+
+/* Appends a new level made of the candidates cand[0..C-1] (key = index):
+ * empty sets dropped, the least key of each set kept, sets already visited
+ * dropped, survivors stored in key order. */
+static int side_push_level(Side *s, const u64 *cand, int64_t C) {
+    int W = s->W;
+    int64_t *idx = malloc((size_t)(C ? C : 1) * sizeof(int64_t));
+    unsigned char *keep = calloc((size_t)(C ? C : 1), 1);
+    if (!idx || !keep) { free(idx); free(keep); return ORC_ENOMEM; }
+    for (int64_t g = 0; g < C; g++) idx[g] = g;
+    g_rows = cand; g_W = W;
+    qsort(idx, (size_t)C, sizeof(int64_t), cmp_cand);
+    int64_t U = 0;
+    for (int64_t t = 0; t < C; t++) {
+        int64_t g = idx[t];
+        if (t > 0 && rowcmp(cand + idx[t - 1] * W, cand + g * W, W) == 0) continue;
+        if (popcount_set(cand + g * W, W) == 0) continue;
+        if (visited(s, cand + g * W)) continue;
+        keep[g] = 1;
+        U++;
+    }
+    int rc = side_reserve(s, U);
+    if (rc) { free(idx); free(keep); return rc; }
+    int64_t base = s->nrows;
+    int64_t pos = base;
+    for (int64_t g = 0; g < C; g++) {
+        if (!keep[g]) continue;
+        memcpy(s->rows + pos * W, cand + g * W, sizeof(u64) * W);
+        s->par[pos] = g;
+        pos++;
+    }
+    /* merge the new rows into the sorted visited index */
+    int64_t *newsorted = malloc((size_t)(U ? U : 1) * sizeof(int64_t));
+    int64_t *merged = malloc((size_t)(s->nrows + U ? s->nrows + U : 1) * sizeof(int64_t));
+    if (!newsorted || !merged) { free(idx); free(keep); free(newsorted); free(merged); return ORC_ENOMEM; }
+    for (int64_t i = 0; i < U; i++) newsorted[i] = base + i;
+    g_rows = s->rows; g_W = W;
+    qsort(newsorted, (size_t)U, sizeof(int64_t), cmp_cand);
+    int64_t a = 0, b = 0, m = 0;
+    while (a < s->nrows || b < U) {
+        if (b >= U || (a < s->nrows &&
+                       rowcmp(s->rows + s->sorted[a] * W, s->rows + newsorted[b] * W, W) < 0))
+            merged[m++] = s->sorted[a++];
+        else
+            merged[m++] = newsorted[b++];
+    }
+    memcpy(s->sorted, merged, (size_t)m * sizeof(int64_t));
+    free(newsorted); free(merged);
+    s->nrows += U;
+    s->off[s->nlev + 1] = s->nrows;
+    s->nlev++;
+    free(idx); free(keep);
+    return ORC_OK;
+}
+
+static int side_init(Side *s, int W, const u64 *rows, int64_t count) {
+    memset(s, 0, sizeof *s);
+    s->W = W;
+    int rc = side_reserve(s, count);
+    if (rc) return rc;
+    s->off[0] = 0;
+    s->nlev = 0;
+    /* level 0: keep the given order; its "keys" are the positions */
+    rc = side_push_level(s, rows, count);
+    if (rc) return rc;
+    for (int64_t i = 0; i < s->nrows; i++) s->par[i] = -1;
+    return ORC_OK;
+}
+
+/* forward step: L <- { delta(S, a) }, key g = i*k + a */
+static int step_forward(Side *s, int n, int k, const int32_t *delta) {
+    int W = s->W;
+    int L = s->nlev - 1;
+    int64_t m = level_size(s, L);
+    u64 *cand = malloc((size_t)((m * k) > 0 ? m * k : 1) * W * sizeof(u64));
+    if (!cand) return ORC_ENOMEM;
+    for (int64_t i = 0; i < m; i++)
+        for (int a = 0; a < k; a++)
+            orc_image(n, k, delta, a, level_row(s, L, i), cand + (i * k + a) * W);
+    int rc = side_push_level(s, cand, m * k);
+    free(cand);
+    return rc;
+}
+
+/* inverse step: L <- { delta^-1(S, a) }, key g = a*|L| + i */
+static int step_inverse(Side *s, int n, int k, const int32_t *delta) {
+    int W = s->W;
+    int L = s->nlev - 1;
+    int64_t m = level_size(s, L);
+    u64 *cand = malloc((size_t)((m * k) > 0 ? m * k : 1) * W * sizeof(u64));
+    if (!cand) return ORC_ENOMEM;
+    for (int a = 0; a < k; a++)
+        for (int64_t i = 0; i < m; i++)
+            orc_preimage(n, k, delta, a, level_row(s, L, i), cand + ((int64_t)a * m + i) * W);
+    int rc = side_push_level(s, cand, m * k);
+    free(cand);
+    return rc;
+}
+
+static int is_subset(const u64 *X, const u64 *Y, int W) {
+    for (int w = 0; w < W; w++)
+        if (X[w] & ~Y[w]) return 0;
+    return 1;
+}
+
+/* ---------------- Alg. 2: MarkSupersets(A, B, d) ---------------------- */
+
+typedef struct {
+    const Side *A_side; int A_lev;   /* A: forward level, via lex-sorted ids */
+    const Side *B_side; int B_lev;   /* B: inverse level */
+    const int64_t *A;                /* indices into the A level, lex sorted */
+    int64_t *B;                      /* indices into the B level (permuted) */
+    int n, W, minsize;
+    int64_t tests;
+} MarkCtx;
+
+static const u64 *A_row(const MarkCtx *c, int64_t t) { return level_row(c->A_side, c->A_lev, c->A[t]); }
+static const u64 *B_row(const MarkCtx *c, int64_t t) { return level_row(c->B_side, c->B_lev, c->B[t]); }
+
+/* Returns the new end of the active part of B: the sets of B[blo..bhi) that
+ * are supersets of some set of A[alo..ahi) are moved behind it. */
+static int64_t mark_supersets(MarkCtx *c, int64_t alo, int64_t ahi,
+                              int64_t blo, int64_t bhi, int d) {
+    if (alo >= ahi || blo >= bhi) return bhi;
+    if (ahi - alo < c->minsize || d >= c->n) {
+        int64_t b = blo;
+        while (b < bhi) {
+            int hit = 0;
+            for (int64_t a = alo; a < ahi && !hit; a++) {
+                c->tests++;
+                hit = is_subset(A_row(c, a), B_row(c, b), c->W);
+            }
+            if (hit) {
+                int64_t t = c->B[b]; c->B[b] = c->B[bhi - 1]; c->B[bhi - 1] = t;
+                bhi--;
+            } else {
+                b++;
+            }
+        }
+        return bhi;
+    }
+    /* A is lex sorted and all its sets agree on states 0..d-1, so the sets
+     * without state d form a prefix: find its end by binary search. */
+    int64_t lo = alo, hi = ahi;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        if (getbit(A_row(c, mid), d)) hi = mid; else lo = mid + 1;
+    }
+    int64_t split = lo;
+    bhi = mark_supersets(c, alo, split, blo, bhi, d + 1);
+    /* partition the still active part of B: sets containing d go last */
+    int64_t i = blo, j = bhi;
+    while (i < j) {
+        if (getbit(B_row(c, i), d)) {
+            j--;
+            int64_t t = c->B[i]; c->B[i] = c->B[j]; c->B[j] = t;
+        } else {
+            i++;
+        }
+    }
+    return mark_supersets(c, split, ahi, j, bhi, d + 1);
+}
+
+/* lexicographic order of characteristic vectors, state 0 first */
+static const Side *g_lex_side;
+static int g_lex_lev;
+static int g_lex_n;
+static int cmp_lex(const void *pa, const void *pb) {
+    const u64 *x = level_row(g_lex_side, g_lex_lev, *(const int64_t *)pa);
+    const u64 *y = level_row(g_lex_side, g_lex_lev, *(const int64_t *)pb);
+    for (int q = 0; q < g_lex_n; q++) {
+        int bx = getbit(x, q), by = getbit(y, q);
+        if (bx != by) return bx - by;
+    }
+    return 0;
+}
+
+/* least (i, j) with X_i subset of Y_j, or found = 0 */
+static int meet(const Side *F, const Side *B, int n, int mode, int64_t *bi, int64_t *bj,
+                int *found, int64_t *tests) {
+    int W = F->W;
+    int lf = F->nlev - 1, lb = B->nlev - 1;
+    int64_t nx = level_size(F, lf), ny = level_size(B, lb);
+    *found = 0;
+    if (mode == 0) {
+        /* the definition: scan pairs in lexicographic (i, j) order */
+        for (int64_t i = 0; i < nx; i++)
+            for (int64_t j = 0; j < ny; j++) {
+                (*tests)++;
+                if (is_subset(level_row(F, lf, i), level_row(B, lb, j), W)) {
+                    *bi = i; *bj = j; *found = 1;
+                    return ORC_OK;
+                }
+            }
+        return ORC_OK;
+    }
+    /* Alg. 2: mark every Y that is a superset of some X, then the least
+     * pair is found among the marked Y only (every meeting pair's Y is
+     * marked). */
+    int64_t *A = malloc((size_t)(nx ? nx : 1) * sizeof(int64_t));
+    int64_t *Bi = malloc((size_t)(ny ? ny : 1) * sizeof(int64_t));
+    if (!A || !Bi) { free(A); free(Bi); return ORC_ENOMEM; }
+    for (int64_t i = 0; i < nx; i++) A[i] = i;
+    for (int64_t j = 0; j < ny; j++) Bi[j] = j;
+    g_lex_side = F; g_lex_lev = lf; g_lex_n = n;
+    qsort(A, (size_t)nx, sizeof(int64_t), cmp_lex);
+    MarkCtx c = {F, lf, B, lb, A, Bi, n, W, 16, 0};
+    int64_t active = mark_supersets(&c, 0, nx, 0, ny, 0);
+    *tests += c.tests;
+    int64_t nm = ny - active;
+    if (nm > 0) {
+        int64_t *marked = Bi + active;
+        /* ascending j */
+        for (int64_t a = 1; a < nm; a++) {
+            int64_t v = marked[a], b = a - 1;
+            while (b >= 0 && marked[b] > v) { marked[b + 1] = marked[b]; b--; }
+            marked[b + 1] = v;
+        }
+        for (int64_t i = 0; i < nx && !*found; i++)
+            for (int64_t t = 0; t < nm; t++) {
+                (*tests)++;
+                if (is_subset(level_row(F, lf, i), level_row(B, lb, marked[t]), W)) {
+                    *bi = i; *bj = marked[t]; *found = 1;
+                    break;
+                }
+            }
+    }
+    free(A); free(Bi);
+    return ORC_OK;
+}
+
+/* ------------------------------ O-F ------------------------------------ */
+
+typedef struct {
+    int n, k;
+    Side F, B;
+    int64_t pair_tests;     /* subset tests actually made */
+    int64_t pairs;          /* sum of |L_f| * |L_b| over all meet checks */
+    int64_t candidates;     /* sets generated by expansion steps */
+    int steps;
+} OrcRun;
+
+static void trace_forward(const Side *s, int k, int L, int64_t i, uint8_t *out) {
+    for (int d = L; d > 0; d--) {
+        int64_t g = s->par[s->off[d] + i];
+        out[d - 1] = (uint8_t)(g % k);
+        i = g / k;
+    }
+}
+
+static void trace_inverse(const Side *s, int L, int64_t j, uint8_t *out) {
+    for (int d = L, pos = 0; d > 0; d--, pos++) {
+        int64_t g = s->par[s->off[d] + j];
+        int64_t prev = level_size(s, d - 1);
+        out[pos] = (uint8_t)(g / prev);
+        j = g % prev;
+    }
+}
+
+/* Forward BFS from Q; the first singleton generated at the first level that
+ * has one is reached by the lex-least shortest reset word. */
+int orc_forward(int n, int k, const int32_t *delta, int64_t max_sets,
+                int32_t *r, uint8_t *word, int64_t word_cap) {
+    int rc = check_input(n, k, delta);
+    if (rc) return rc;
+    rc = orc_is_synchronizing(n, k, delta);
+    if (rc < 0) return rc;
+    if (rc == 0) return ORC_ENOTSYNC;
+    int W = nwords(n);
+    u64 Q[8];
+    memset(Q, 0, sizeof Q);
+    for (int q = 0; q < n; q++) setbit(Q, q);
+    Side F;
+    rc = side_init(&F, W, Q, 1);
+    if (rc) { side_free(&F); return rc; }
+    int out = ORC_OK;
+    for (;;) {
+        int L = F.nlev - 1;
+        int64_t m = level_size(&F, L);
+        int64_t hit = -1;
+        for (int64_t i = 0; i < m; i++)
+            if (popcount_set(level_row(&F, L, i), W) == 1) { hit = i; break; }
+        if (hit >= 0) {
+            *r = L;
+            if (word) {
+                if (word_cap < L) out = ORC_EWORDCAP;
+                else trace_forward(&F, k, L, hit, word);
+            }
+            break;
+        }
+        if (m == 0) { out = ORC_ENOTSYNC; break; }
+        if (F.nrows + m * k > max_sets) { out = ORC_ELIMIT; break; }
+        rc = step_forward(&F, n, k, delta);
+        if (rc) { out = rc; break; }
+    }
+    side_free(&F);
+    return out;
+}
+
+/* ------------------------------ O-B ------------------------------------ */
+
+/* sides_out[s] = 0 for a forward step, 1 for an inverse step */
+int orc_bidir(int n, int k, const int32_t *delta, int meet_mode,
+              const uint8_t *sched, int sched_len, int max_steps,
+              int32_t *r, uint8_t *word, int64_t word_cap,
+              uint8_t *sides_out, int64_t *stats_out, void **handle_out) {
+    int rc = check_input(n, k, delta);
+    if (rc) return rc;
+    if (handle_out) *handle_out = NULL;
+    rc = orc_is_synchronizing(n, k, delta);
+    if (rc < 0) return rc;
+    if (rc == 0) return ORC_ENOTSYNC;
+    int W = nwords(n);
+    OrcRun *run = calloc(1, sizeof(OrcRun));
+    if (!run) return ORC_ENOMEM;
+    run->n = n; run->k = k;
+    u64 *init = calloc((size_t)n * W, sizeof(u64));
+    if (!init) { free(run); return ORC_ENOMEM; }
+    for (int q = 0; q < n; q++) setbit(init + (int64_t)q * W, q);
+    u64 Q[8];
+    memset(Q, 0, sizeof Q);
+    for (int q = 0; q < n; q++) setbit(Q, q);
+    rc = side_init(&run->F, W, Q, 1);
+    if (!rc) rc = side_init(&run->B, W, init, n);
+    free(init);
+    int out = rc;
+    if (!rc) {
+        int step = 0;
+        for (;;) {
+            int64_t bi = 0, bj = 0;
+            int found = 0;
+            run->pairs += level_size(&run->F, run->F.nlev - 1) * level_size(&run->B, run->B.nlev - 1);
+            rc = meet(&run->F, &run->B, n, meet_mode, &bi, &bj, &found, &run->pair_tests);
+            if (rc) { out = rc; break; }
+            if (found) {
+                int f = run->F.nlev - 1, b = run->B.nlev - 1;
+                *r = f + b;
+                if (word) {
+                    if (word_cap < f + b) out = ORC_EWORDCAP;
+                    else {
+                        trace_forward(&run->F, k, f, bi, word);
+                        trace_inverse(&run->B, b, bj, word + f);
+                    }
+                }
+                break;
+            }
+            if (step >= max_steps) { out = ORC_ELIMIT; break; }
+            int64_t lf = level_size(&run->F, run->F.nlev - 1);
+            int64_t lb = level_size(&run->B, run->B.nlev - 1);
+            int side;
+            if (sched && step < sched_len) side = sched[step] ? 1 : 0;
+            else side = (lb < lf) ? 1 : 0;   /* smaller frontier; tie: forward */
+            if (sides_out) sides_out[step] = (uint8_t)side;
+            run->candidates += (side ? lb : lf) * k;
+            rc = side ? step_inverse(&run->B, n, k, delta) : step_forward(&run->F, n, k, delta);
+            if (rc) { out = rc; break; }
+            step++;
+            int64_t nl = side ? level_size(&run->B, run->B.nlev - 1)
+                              : level_size(&run->F, run->F.nlev - 1);
+            if (nl == 0) { out = ORC_ENOTSYNC; break; }
+        }
+        run->steps = step;
+    }
+    if (stats_out) {
+        stats_out[0] = run->steps;
+        stats_out[1] = run->F.nlev ? run->F.nlev - 1 : 0;
+        stats_out[2] = run->B.nlev ? run->B.nlev - 1 : 0;
+        stats_out[3] = run->F.nrows;
+        stats_out[4] = run->B.nrows;
+        stats_out[5] = run->candidates;
+        stats_out[6] = run->pair_tests;
+        stats_out[7] = run->pairs;
+    }
+    if (handle_out && out == ORC_OK) {
+        *handle_out = run;
+    } else {
+        side_free(&run->F); side_free(&run->B); free(run);
+    }
+    return out;
+}
+
+/* Level data of a finished orc_bidir run (side 0 forward, 1 inverse).
+ * With rows == NULL only the counts are returned: *nlev levels and
+ * *nrows rows in total.  Otherwise off[0..nlev], rows[nrows*W] and
+ * par[nrows] are filled. */
+int orc_levels(void *handle, int side, int32_t *nlev, int64_t *nrows,
+               int64_t *off, u64 *rows, int64_t *par) {
+    OrcRun *run = handle;
+    if (!run) return ORC_EINVAL;
+    const Side *s = side ? &run->B : &run->F;
+    *nlev = s->nlev;
+    *nrows = s->nrows;
+    if (!rows) return ORC_OK;
+    memcpy(off, s->off, sizeof(int64_t) * (s->nlev + 1));
+    memcpy(rows, s->rows, sizeof(u64) * s->nrows * s->W);
+    memcpy(par, s->par, sizeof(int64_t) * s->nrows);
+    return ORC_OK;
+}
+
+void orc_free(void *handle) {
+    OrcRun *run = handle;
+    if (!run) return;
+    side_free(&run->F); side_free(&run->B); free(run);
+}

@@ -1,0 +1,294 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle.
+
+Each test states what fixes the expected value: the paper (closed forms and
+printed formulas), hand-worked examples, the textbook algorithms the paper
+names (trivial word enumeration, exhaustive power-automaton BFS), and
+invariants implied by the definitions.  No expected value here comes from the
+GPU path.
+"""
+
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2207_05495_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def words(n):
+    return (n + 63) // 64
+
+
+def set_of(n, states):
+    s = np.zeros(words(n), dtype=np.uint64)
+    for q in states:
+        s[q >> 6] |= np.uint64(1) << np.uint64(q & 63)
+    return s
+
+
+def members(n, s):
+    return [q for q in range(n) if (int(s[q >> 6]) >> (q & 63)) & 1]
+
+
+def tiny_cases(count, nmax=10, kmax=3, base=777):
+    out = []
+    for i in range(count):
+        n = 1 + i % nmax
+        k = 1 + (i // nmax) % kmax
+        d = I.random_automaton(n, k, I.member_seed(base, i))
+        out.append((n, k, d))
+    return out
+
+
+# ---------------------------------------------------------------- golden
+
+def load_hand_examples():
+    cases = []
+    with open(os.path.join(GOLDEN, "hand_examples.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            p = [x.strip() for x in line.split("|")]
+            n, k = map(int, p[0].split())
+            d = list(map(int, p[1].split()))
+            r = int(p[2])
+            w = list(map(int, p[3].split())) if p[3] else []
+            cases.append((n, k, d, r, w))
+    return cases
+
+
+@pytest.mark.parametrize("case", load_hand_examples())
+def test_hand_examples(case):
+    n, k, d, r, w = case
+    if r == O.ENOTSYNC:
+        assert not O.is_synchronizing(n, k, d)
+        with pytest.raises(O.OracleError) as e:
+            O.bidir(n, k, d)
+        assert e.value.code == O.ENOTSYNC
+        return
+    assert O.bidir(n, k, d)[:2] == (r, w)
+    assert O.bidir(n, k, d, meet=O.MEET_BRUTE)[:2] == (r, w)
+    assert O.forward(n, k, d) == (r, w)
+    assert O.exhaustive(n, k, d) == (r, w)
+    assert O.bruteforce(n, k, d, 12) == (r, w)
+
+
+# ------------------------------------------------------ Cerny closed form
+
+@pytest.mark.parametrize("n", list(range(2, 41)))
+def test_cerny_reset_threshold(n):
+    """C_n meets the bound r = (n-1)^2 (paper Section 1.1 and 3.1.1)."""
+    r, w, info = O.bidir(n, 2, I.cerny(n))
+    assert r == (n - 1) ** 2
+    assert w == I.cerny_word(n)
+    assert O.verify(n, 2, I.cerny(n), w)
+
+
+@pytest.mark.parametrize("n", list(range(2, 15)))
+def test_cerny_exhaustive(n):
+    """Exhaustive 2^n BFS (Section 1.3.1) agrees with the closed form."""
+    assert O.exhaustive(n, 2, I.cerny(n)) == ((n - 1) ** 2, I.cerny_word(n))
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5])
+def test_cerny_word_is_unique(n):
+    """Enumerate all 2^r words of length r = (n-1)^2 with numpy: exactly one
+    resets C_n, and it is (0 1^(n-1))^(n-2) 0.  Fixes the convention."""
+    r = (n - 1) ** 2
+    d = I.cerny(n).reshape(2, n)
+    codes = np.arange(1 << r, dtype=np.int64)
+    cur = np.tile(np.arange(n), (len(codes), 1))
+    for t in range(r):
+        letter = (codes >> (r - 1 - t)) & 1
+        cur = np.where(letter[:, None] == 0, d[0][cur], d[1][cur])
+    resets = np.all(cur == cur[:, :1], axis=1)
+    assert resets.sum() == 1
+    code = int(codes[resets][0])
+    word = [(code >> (r - 1 - t)) & 1 for t in range(r)]
+    assert word == I.cerny_word(n)
+    # and nothing shorter: the (r-1)-prefixes never reset
+    assert not O.verify(n, 2, I.cerny(n), word[:-1])
+
+
+# --------------------------------------------- textbook algorithms agree
+
+@pytest.mark.parametrize("case", tiny_cases(360))
+def test_tiny_all_methods_agree(case):
+    """Trivial enumeration (Section 1.3), exhaustive BFS (Section 1.3.1),
+    forward BFS and the bidirectional search (Alg. 1, both meet tests)."""
+    n, k, d = case
+    if not O.is_synchronizing(n, k, d):
+        with pytest.raises(O.OracleError):
+            O.exhaustive(n, k, d)
+        return
+    expect = O.bruteforce(n, k, d, 40)
+    assert O.exhaustive(n, k, d) == expect
+    assert O.forward(n, k, d) == expect
+    assert O.bidir(n, k, d, meet=O.MEET_BRUTE)[:2] == expect
+    assert O.bidir(n, k, d, meet=O.MEET_MARK)[:2] == expect
+
+
+@pytest.mark.parametrize("n,k", [(12, 2), (14, 3), (16, 2), (16, 4), (20, 2)])
+def test_small_exhaustive_agree(n, k):
+    for i in range(6):
+        d, _ = I.first_synchronizing(n, k, I.member_seed(99, i), O.is_synchronizing)
+        expect = O.exhaustive(n, k, d)
+        assert O.forward(n, k, d) == expect
+        assert O.bidir(n, k, d)[:2] == expect
+        assert O.bidir(n, k, d, meet=O.MEET_BRUTE)[:2] == expect
+
+
+@pytest.mark.parametrize("n,k", [(32, 2), (48, 3), (64, 2), (70, 2), (130, 2)])
+def test_medium_forward_agrees(n, k):
+    """Forward BFS (the definition) against the bidirectional search."""
+    for i in range(3):
+        d, _ = I.first_synchronizing(n, k, I.member_seed(5, i), O.is_synchronizing)
+        b = O.bidir(n, k, d)
+        assert O.bidir(n, k, d, meet=O.MEET_BRUTE)[:2] == b[:2]
+        if n <= 70:
+            assert O.forward(n, k, d, max_sets=3_000_000) == b[:2]
+        assert O.verify(n, k, d, b[1])
+        assert not O.verify(n, k, d, b[1][:-1])
+
+
+# ------------------------------------------------------------ invariants
+
+@pytest.mark.parametrize("seed", range(8))
+def test_schedule_invariance(seed):
+    """Any order of forward / inverse steps gives the same r and word."""
+    rng = np.random.default_rng(seed)
+    n, k = 40, 2 + seed % 2
+    d, _ = I.first_synchronizing(n, k, I.member_seed(31, seed), O.is_synchronizing)
+    base = O.bidir(n, k, d)[:2]
+    for _ in range(5):
+        sched = rng.integers(0, 2, size=64)
+        assert O.bidir(n, k, d, sched=sched)[:2] == base
+    assert O.bidir(n, k, d, sched=[0] * 64)[:2] == base
+    assert O.bidir(n, k, d, sched=[1] * 64)[:2] == base
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_relabel_invariance(seed):
+    """Renaming states (also across 64-bit word boundaries) changes neither
+    r nor the lex-least word."""
+    n, k = 100, 2
+    d, _ = I.first_synchronizing(n, k, I.member_seed(17, seed), O.is_synchronizing)
+    base = O.bidir(n, k, d)[:2]
+    perm = np.random.default_rng(seed).permutation(n)
+    assert O.bidir(n, k, I.relabel(d, n, k, perm))[:2] == base
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_letter_permutation_and_extra_letter(seed):
+    n, k = 30, 3
+    d, _ = I.first_synchronizing(n, k, I.member_seed(23, seed), O.is_synchronizing)
+    r = O.bidir(n, k, d)[0]
+    sigma = [2, 0, 1]
+    assert O.bidir(n, k, I.permute_letters(d, n, k, sigma))[0] == r
+    # adding a letter never increases r
+    extra = I.random_automaton(n, 1, I.member_seed(29, seed))
+    assert O.bidir(n, k + 1, np.concatenate([d, extra]))[0] <= r
+
+
+def test_image_preimage_identities():
+    """Galois connection delta(S,a) <= T iff S <= delta^-1(T,a), complement
+    and union laws, |delta(S,a)| <= |S| (definitions of Section 2)."""
+    rng = np.random.default_rng(3)
+    for n in (5, 63, 64, 65, 130, 200):
+        k = 3
+        d = I.random_automaton(n, k, 4242 + n)
+        full = set(range(n))
+        for _ in range(30):
+            a = int(rng.integers(k))
+            S = set(rng.choice(n, size=int(rng.integers(1, n + 1)), replace=False).tolist())
+            T = set(rng.choice(n, size=int(rng.integers(1, n + 1)), replace=False).tolist())
+            img = set(members(n, O.image(n, k, d, a, set_of(n, S))))
+            pre = set(members(n, O.preimage(n, k, d, a, set_of(n, T))))
+            assert (img <= T) == (S <= pre)
+            pre_c = set(members(n, O.preimage(n, k, d, a, set_of(n, full - T))))
+            assert pre_c == full - pre
+            U = S | T
+            assert set(members(n, O.image(n, k, d, a, set_of(n, U)))) == \
+                img | set(members(n, O.image(n, k, d, a, set_of(n, T))))
+            assert len(img) <= len(S)
+            # membership spelled out from the definitions
+            dd = d.reshape(k, n)
+            assert img == {int(dd[a, q]) for q in S}
+            assert pre == {q for q in range(n) if int(dd[a, q]) in T}
+
+
+def test_sync_check_against_exhaustive():
+    """Synchronizing iff a singleton is reachable from Q in the power
+    automaton (exhaustive BFS)."""
+    seen = [0, 0]
+    for n, k, d in tiny_cases(400, nmax=9, kmax=2, base=4040):
+        s = O.is_synchronizing(n, k, d)
+        try:
+            O.exhaustive(n, k, d)
+            reach = True
+        except O.OracleError as e:
+            assert e.code == O.ENOTSYNC
+            reach = False
+        assert s == reach
+        seen[s] += 1
+    assert seen[0] > 5 and seen[1] > 100
+
+
+def test_permutation_automaton_not_synchronizing():
+    n = 70
+    rot = ((np.arange(n) + 1) % n).astype(np.int32)
+    swap = np.arange(n, dtype=np.int32)
+    swap[[0, 1]] = [1, 0]
+    assert not O.is_synchronizing(n, 2, np.concatenate([rot, swap]))
+
+
+def test_bad_input_rejected():
+    with pytest.raises(O.OracleError) as e:
+        O.bidir(3, 1, [0, 1, 3])
+    assert e.value.code == O.EINVAL
+
+
+# ------------------------------------------------- level structure
+
+def test_level_structure():
+    """Every stored set is the image / preimage of its parent under the
+    letter its key names; keys ascend within a level; no duplicates on a
+    side; no empty set (Alg. 1 lists with duplicates removed)."""
+    n, k = 80, 3
+    d, _ = I.first_synchronizing(n, k, I.member_seed(8, 1), O.is_synchronizing)
+    r, w, info = O.bidir(n, k, d, keep_levels=True)
+    fwd, inv = info["levels"]
+    for side, levels in ((0, fwd), (1, inv)):
+        seen = set()
+        for L, (rows, par) in enumerate(levels):
+            for row in rows:
+                key = tuple(int(x) for x in row)
+                assert key not in seen and any(key)
+                seen.add(key)
+            if L == 0:
+                continue
+            assert np.all(np.diff(par) > 0)
+            prev = levels[L - 1][0]
+            for row, g in zip(rows, par):
+                if side == 0:
+                    i, a = divmod(int(g), k)
+                    assert np.array_equal(O.image(n, k, d, a, prev[i]), row)
+                else:
+                    a, i = divmod(int(g), len(prev))
+                    assert np.array_equal(O.preimage(n, k, d, a, prev[i]), row)
+    assert len(fwd) - 1 + len(inv) - 1 == r
+
+
+def test_mean_reset_threshold_matches_paper_fit():
+    """Section 3.2 fits the mean reset threshold of random binary automata
+    as 2.284 n^0.515 (19.45 at n = 64).  200 seeds: the standard error of
+    the mean is about 0.2, so allow 1.0."""
+    rs = []
+    for i in range(200):
+        d, _ = I.first_synchronizing(64, 2, I.member_seed(12345, i), O.is_synchronizing)
+        rs.append(O.bidir(64, 2, d)[0])
+    assert abs(np.mean(rs) - 2.284 * 64 ** 0.515) < 1.0

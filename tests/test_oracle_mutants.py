@@ -1,0 +1,114 @@
+"""The oracle's pins must catch plausible mistakes.
+
+Each case plants one mistake in a private copy of the oracle source (on the
+CPU, in a temporary directory), compiles it, and runs a quick subset of the
+pins of test_oracle.py against it: the hand-worked examples, the Černý closed
+form, and agreement with the trivial word enumeration.  Every mutant must fail
+at least one of them.
+"""
+
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2207_05495_amd import inputs as I
+
+MUTANTS = {
+    # image indexes delta as if it were state-major
+    "image_wrong_index": [("setbit(X, delta[(int64_t)a * n + q])",
+                           "setbit(X, delta[((int64_t)q * k + a) % ((int64_t)n * k)])")],
+    # preimage tests the source state instead of its target
+    "preimage_no_delta": [("if (getbit(S, delta[(int64_t)a * n + q])) setbit(Y, q);",
+                           "if (getbit(S, q)) setbit(Y, delta[(int64_t)a * n + q]);")],
+    # meet tests Y subset X
+    "meet_swapped": [("hit = is_subset(A_row(c, a), B_row(c, b), c->W);",
+                      "hit = is_subset(B_row(c, b), A_row(c, a), c->W);"),
+                     ("if (is_subset(level_row(F, lf, i), level_row(B, lb, marked[t]), W)) {",
+                      "if (is_subset(level_row(B, lb, marked[t]), level_row(F, lf, i), W)) {")],
+    # duplicates keep the largest key instead of the least
+    "dedup_keeps_last": [("return (a > b) - (a < b);", "return (a < b) - (a > b);")],
+    # inverse candidates generated parent-major (decoded consistently)
+    "inverse_parent_major": [
+        ("orc_preimage(n, k, delta, a, level_row(s, L, i), cand + ((int64_t)a * m + i) * W);",
+         "orc_preimage(n, k, delta, a, level_row(s, L, i), cand + (i * k + a) * W);"),
+        ("out[pos] = (uint8_t)(g / prev);\n        j = g % prev;",
+         "out[pos] = (uint8_t)(g % (g >= 0 ? (int64_t)run_k : 1));\n        j = g / run_k;")],
+    # Alg. 2 split on the wrong side of the binary search
+    "mark_split_wrong": [("if (getbit(A_row(c, mid), d)) hi = mid; else lo = mid + 1;",
+                          "if (!getbit(A_row(c, mid), d)) hi = mid; else lo = mid + 1;")],
+    # inverse half of the word read back to front
+    "trace_inverse_reversed": [("out[pos] = (uint8_t)(g / prev);",
+                                "out[L - 1 - pos] = (uint8_t)(g / prev);")],
+    # sync check never merges through letters
+    "sync_no_letters": [("if (m[(size_t)pp * n + qq]) {", "if (pp == qq) {")],
+}
+
+
+def build_mutant(name, edits, tmpdir):
+    src = open(O.SRC).read()
+    if name == "inverse_parent_major":
+        src = src.replace("static void trace_inverse(const Side *s, int L, int64_t j, uint8_t *out) {",
+                          "static int64_t run_k = 2;\n"
+                          "static void trace_inverse(const Side *s, int L, int64_t j, uint8_t *out) {")
+        src = src.replace("    run->n = n; run->k = k;", "    run->n = n; run->k = k; run_k = k;")
+    for old, new in edits:
+        assert old in src, (name, old)
+        src = src.replace(old, new)
+    path = os.path.join(tmpdir, f"{name}.c")
+    so = os.path.join(tmpdir, f"lib{name}.so")
+    with open(path, "w") as f:
+        f.write(src)
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-w", "-o", so, path])
+    return so
+
+
+def pins_hold():
+    """Quick subset of the pins; False as soon as one fails."""
+    from tests.test_oracle import load_hand_examples
+    try:
+        for n, k, d, r, w in load_hand_examples():
+            if r == O.ENOTSYNC:
+                if O.is_synchronizing(n, k, d):
+                    return False
+                continue
+            if O.bidir(n, k, d)[:2] != (r, w) or O.bidir(n, k, d, meet=0)[:2] != (r, w):
+                return False
+        for n in range(2, 12):
+            got = O.bidir(n, 2, I.cerny(n))[:2]
+            if got != ((n - 1) ** 2, I.cerny_word(n)):
+                return False
+        for i in range(200):
+            n, k = 3 + i % 12, 2 + i % 3
+            d = I.random_automaton(n, k, I.member_seed(31337, i))
+            if not O.is_synchronizing(n, k, d):
+                continue
+            if O.bidir(n, k, d)[:2] != O.bruteforce(n, k, d, 30):
+                return False
+        for i in range(10):
+            d = I.random_automaton(40, 2, I.member_seed(7, i))
+            if not O.is_synchronizing(40, 2, d):
+                continue
+            r, w, _ = O.bidir(40, 2, d)
+            if not O.verify(40, 2, d, w):
+                return False
+    except O.OracleError:
+        return False
+    return True
+
+
+def test_unmutated_oracle_passes():
+    assert pins_hold()
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    so = build_mutant(name, MUTANTS[name], str(tmp_path))
+    saved = O._lib
+    try:
+        O._lib = O.bind(so)
+        assert not pins_hold(), f"planted mistake {name} went unnoticed"
+    finally:
+        O._lib = saved

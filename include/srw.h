@@ -1,0 +1,181 @@
+/*
+ * srw.h -- C ABI of libsrw: exact shortest reset words on one MI355X GPU.
+ *
+ * Paper: M. Szykula, A. Zyzik, "An Improved Algorithm for Finding the
+ * Shortest Synchronizing Words".
+ *
+ * Problem (Section 1 and the input/output of Alg. 1): a complete
+ * deterministic automaton (Q, Sigma, delta) with n states and k letters.  A
+ * word w is a reset word if |delta(Q, w)| = 1; the reset threshold r is the
+ * length of the shortest ones.  The library returns r and, on request, the
+ * lexicographically least reset word of length r (letters ordered by their
+ * index; the paper returns "a" shortest word through predecessor pointers,
+ * end of the Section 2 intro, and this is the one fixed here).
+ *
+ * Method: the bidirectional breadth-first search of Alg. 1 in its plain
+ * variant -- forward steps compute images of the BFS list, inverse steps
+ * compute preimages of the IBFS list, each new list is deduplicated (here
+ * also against all earlier lists of the same side), and after every step the
+ * meet test (some X of the BFS list is a subset of some Y of the IBFS list,
+ * Section 2) decides r.  The side expanded next is the one with the smaller
+ * current list (ties: forward).  The inclusion reductions, the cost-model
+ * step choice and the DFS phase of the paper are not part of this path.
+ *
+ * Conventions shared by every call:
+ *   delta   letter-major int32: delta[a*n + q] = delta(q, a), every entry in
+ *           [0, n).  Caller-owned host memory, read only, copied before the
+ *           call returns.
+ *   word    host buffer of letters 0..k-1 (uint8), written only on SRW_OK.
+ *   n = 1   gives r = 0 and the empty word (the empty word already resets).
+ *   limits  1 <= n <= SRW_MAX_N, 1 <= k <= 255.
+ * Every call returns an int status (SRW_OK or a negative code below) and is
+ * thread-safe; calls on the default context are serialized.  Device memory
+ * and the HIP stream come from srw_set_allocator / srw_set_stream (PyTorch's
+ * caching allocator and current stream in the Python binding) or, when those
+ * are unset, from hipMalloc and a stream of the library's own.
+ */
+#ifndef SRW_H
+#define SRW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SRW_MAX_N 512
+
+#define SRW_OK 0
+#define SRW_EINVAL (-1)        /* null pointer, n or k out of range, delta entry outside [0,n) */
+#define SRW_ENOTSYNC (-2)      /* not synchronizing (pair test, Section 2 intro); *r = -1 */
+#define SRW_EUNSUPPORTED (-3)  /* n > SRW_MAX_N */
+#define SRW_ENOMEM (-4)        /* device memory budget exhausted before the searches met */
+#define SRW_EWORDCAP (-5)      /* *r written, the word did not fit word_cap */
+#define SRW_EDEVICE (-6)       /* HIP error or no usable GPU; srw_last_error() has the text */
+#define SRW_ETIMEOUT (-7)      /* srw_server_poll: nothing completed within the timeout */
+#define SRW_EINTERNAL (-8)     /* internal check failed (e.g. the word did not verify) */
+
+/* Solve one automaton.  r: out, the reset threshold.  word: out, may be NULL
+ * (r only); otherwise room for word_cap letters.  On SRW_EWORDCAP *r is set. */
+int srw_solve(int32_t n, int32_t k, const int32_t *delta,
+              int32_t *r, uint8_t *word, int64_t word_cap);
+
+/* Solve `count` automata together: each global step expands every active
+ * automaton once, with one launch per kernel for all of them.  Automaton i
+ * has n[i] states, k[i] letters and its table at delta + delta_off[i].
+ * Per automaton: r[i] and status[i] (an SRW_ status) are written.  words may
+ * be NULL; otherwise automaton i's word goes to words + word_off[i] with room
+ * for word_cap[i] letters.  Returns SRW_OK when every status was written
+ * (individual failures are in status[]), or a call-level error. */
+int srw_solve_batch(int32_t count, const int32_t *n, const int32_t *k,
+                    const int64_t *delta_off, const int32_t *delta,
+                    int32_t *r, int32_t *status,
+                    const int64_t *word_off, uint8_t *words, const int64_t *word_cap);
+
+/* Synchronizability test by state pairs (Section 2 intro): 1 if every pair
+ * of states can be mapped to one state, 0 if not, <0 on bad input.  Host
+ * code only. */
+int srw_check_sync(int32_t n, int32_t k, const int32_t *delta);
+
+/* 1 if |delta(Q, word)| = 1 (Section 1 definition), 0 if not, <0 on bad input. */
+int srw_verify(int32_t n, int32_t k, const int32_t *delta, const uint8_t *word, int64_t len);
+
+/* ---- serving: continuous batching ------------------------------------ */
+
+typedef struct srw_config {
+    int32_t device;        /* HIP device ordinal */
+    int32_t max_slots;     /* automata resident on the device at once (0: 4096) */
+    int64_t hbm_budget;    /* bytes of device memory the server may hold (0: 80% of free) */
+} srw_config;
+
+typedef struct srw_result {
+    uint64_t tag;          /* the caller's tag from srw_server_submit */
+    int32_t status;        /* SRW_ status of this request */
+    int32_t r;             /* reset threshold, -1 unless status is SRW_OK */
+    const uint8_t *word;   /* r letters, owned by the server until the next poll */
+    double latency_ms;     /* submit -> completion */
+    double queue_ms;       /* submit -> admission to the device */
+} srw_result;
+
+typedef struct srw_server srw_server;
+
+/* Start a server with its own worker thread and stream.  Requests are
+ * admitted while their estimated device footprint fits the budget and a
+ * slot is free; admitted automata keep their lists on the device and step
+ * together with the rest. */
+int srw_server_create(srw_server **out, const srw_config *cfg);
+/* Non-blocking.  Copies delta.  Results come back through srw_server_poll. */
+int srw_server_submit(srw_server *s, int32_t n, int32_t k, const int32_t *delta, uint64_t tag);
+/* Up to max completed results, in completion order.  Waits up to timeout_us
+ * microseconds for the first one (0: no wait).  Returns the number written
+ * (>= 0), SRW_ETIMEOUT if none completed in time, or another error. */
+int srw_server_poll(srw_server *s, srw_result *out, int32_t max, int32_t timeout_us);
+/* Number of requests submitted but not yet returned by srw_server_poll. */
+int64_t srw_server_pending(srw_server *s);
+void srw_server_destroy(srw_server *s);
+
+/* ---- plumbing: device memory and stream -------------------------------- */
+
+/* Device memory comes from alloc(bytes, ctx) / free(ptr, ctx) once set
+ * (NULL, NULL restores hipMalloc / hipFree).  Only for contexts created
+ * after the call. */
+int srw_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
+                      void (*free_fn)(void *ptr, void *ctx), void *ctx);
+/* Launch on this hipStream_t (NULL: the library's own stream). */
+int srw_set_stream(void *hip_stream);
+
+/* Tuning and test options of the default context (srw_solve /
+ * srw_solve_batch).  Keys:
+ *   "budget"      device memory budget in bytes (0: 80% of free memory)
+ *   "max_slots"   automata resident at once in srw_solve_batch
+ *   "profile"     1: time every kernel class with HIP events (srw_get_stats)
+ *   "schedule"    0: smaller frontier first, ties forward (default)
+ *                 1: pseudo-random side per step from "sched_seed"
+ *                 2: alternate forward / inverse
+ *   "sched_seed"  seed of schedule 1
+ *   "meet_tiles"  tiles of 64 inverse sets per meet block (0: auto)
+ *   "keep_levels" 1: keep the device lists of the last srw_solve for
+ *                 srw_last_levels
+ * Unknown keys give SRW_EINVAL. */
+int srw_set_option(const char *key, int64_t value);
+
+typedef struct srw_stats {
+    int64_t solves;            /* automata finished */
+    int64_t steps;             /* expansion steps over all automata */
+    int64_t global_steps;      /* batched steps (one launch of each kernel) */
+    int64_t candidates;        /* subsets expanded: k * |list| per step */
+    int64_t unique;            /* new sets kept after duplicate removal */
+    int64_t pairs;             /* meet pairs |L_f| * |L_b| over all checks */
+    int64_t cand_words;        /* candidates * W (64-bit words) */
+    int64_t pair_words;        /* pairs * W */
+    int64_t launches[8];       /* per kernel class, see below */
+    double ms[8];              /* per kernel class, with "profile" on */
+    int64_t bytes_expand;      /* algorithmic bytes of the expand kernel */
+    int64_t bytes_insert;      /* algorithmic bytes of the insert kernel */
+    int64_t bytes_compact;     /* algorithmic bytes of count+compact */
+    int64_t peak_device_bytes; /* device memory held at peak */
+} srw_stats;
+/* kernel classes: 0 expand, 1 insert, 2 count+scan+compact, 3 transpose,
+ * 4 meet, 5 trace, 6 init/rehash/fill/copies, 7 whole steps (host view) */
+
+int srw_get_stats(srw_stats *out);
+int srw_reset_stats(void);
+
+/* Lists kept by the last srw_solve with "keep_levels" on (side 0 forward,
+ * 1 inverse).  With rows == NULL only *nlev and *nrows are written;
+ * otherwise off[0..nlev] (level L holds rows off[L]..off[L+1]-1),
+ * rows[nrows * W] (W = ceil(n/64) words, state q = bit q%64 of word q/64)
+ * and par[nrows] (the key that produced the row: forward i*k+a, inverse
+ * a*|previous level|+i; 0xFFFFFFFF on level 0). */
+int srw_last_levels(int32_t side, int32_t *nlev, int64_t *nrows,
+                    int64_t *off, uint64_t *rows, uint32_t *par);
+
+/* Text of the last error of the calling thread. */
+const char *srw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SRW_H */

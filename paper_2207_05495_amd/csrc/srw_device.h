@@ -1,0 +1,94 @@
+// srw_device.h -- data shared between the host engine and the HIP kernels.
+//
+// One "segment" is one automaton taking one step of the bidirectional
+// breadth-first search (Alg. 1 of the paper with only duplicate removal).
+// Every kernel of a step is launched once for all segments of the step; a
+// block finds its segment by binary search in a per-kernel block prefix.
+#pragma once
+#include <stdint.h>
+
+namespace srw {
+
+typedef unsigned long long u64;
+typedef uint32_t u32;
+
+constexpr int kMaxW = 8;                 // subsets of up to 512 states
+constexpr u64 kEmpty = ~0ull;            // free hash slot
+constexpr u32 kCandBit = 0x80000000u;    // slot ref names a candidate of this step
+constexpr u32 kDrop = 0xFFFFFFFFu;       // candidate dropped (empty or seen before)
+constexpr int kBS = 256;                 // threads per block (4 wave64)
+constexpr int kCB = 1024;                // candidates per compaction block
+constexpr int kMeetTileWords = 32;       // LDS budget of the meet: tiles*W <= this
+constexpr int64_t kMeetMaxGrid = 65536;  // meet blocks per launch (grid-stride beyond)
+
+// A hash-slot is 64 bits: high 32 = fingerprint of the set, low 32 = ref.
+// ref < 2^31: id of a stored (visited) row of this side;
+// ref >= 2^31: candidate (ref - 2^31) of the current step.
+
+struct StepDesc {
+    // automaton
+    int32_t n, k, W, dir;      // dir 0: forward (images), 1: inverse (preimages)
+    const uint16_t *delta;     // delta[a*n + q], k*n entries
+    // expansion input: the current level of the expanded side
+    const u64 *par_rows;       // m rows of W words
+    int64_t m;                 // parent count
+    int64_t C;                 // candidates = k*m
+    u64 *cand;                 // C rows
+    u32 *cslot;                // C slot positions (or kDrop)
+    // dedup (visited hash set of the expanded side)
+    u64 *tab;
+    u64 tab_mask;              // capacity - 1 (capacity is a power of two)
+    const u64 *vis_rows;       // all stored rows of the side (ids < 2^31)
+    // compaction
+    u64 *out_rows;             // where the new level starts (vis_rows + base*W)
+    u32 *out_par;              // parent key per new row
+    int64_t out_base;          // store id of the first new row
+    int64_t cblk_base;         // first compaction block of this segment
+    int64_t ncblk;             // compaction blocks of this segment
+    // meet (X: forward level, Y: inverse level, transposed in tiles of 64)
+    const u64 *X;
+    int64_t nX;                // -1: the new level (count in res[0])
+    u64 *YT;                   // tiles of 64*W column words
+    int64_t nY;                // -1: the new level (count in res[0])
+    int64_t nXb, nYc;          // meet grid of this segment (upper bounds)
+    int32_t tpb;               // tiles per meet block
+    int32_t pad0;
+    // transpose of a new inverse level into YT
+    int64_t ntr_waves;         // upper bound of (tile, word) waves
+    // results: res[0] = new level size, res[1] = least (i << 32 | j) meeting pair
+    u64 *res;
+};
+
+struct InitDesc {
+    int32_t n, W;
+    u64 *rows_f;               // forward level 0: Q
+    u64 *rows_b;               // inverse level 0: the n singletons
+    u32 *par_f, *par_b;
+};
+
+struct RehashDesc {
+    int32_t W, pad;
+    const u64 *rows;           // rows 0..count-1 to insert
+    int64_t count;
+    u64 *tab;
+    u64 tab_mask;
+};
+
+struct TransposeDesc {
+    int32_t W, pad;
+    const u64 *rows;
+    int64_t count;
+    u64 *YT;
+};
+
+struct TraceDesc {
+    const u32 *par_f;
+    const int64_t *off_f;      // level offsets of the forward side
+    const u32 *par_b;
+    const int64_t *off_b;
+    int64_t i, j;              // meeting pair (ranks in the two levels)
+    int32_t f, b, k, pad;
+    uint8_t *out;              // f + b letters
+};
+
+}  // namespace srw

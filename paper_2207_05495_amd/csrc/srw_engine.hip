@@ -1,0 +1,1396 @@
+// srw_engine.hip -- host side of libsrw: the C ABI, the step orchestration
+// of the bidirectional breadth-first search, device memory and serving.
+//
+// Paper: Szykula & Zyzik, "An Improved Algorithm for Finding the Shortest
+// Synchronizing Words".  The search loop follows Alg. 1 in its plain
+// variant; see include/srw.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/srw.h"
+#include "srw_device.h"
+
+namespace srw {
+
+hipError_t launch_expand(const StepDesc *, const int64_t *, int, int64_t, hipStream_t);
+hipError_t launch_insert(const StepDesc *, const int64_t *, int, int64_t, hipStream_t);
+hipError_t launch_count(const StepDesc *, const int64_t *, int, int64_t, u32 *, hipStream_t);
+hipError_t launch_scan(const StepDesc *, int, const u32 *, u32 *, hipStream_t);
+hipError_t launch_compact(const StepDesc *, const int64_t *, int, int64_t, const u32 *, hipStream_t);
+hipError_t launch_transpose(const StepDesc *, const int64_t *, int, int64_t, hipStream_t);
+hipError_t launch_transpose_rows(const TransposeDesc *, const int64_t *, int, int64_t, hipStream_t);
+hipError_t launch_meet(const StepDesc *, const int64_t *, int, int64_t, hipStream_t);
+hipError_t launch_init(const InitDesc *, const int64_t *, int, int64_t, hipStream_t);
+hipError_t launch_rehash(const RehashDesc *, const int64_t *, int, int64_t, hipStream_t);
+hipError_t launch_fill(u64 *, int64_t, u64, hipStream_t);
+hipError_t launch_trace(const TraceDesc *, int, hipStream_t);
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string t_err;
+
+struct HipFailure {
+    hipError_t e;
+    std::string where;
+};
+
+static int set_error(int code, const std::string &msg) {
+    t_err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) throw HipFailure{e_, std::string(#expr) + " @" +          \
+                                                      std::to_string(__LINE__)};        \
+    } while (0)
+
+static double now_ms() {
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------------------ host checks
+
+static int check_input(int32_t n, int32_t k, const int32_t *delta) {
+    if (!delta) return set_error(SRW_EINVAL, "delta is NULL");
+    if (n < 1 || k < 1 || k > 255) return set_error(SRW_EINVAL, "n or k out of range");
+    if (n > SRW_MAX_N) return set_error(SRW_EUNSUPPORTED, "n exceeds SRW_MAX_N");
+    for (int64_t i = 0; i < (int64_t)n * k; ++i)
+        if (delta[i] < 0 || delta[i] >= n) return set_error(SRW_EINVAL, "delta entry outside [0,n)");
+    return SRW_OK;
+}
+
+// Pair test: every pair {p,q} must be mergeable (Section 2 intro).  Backward
+// search in the pair automaton from the diagonal, O(k n^2).
+static bool is_synchronizing(int n, int k, const int32_t *delta) {
+    if (n == 1) return true;
+    std::vector<int> start((size_t)k * (n + 1), 0), list((size_t)k * n);
+    for (int a = 0; a < k; ++a) {
+        int *st = &start[(size_t)a * (n + 1)];
+        for (int q = 0; q < n; ++q) st[delta[(size_t)a * n + q] + 1]++;
+        for (int t = 0; t < n; ++t) st[t + 1] += st[t];
+        std::vector<int> fillp(st, st + n);
+        for (int q = 0; q < n; ++q) list[(size_t)a * n + fillp[delta[(size_t)a * n + q]]++] = q;
+    }
+    std::vector<uint8_t> merged((size_t)n * n, 0);
+    std::vector<int32_t> queue;
+    queue.reserve((size_t)n * 2);
+    for (int p = 0; p < n; ++p) {
+        merged[(size_t)p * n + p] = 1;
+        queue.push_back(p);
+        queue.push_back(p);
+    }
+    int64_t count = n;
+    for (size_t h = 0; h < queue.size(); h += 2) {
+        const int s = queue[h], t = queue[h + 1];
+        for (int a = 0; a < k; ++a) {
+            const int *st = &start[(size_t)a * (n + 1)];
+            const int *ls = &list[(size_t)a * n];
+            for (int x = st[s]; x < st[s + 1]; ++x)
+                for (int y = st[t]; y < st[t + 1]; ++y) {
+                    const int p = ls[x], q = ls[y];
+                    if (!merged[(size_t)p * n + q]) {
+                        merged[(size_t)p * n + q] = merged[(size_t)q * n + p] = 1;
+                        count += 2;
+                        queue.push_back(p);
+                        queue.push_back(q);
+                    }
+                }
+        }
+    }
+    return count == (int64_t)n * n;
+}
+
+static bool verify_word(int n, int k, const int32_t *delta, const uint8_t *w, int64_t len) {
+    std::vector<uint8_t> cur(n, 1), nxt(n);
+    for (int64_t i = 0; i < len; ++i) {
+        if (w[i] >= k) return false;
+        std::fill(nxt.begin(), nxt.end(), 0);
+        const int32_t *da = delta + (size_t)w[i] * n;
+        for (int q = 0; q < n; ++q)
+            if (cur[q]) nxt[da[q]] = 1;
+        cur.swap(nxt);
+    }
+    int c = 0;
+    for (int q = 0; q < n; ++q) c += cur[q];
+    return c == 1;
+}
+
+// ------------------------------------------------------------- memory pool
+
+struct Backing {
+    void *(*alloc)(size_t, void *) = nullptr;
+    void (*free)(void *, void *) = nullptr;
+    void *ctx = nullptr;
+};
+
+// Power-of-two size classes.  Blocks up to 4 MiB are carved from 64 MiB
+// slabs; larger ones are separate backing allocations.  Freed blocks are
+// cached per class and reused; everything returns to the backing allocator
+// when the pool is destroyed.  `budget` caps the bytes taken from backing.
+class Pool {
+  public:
+    Pool(Backing b, int64_t budget) : b_(b), budget_(budget) {}
+    ~Pool() {
+        for (auto &c : chunks_) backing_free(c.first);
+    }
+    void *alloc(size_t bytes) {
+        const int c = cls_of(bytes);
+        const size_t size = (size_t)256 << c;
+        if (!free_[c].empty()) {
+            void *p = free_[c].back();
+            free_[c].pop_back();
+            account(size);
+            return p;
+        }
+        void *p = nullptr;
+        if (size <= kSmallMax) {
+            if (slab_left_ < size) {
+                char *s = (char *)backing_alloc(kSlab);
+                if (!s) {
+                    trim();
+                    s = (char *)backing_alloc(kSlab);
+                    if (!s) return nullptr;
+                }
+                slab_ = s;
+                slab_left_ = kSlab;
+            }
+            p = slab_;
+            slab_ += size;
+            slab_left_ -= size;
+        } else {
+            p = backing_alloc(size);
+            if (!p) {
+                trim();
+                p = backing_alloc(size);
+                if (!p) return nullptr;
+            }
+            big_.insert({p, size});
+        }
+        cls_[p] = c;
+        account(size);
+        return p;
+    }
+    void free(void *p) {
+        if (!p) return;
+        auto it = cls_.find(p);
+        if (it == cls_.end()) return;
+        free_[it->second].push_back(p);
+        in_use_ -= (int64_t)256 << it->second;
+    }
+    int64_t reserved() const { return reserved_; }
+    int64_t in_use() const { return in_use_; }
+    int64_t peak() const { return peak_; }
+    int64_t budget() const { return budget_; }
+    void set_budget(int64_t b) { budget_ = b; }
+
+  private:
+    static int cls_of(size_t bytes) {
+        int c = 0;
+        size_t s = 256;
+        while (s < bytes) { s <<= 1; ++c; }
+        return c;
+    }
+    void account(size_t size) {
+        in_use_ += (int64_t)size;
+        peak_ = std::max(peak_, in_use_);
+    }
+    void *backing_alloc(size_t bytes) {
+        if (reserved_ + (int64_t)bytes > budget_) return nullptr;
+        void *p = nullptr;
+        if (b_.alloc) {
+            p = b_.alloc(bytes, b_.ctx);
+            if (!p) return nullptr;
+        } else {
+            if (hipMalloc(&p, bytes) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+        }
+        reserved_ += (int64_t)bytes;
+        chunks_.push_back({p, bytes});
+        return p;
+    }
+    void backing_free(void *p) {
+        if (b_.free) b_.free(p, b_.ctx);
+        else (void)hipFree(p);
+    }
+    // hand cached large blocks back to the backing allocator
+    void trim() {
+        for (int c = 0; c < 48; ++c) {
+            const size_t size = (size_t)256 << c;
+            if (size <= kSmallMax) continue;
+            for (void *p : free_[c]) {
+                backing_free(p);
+                reserved_ -= (int64_t)size;
+                cls_.erase(p);
+                big_.erase(p);
+                for (size_t i = 0; i < chunks_.size(); ++i)
+                    if (chunks_[i].first == p) {
+                        chunks_[i] = chunks_.back();
+                        chunks_.pop_back();
+                        break;
+                    }
+            }
+            free_[c].clear();
+        }
+    }
+    static constexpr size_t kSlab = (size_t)64 << 20;
+    static constexpr size_t kSmallMax = (size_t)4 << 20;
+    Backing b_;
+    int64_t budget_, reserved_ = 0, in_use_ = 0, peak_ = 0;
+    std::vector<void *> free_[48];
+    std::unordered_map<void *, int> cls_;
+    std::unordered_map<void *, size_t> big_;
+    std::vector<std::pair<void *, size_t>> chunks_;
+    char *slab_ = nullptr;
+    size_t slab_left_ = 0;
+};
+
+// pinned host buffer that only grows
+struct Pinned {
+    void *p = nullptr;
+    size_t cap = 0;
+    void *need(size_t bytes) {
+        if (bytes > cap) {
+            if (p) (void)hipHostFree(p);
+            p = nullptr;
+            size_t nc = std::max(bytes, cap * 2);
+            nc = std::max(nc, (size_t)1 << 16);
+            HIPCHK(hipHostMalloc(&p, nc, hipHostMallocDefault));
+            cap = nc;
+        }
+        return p;
+    }
+    ~Pinned() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+
+// --------------------------------------------------------------- problem
+
+struct SideState {
+    u64 *rows = nullptr;     // every visited set of the side, level by level
+    u32 *par = nullptr;      // parent key per row
+    int64_t cap = 0;         // rows of capacity
+    u64 *tab = nullptr;      // visited hash set
+    int64_t tab_cap = 0;     // slots (power of two)
+    int64_t nrows = 0;
+    std::vector<int64_t> off;  // level L: rows off[L] .. off[L+1]-1
+    int nlev() const { return (int)off.size() - 1; }
+    int64_t cur() const { return off[off.size() - 1] - off[off.size() - 2]; }
+    int64_t cur_start() const { return off[off.size() - 2]; }
+};
+
+struct Problem {
+    int n = 0, k = 0, W = 0;
+    uint64_t tag = 0;
+    int64_t index = -1;
+    std::vector<int32_t> delta;
+    uint16_t *d_delta = nullptr;
+    SideState s[2];
+    u64 *colT = nullptr;      // current inverse level, tiles of 64*W columns
+    int64_t colT_cap = 0;     // words
+    u64 *cand = nullptr;
+    int64_t cand_cap = 0;     // rows
+    u32 *cslot = nullptr;
+    int64_t cslot_cap = 0;
+    int status = 1;           // 1 running, else SRW_ status
+    int32_t r = -1;
+    std::vector<uint8_t> word;
+    int steps = 0;
+    bool admitted = false;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    int64_t est_bytes = 0;
+};
+
+// --------------------------------------------------------------- options
+
+struct Options {
+    int schedule = 0;
+    uint64_t sched_seed = 1;
+    int meet_tiles = 0;
+    bool profile = false;
+    bool keep_levels = false;
+    int64_t max_slots = 4096;
+};
+
+static uint64_t mix64(uint64_t z) {
+    z ^= z >> 33;
+    z *= 0xff51afd7ed558ccdull;
+    z ^= z >> 33;
+    z *= 0xc4ceb9fe1a85ec53ull;
+    z ^= z >> 33;
+    return z;
+}
+
+// --------------------------------------------------------------- engine
+
+class Engine {
+  public:
+    Engine(int device, Backing backing, int64_t budget, hipStream_t ext_stream)
+        : device_(device), backing_(backing) {
+        HIPCHK(hipSetDevice(device_));
+        if (ext_stream) {
+            stream_ = ext_stream;
+        } else {
+            HIPCHK(hipStreamCreateWithFlags(&own_stream_, hipStreamNonBlocking));
+            stream_ = own_stream_;
+        }
+        if (budget <= 0) {
+            size_t fr = 0, tot = 0;
+            HIPCHK(hipMemGetInfo(&fr, &tot));
+            budget = (int64_t)(fr * 0.8);
+        }
+        pool_.reset(new Pool(backing_, budget));
+        for (int c = 0; c < 16; ++c) HIPCHK(hipEventCreate(&ev_[c]));
+        memset(&stats_, 0, sizeof stats_);
+    }
+    ~Engine() {
+        (void)hipSetDevice(device_);
+        if (stream_) (void)hipStreamSynchronize(stream_);
+        release_kept();
+        pool_.reset();
+        for (int c = 0; c < 16; ++c) (void)hipEventDestroy(ev_[c]);
+        if (own_stream_) (void)hipStreamDestroy(own_stream_);
+    }
+
+    Options opt;
+    srw_stats stats_;
+
+    void set_budget(int64_t b) {
+        if (b <= 0) {
+            size_t fr = 0, tot = 0;
+            HIPCHK(hipMemGetInfo(&fr, &tot));
+            b = pool_->reserved() + (int64_t)(fr * 0.8);
+        }
+        pool_->set_budget(b);
+    }
+    int64_t budget() const { return pool_->budget(); }
+    int64_t in_use() const { return pool_->in_use(); }
+    int device() const { return device_; }
+
+    // Runs every problem of `probs` to completion, at most opt.max_slots at
+    // a time (continuous admission as others finish).
+    void run(std::vector<Problem *> &probs) {
+        HIPCHK(hipSetDevice(device_));
+        std::deque<Problem *> pending(probs.begin(), probs.end());
+        std::vector<Problem *> active;
+        while (!pending.empty() || !active.empty()) {
+            std::vector<Problem *> fresh;
+            while (!pending.empty() && (int64_t)active.size() < opt.max_slots) {
+                Problem *p = pending.front();
+                if (!active.empty() && in_use() + p->est_bytes > budget()) break;
+                pending.pop_front();
+                if (admit(p)) {
+                    active.push_back(p);
+                    fresh.push_back(p);
+                } else if (active.empty()) {
+                    finish_error(p, SRW_ENOMEM);
+                } else {
+                    pending.push_front(p);
+                    break;
+                }
+            }
+            if (!fresh.empty()) init(fresh);
+            if (active.empty()) continue;
+            step(active);
+            std::vector<Problem *> still;
+            for (Problem *p : active)
+                if (p->status == 1) still.push_back(p);
+            active.swap(still);
+        }
+    }
+
+    // --- single steps for the server
+    bool admit(Problem *p) {
+        const int n = p->n, W = p->W;
+        p->t_admit = now_ms();
+        bool ok = true;
+        auto A = [&](size_t bytes) -> void * {
+            void *q = pool_->alloc(bytes);
+            if (!q) ok = false;
+            return q;
+        };
+        p->d_delta = (uint16_t *)A((size_t)p->k * n * sizeof(uint16_t));
+        const int64_t cap0 = std::max<int64_t>(256, n + 1);
+        for (int sd = 0; sd < 2; ++sd) {
+            SideState &s = p->s[sd];
+            s.cap = cap0;
+            s.rows = (u64 *)A((size_t)cap0 * W * 8);
+            s.par = (u32 *)A((size_t)cap0 * 4);
+            s.tab_cap = 1024;
+            while (s.tab_cap < 4 * cap0) s.tab_cap <<= 1;
+            s.tab = (u64 *)A((size_t)s.tab_cap * 8);
+        }
+        p->colT_cap = ceil_div(n, 64) * 64 * W;
+        p->colT = (u64 *)A((size_t)p->colT_cap * 8);
+        if (!ok) {
+            release(p);
+            return false;
+        }
+        p->s[0].off = {0, 1};
+        p->s[0].nrows = 1;
+        p->s[1].off = {0, n};
+        p->s[1].nrows = n;
+        p->admitted = true;
+        return true;
+    }
+
+    void init(std::vector<Problem *> &ps) {
+        const int nseg = (int)ps.size();
+        // deltas as uint16
+        size_t dbytes = 0;
+        for (Problem *p : ps) dbytes += (size_t)p->k * p->n * 2;
+        uint16_t *hd = (uint16_t *)pin_delta_.need(dbytes);
+        size_t o = 0;
+        for (Problem *p : ps) {
+            const size_t cnt = (size_t)p->k * p->n;
+            for (size_t e = 0; e < cnt; ++e) hd[o + e] = (uint16_t)p->delta[e];
+            HIPCHK(hipMemcpyAsync(p->d_delta, hd + o, cnt * 2, hipMemcpyHostToDevice, stream_));
+            o += cnt;
+        }
+        // fill both tables, write level 0, insert it, transpose inverse level 0
+        for (Problem *p : ps)
+            for (int sd = 0; sd < 2; ++sd)
+                HIPCHK(launch_fill(p->s[sd].tab, p->s[sd].tab_cap, kEmpty, stream_));
+        std::vector<InitDesc> idesc(nseg);
+        std::vector<int64_t> ipre(nseg + 1, 0);
+        std::vector<RehashDesc> rdesc;
+        std::vector<int64_t> rpre(1, 0);
+        std::vector<TransposeDesc> tdesc(nseg);
+        std::vector<int64_t> tpre(nseg + 1, 0);
+        for (int i = 0; i < nseg; ++i) {
+            Problem *p = ps[i];
+            idesc[i] = InitDesc{p->n, p->W, p->s[0].rows, p->s[1].rows, p->s[0].par, p->s[1].par};
+            ipre[i + 1] = ipre[i] + ceil_div(p->n + 1, kBS);
+            for (int sd = 0; sd < 2; ++sd) {
+                rdesc.push_back(RehashDesc{p->W, 0, p->s[sd].rows, p->s[sd].nrows, p->s[sd].tab,
+                                           (u64)(p->s[sd].tab_cap - 1)});
+                rpre.push_back(rpre.back() + ceil_div(p->s[sd].nrows, kBS));
+            }
+            tdesc[i] = TransposeDesc{p->W, 0, p->s[1].rows, p->n, p->colT};
+            tpre[i + 1] = tpre[i] + ceil_div(ceil_div(p->n, 64) * p->W, kBS / 64);
+        }
+        prof_begin(6);
+        char *blob = upload3(idesc, ipre, rdesc, rpre, tdesc, tpre);
+        const size_t a1 = sizeof(InitDesc) * idesc.size(), a2 = 8 * ipre.size();
+        const size_t a3 = sizeof(RehashDesc) * rdesc.size(), a4 = 8 * rpre.size();
+        const size_t a5 = sizeof(TransposeDesc) * tdesc.size();
+        char *b = blob;
+        const InitDesc *dI = (const InitDesc *)b; b += align8(a1);
+        const int64_t *dIp = (const int64_t *)b; b += align8(a2);
+        const RehashDesc *dR = (const RehashDesc *)b; b += align8(a3);
+        const int64_t *dRp = (const int64_t *)b; b += align8(a4);
+        const TransposeDesc *dT = (const TransposeDesc *)b; b += align8(a5);
+        const int64_t *dTp = (const int64_t *)b;
+        HIPCHK(launch_init(dI, dIp, nseg, ipre[nseg], stream_));
+        HIPCHK(launch_rehash(dR, dRp, (int)rdesc.size(), rpre.back(), stream_));
+        HIPCHK(launch_transpose_rows(dT, dTp, nseg, tpre[nseg], stream_));
+        prof_end(6);
+        stats_.launches[6] += 3;
+    }
+
+    // One global step: every active problem expands one side.
+    void step(std::vector<Problem *> &act) {
+        HIPCHK(hipSetDevice(device_));
+        const double t0 = now_ms();
+        std::vector<Problem *> segp;
+        std::vector<int> segdir;
+        std::vector<RehashDesc> grow;
+        std::vector<int64_t> growpre(1, 0);
+        std::vector<Problem *> waiting;
+        prof_begin(6);
+        for (Problem *p : act) {
+            if (p->status != 1) continue;
+            const int dir = choose_side(p);
+            const int fail = prepare(p, dir, grow, growpre);
+            if (fail == SRW_ENOMEM) {
+                waiting.push_back(p);   // sits this step out; others may free memory
+                continue;
+            }
+            if (fail) {
+                finish_error(p, fail);
+                continue;
+            }
+            segp.push_back(p);
+            segdir.push_back(dir);
+        }
+        if (segp.empty() && !waiting.empty()) {
+            // nothing can move: give up on the largest one to free memory
+            Problem *big = waiting[0];
+            for (Problem *p : waiting)
+                if (p->s[0].nrows + p->s[1].nrows > big->s[0].nrows + big->s[1].nrows) big = p;
+            finish_error(big, SRW_ENOMEM, "device memory budget exhausted before the searches met");
+        }
+        if (!grow.empty()) {
+            for (auto &g : grow) HIPCHK(launch_fill(g.tab, (int64_t)g.tab_mask + 1, kEmpty, stream_));
+            const RehashDesc *dR = (const RehashDesc *)upload_simple(grow, growpre, rehash_blob_);
+            const int64_t *dRp = (const int64_t *)((char *)dR + align8(sizeof(RehashDesc) * grow.size()));
+            HIPCHK(launch_rehash(dR, dRp, (int)grow.size(), growpre.back(), stream_));
+            stats_.launches[6] += 2;
+        }
+        prof_end(6);
+        const int nseg = (int)segp.size();
+        if (nseg == 0) return;
+
+        // descriptors
+        std::vector<StepDesc> D(nseg);
+        std::vector<int64_t> pe(nseg + 1, 0), pc(nseg + 1, 0), pt(nseg + 1, 0), pm(nseg + 1, 0);
+        if ((int64_t)nseg * 2 > res_cap_) {
+            pool_->free(d_res_);
+            res_cap_ = std::max<int64_t>((int64_t)nseg * 2, 2 * res_cap_);
+            d_res_ = (u64 *)pool_->alloc((size_t)res_cap_ * 8);
+            if (!d_res_) throw HipFailure{hipErrorOutOfMemory, "step result buffer"};
+        }
+        for (int i = 0; i < nseg; ++i) {
+            Problem *p = segp[i];
+            const int dir = segdir[i];
+            SideState &s = p->s[dir];
+            const int W = p->W;
+            StepDesc &d = D[i];
+            memset(&d, 0, sizeof d);
+            d.n = p->n;
+            d.k = p->k;
+            d.W = W;
+            d.dir = dir;
+            d.delta = p->d_delta;
+            d.m = s.cur();
+            d.par_rows = s.rows + s.cur_start() * W;
+            d.C = d.m * p->k;
+            d.cand = p->cand;
+            d.cslot = p->cslot;
+            d.tab = s.tab;
+            d.tab_mask = (u64)(s.tab_cap - 1);
+            d.vis_rows = s.rows;
+            d.out_rows = s.rows + s.nrows * W;
+            d.out_par = s.par + s.nrows;
+            d.out_base = s.nrows;
+            d.ncblk = ceil_div(d.C, kCB);
+            d.cblk_base = pc[i];
+            int64_t nx_ub, ny_ub;
+            if (dir == 0) {
+                d.X = d.out_rows;
+                d.nX = -1;
+                nx_ub = d.C;
+                d.YT = p->colT;
+                d.nY = p->s[1].cur();
+                ny_ub = d.nY;
+            } else {
+                d.X = p->s[0].rows + p->s[0].cur_start() * W;
+                d.nX = p->s[0].cur();
+                nx_ub = d.nX;
+                d.YT = p->colT;
+                d.nY = -1;
+                ny_ub = d.C;
+            }
+            const int tmax = std::max(1, kMeetTileWords / W);   // LDS holds tpb*64*W words
+            d.tpb = opt.meet_tiles > 0 ? std::min(opt.meet_tiles, tmax) : tmax;
+            d.nXb = ceil_div(nx_ub, kBS);
+            d.nYc = ceil_div(ceil_div(ny_ub, 64), d.tpb);
+            d.ntr_waves = dir == 1 ? ceil_div(d.C, 64) * W : 0;
+            d.res = d_res_ + 2 * i;
+            pe[i + 1] = pe[i] + ceil_div(d.C, kBS);
+            pc[i + 1] = pc[i] + d.ncblk;
+            pt[i + 1] = pt[i] + ceil_div(d.ntr_waves, kBS / 64);
+            pm[i + 1] = pm[i] + d.nXb * d.nYc;
+            stats_.candidates += d.C;
+            stats_.cand_words += d.C * W;
+            stats_.bytes_expand += 8 * W * (d.m + d.C);
+            stats_.bytes_insert += d.C * (8 * W + 8 + 4);
+        }
+        // compaction block counters
+        const int64_t ncb = pc[nseg];
+        if (ncb > cblk_cap_) {
+            pool_->free(d_cnt_);
+            pool_->free(d_off_);
+            cblk_cap_ = std::max(ncb, 2 * cblk_cap_);
+            d_cnt_ = (u32 *)pool_->alloc((size_t)cblk_cap_ * 4);
+            d_off_ = (u32 *)pool_->alloc((size_t)cblk_cap_ * 4);
+            if (!d_cnt_ || !d_off_) throw HipFailure{hipErrorOutOfMemory, "compaction counters"};
+        }
+        // upload descriptors + the four block prefixes in one copy
+        const size_t szD = align8(sizeof(StepDesc) * nseg), szP = align8(8 * (nseg + 1));
+        const size_t total = szD + 4 * szP;
+        char *h = (char *)pin_step_.need(total);
+        memcpy(h, D.data(), sizeof(StepDesc) * nseg);
+        memcpy(h + szD, pe.data(), 8 * (nseg + 1));
+        memcpy(h + szD + szP, pc.data(), 8 * (nseg + 1));
+        memcpy(h + szD + 2 * szP, pt.data(), 8 * (nseg + 1));
+        memcpy(h + szD + 3 * szP, pm.data(), 8 * (nseg + 1));
+        char *dblob = dev_need(step_blob_, step_blob_cap_, total);
+        HIPCHK(hipMemcpyAsync(dblob, h, total, hipMemcpyHostToDevice, stream_));
+        const StepDesc *dD = (const StepDesc *)dblob;
+        const int64_t *dpe = (const int64_t *)(dblob + szD);
+        const int64_t *dpc = (const int64_t *)(dblob + szD + szP);
+        const int64_t *dpt = (const int64_t *)(dblob + szD + 2 * szP);
+        const int64_t *dpm = (const int64_t *)(dblob + szD + 3 * szP);
+
+        prof_begin(0);
+        HIPCHK(launch_expand(dD, dpe, nseg, pe[nseg], stream_));
+        prof_end(0);
+        prof_begin(1);
+        HIPCHK(launch_insert(dD, dpe, nseg, pe[nseg], stream_));
+        prof_end(1);
+        prof_begin(2);
+        HIPCHK(launch_count(dD, dpc, nseg, pc[nseg], d_cnt_, stream_));
+        HIPCHK(launch_scan(dD, nseg, d_cnt_, d_off_, stream_));
+        HIPCHK(launch_compact(dD, dpc, nseg, pc[nseg], d_off_, stream_));
+        prof_end(2);
+        if (pt[nseg] > 0) {
+            prof_begin(3);
+            HIPCHK(launch_transpose(dD, dpt, nseg, pt[nseg], stream_));
+            prof_end(3);
+            stats_.launches[3]++;
+        }
+        prof_begin(4);
+        HIPCHK(launch_meet(dD, dpm, nseg, pm[nseg], stream_));
+        prof_end(4);
+        stats_.launches[0]++;
+        stats_.launches[1]++;
+        stats_.launches[2]++;
+        stats_.launches[4]++;
+        u64 *hres = (u64 *)pin_res_.need((size_t)nseg * 16);
+        HIPCHK(hipMemcpyAsync(hres, d_res_, (size_t)nseg * 16, hipMemcpyDeviceToHost, stream_));
+        HIPCHK(hipStreamSynchronize(stream_));
+        prof_collect();
+        stats_.global_steps++;
+
+        std::vector<Problem *> met;
+        std::vector<u64> metbest;
+        for (int i = 0; i < nseg; ++i) {
+            Problem *p = segp[i];
+            const int dir = segdir[i];
+            SideState &s = p->s[dir];
+            const int64_t U = (int64_t)hres[2 * i];
+            const u64 best = hres[2 * i + 1];
+            const StepDesc &d = D[i];
+            s.nrows += U;
+            s.off.push_back(s.nrows);
+            p->steps++;
+            stats_.steps++;
+            stats_.unique += U;
+            stats_.bytes_compact += d.C * 24 + U * (16 * p->W + 12);
+            const int64_t nx = dir == 0 ? U : d.nX;
+            const int64_t ny = dir == 0 ? d.nY : U;
+            stats_.pairs += nx * ny;
+            stats_.pair_words += nx * ny * p->W;
+            if (best != kEmpty) {
+                met.push_back(p);
+                metbest.push_back(best);
+            } else if (U == 0) {
+                finish_error(p, SRW_EINTERNAL, "a list became empty before the searches met");
+            }
+        }
+        if (!met.empty()) trace(met, metbest);
+        stats_.ms[7] += now_ms() - t0;
+    }
+
+    void finish_error(Problem *p, int code, const char *msg = nullptr) {
+        p->status = code;
+        p->r = -1;
+        p->t_done = now_ms();
+        if (msg) t_err = msg;
+        release(p);
+    }
+
+    // lists of the last kept problem
+    Problem *kept() { return kept_; }
+    void release_kept() {
+        if (kept_) {
+            release(kept_, true);
+            delete kept_;
+            kept_ = nullptr;
+        }
+    }
+    void keep(Problem *p) {
+        release_kept();
+        kept_ = p;
+    }
+    hipStream_t stream() const { return stream_; }
+
+  private:
+    static size_t align8(size_t x) { return (x + 7) & ~(size_t)7; }
+
+    int choose_side(Problem *p) {
+        const int64_t lf = p->s[0].cur(), lb = p->s[1].cur();
+        switch (opt.schedule) {
+            case 1: return (int)(mix64(opt.sched_seed * 0x9E3779B97F4A7C15ull + (uint64_t)p->steps +
+                                       ((uint64_t)p->index << 32)) & 1);
+            case 2: return p->steps & 1;
+            default: return lb < lf ? 1 : 0;   // smaller list first, ties forward
+        }
+    }
+
+    bool dev_grow(void *&ptr, int64_t &cap, int64_t need, size_t elem, int64_t keep) {
+        if (need <= cap) return true;
+        const int64_t nc = std::max(need, cap * 2);
+        void *q = pool_->alloc((size_t)nc * elem);
+        if (!q) return false;
+        if (ptr && keep > 0) HIPCHK(hipMemcpyAsync(q, ptr, (size_t)keep * elem, hipMemcpyDeviceToDevice, stream_));
+        pool_->free(ptr);
+        ptr = q;
+        cap = nc;
+        return true;
+    }
+
+    // make room for one step of side `dir`; returns 0 or an SRW_ error
+    int prepare(Problem *p, int dir, std::vector<RehashDesc> &grow, std::vector<int64_t> &growpre) {
+        SideState &s = p->s[dir];
+        const int W = p->W;
+        const int64_t C = s.cur() * p->k;
+        if (C >= (int64_t)kCandBit - 1 || s.nrows + C >= (int64_t)kCandBit - 1)
+            return set_error(SRW_ENOMEM, "list size beyond 2^31");
+        void *pp;
+        int64_t cap;
+        pp = p->cand; cap = p->cand_cap;
+        if (!dev_grow(pp, cap, C, (size_t)W * 8, 0)) return set_error(SRW_ENOMEM, "device budget (candidates)");
+        p->cand = (u64 *)pp; p->cand_cap = cap;
+        pp = p->cslot; cap = p->cslot_cap;
+        if (!dev_grow(pp, cap, C, 4, 0)) return set_error(SRW_ENOMEM, "device budget (slots)");
+        p->cslot = (u32 *)pp; p->cslot_cap = cap;
+        if (s.nrows + C > s.cap) {
+            int64_t c1 = s.cap, c2 = s.cap;
+            pp = s.rows;
+            if (!dev_grow(pp, c1, s.nrows + C, (size_t)W * 8, s.nrows)) return set_error(SRW_ENOMEM, "device budget (rows)");
+            s.rows = (u64 *)pp;
+            pp = s.par;
+            if (!dev_grow(pp, c2, s.nrows + C, 4, s.nrows)) return set_error(SRW_ENOMEM, "device budget (parents)");
+            s.par = (u32 *)pp;
+            s.cap = c1;
+        }
+        if (2 * (s.nrows + C) > s.tab_cap) {
+            int64_t nc = s.tab_cap;
+            while (2 * (s.nrows + C) > nc) nc <<= 1;
+            nc = std::max(nc, 2 * s.tab_cap);
+            if (nc > ((int64_t)1 << 31)) return set_error(SRW_ENOMEM, "hash table beyond 2^31 slots");
+            void *t = pool_->alloc((size_t)nc * 8);
+            if (!t) return set_error(SRW_ENOMEM, "device budget (hash table)");
+            pool_->free(s.tab);
+            s.tab = (u64 *)t;
+            s.tab_cap = nc;
+            grow.push_back(RehashDesc{W, 0, s.rows, s.nrows, s.tab, (u64)(nc - 1)});
+            growpre.push_back(growpre.back() + ceil_div(s.nrows, kBS));
+        }
+        if (dir == 1) {
+            pp = p->colT; cap = p->colT_cap;
+            if (!dev_grow(pp, cap, ceil_div(C, 64) * 64 * W, 8, 0)) return set_error(SRW_ENOMEM, "device budget (tiles)");
+            p->colT = (u64 *)pp; p->colT_cap = cap;
+        }
+        return 0;
+    }
+
+    void trace(std::vector<Problem *> &met, std::vector<u64> &best) {
+        const int cnt = (int)met.size();
+        size_t offs = 0, words = 0;
+        for (Problem *p : met) {
+            offs += p->s[0].off.size() + p->s[1].off.size();
+            words += p->s[0].nlev() - 1 + p->s[1].nlev() - 1;
+        }
+        const size_t szT = align8(sizeof(TraceDesc) * cnt), szO = align8(8 * offs);
+        const size_t total = szT + szO + align8(words);
+        char *h = (char *)pin_trace_.need(total);
+        char *dblob = dev_need(trace_blob_, trace_blob_cap_, total);
+        TraceDesc *T = (TraceDesc *)h;
+        int64_t *O = (int64_t *)(h + szT);
+        size_t oo = 0, wo = 0;
+        for (int t = 0; t < cnt; ++t) {
+            Problem *p = met[t];
+            const int f = p->s[0].nlev() - 1, b = p->s[1].nlev() - 1;
+            TraceDesc &d = T[t];
+            d.par_f = p->s[0].par;
+            d.off_f = (const int64_t *)(dblob + szT) + oo;
+            memcpy(O + oo, p->s[0].off.data(), 8 * p->s[0].off.size());
+            oo += p->s[0].off.size();
+            d.par_b = p->s[1].par;
+            d.off_b = (const int64_t *)(dblob + szT) + oo;
+            memcpy(O + oo, p->s[1].off.data(), 8 * p->s[1].off.size());
+            oo += p->s[1].off.size();
+            d.i = (int64_t)(best[t] >> 32);
+            d.j = (int64_t)(best[t] & 0xFFFFFFFFull);
+            d.f = f;
+            d.b = b;
+            d.k = p->k;
+            d.out = (uint8_t *)(dblob + szT + szO + wo);
+            p->r = f + b;
+            wo += (size_t)(f + b);
+        }
+        prof_begin(5);
+        HIPCHK(hipMemcpyAsync(dblob, h, szT + szO, hipMemcpyHostToDevice, stream_));
+        HIPCHK(launch_trace((const TraceDesc *)dblob, cnt, stream_));
+        if (words) HIPCHK(hipMemcpyAsync(h + szT + szO, dblob + szT + szO, words, hipMemcpyDeviceToHost, stream_));
+        prof_end(5);
+        stats_.launches[5]++;
+        HIPCHK(hipStreamSynchronize(stream_));
+        prof_collect();
+        wo = 0;
+        for (int t = 0; t < cnt; ++t) {
+            Problem *p = met[t];
+            p->word.assign((uint8_t *)h + szT + szO + wo, (uint8_t *)h + szT + szO + wo + p->r);
+            wo += p->r;
+            p->t_done = now_ms();
+            if (!verify_word(p->n, p->k, p->delta.data(), p->word.data(), p->r)) {
+                p->status = SRW_EINTERNAL;
+                t_err = "returned word does not reset the automaton";
+            } else {
+                p->status = SRW_OK;
+            }
+            stats_.solves++;
+            if (!opt.keep_levels) release(p);
+        }
+    }
+
+  public:
+    void release(Problem *p, bool force = false) {
+        (void)force;
+        pool_->free(p->d_delta); p->d_delta = nullptr;
+        for (int sd = 0; sd < 2; ++sd) {
+            pool_->free(p->s[sd].rows); p->s[sd].rows = nullptr;
+            pool_->free(p->s[sd].par); p->s[sd].par = nullptr;
+            pool_->free(p->s[sd].tab); p->s[sd].tab = nullptr;
+            p->s[sd].cap = p->s[sd].tab_cap = 0;
+        }
+        pool_->free(p->colT); p->colT = nullptr; p->colT_cap = 0;
+        pool_->free(p->cand); p->cand = nullptr; p->cand_cap = 0;
+        pool_->free(p->cslot); p->cslot = nullptr; p->cslot_cap = 0;
+        stats_.peak_device_bytes = std::max<int64_t>(stats_.peak_device_bytes, pool_->peak());
+    }
+
+  private:
+    char *dev_need(void *&p, int64_t &cap, size_t bytes) {
+        if ((int64_t)bytes > cap) {
+            pool_->free(p);
+            cap = std::max<int64_t>((int64_t)bytes, 2 * cap);
+            p = pool_->alloc((size_t)cap);
+            if (!p) throw HipFailure{hipErrorOutOfMemory, "descriptor blob"};
+        }
+        return (char *)p;
+    }
+
+    template <class T>
+    void *upload_simple(const std::vector<T> &v, const std::vector<int64_t> &pre, void *&blob) {
+        const size_t a = align8(sizeof(T) * v.size()), b = align8(8 * pre.size());
+        char *h = (char *)pin_misc_.need(a + b);
+        memcpy(h, v.data(), sizeof(T) * v.size());
+        memcpy(h + a, pre.data(), 8 * pre.size());
+        char *d = dev_need(blob, misc_blob_cap_, a + b);
+        HIPCHK(hipMemcpyAsync(d, h, a + b, hipMemcpyHostToDevice, stream_));
+        // the pinned staging buffer is reused by the next upload: wait
+        HIPCHK(hipStreamSynchronize(stream_));
+        return d;
+    }
+
+    char *upload3(const std::vector<InitDesc> &a, const std::vector<int64_t> &ap,
+                  const std::vector<RehashDesc> &b, const std::vector<int64_t> &bp,
+                  const std::vector<TransposeDesc> &c, const std::vector<int64_t> &cp) {
+        const size_t s1 = align8(sizeof(InitDesc) * a.size()), s2 = align8(8 * ap.size());
+        const size_t s3 = align8(sizeof(RehashDesc) * b.size()), s4 = align8(8 * bp.size());
+        const size_t s5 = align8(sizeof(TransposeDesc) * c.size()), s6 = align8(8 * cp.size());
+        const size_t total = s1 + s2 + s3 + s4 + s5 + s6;
+        char *h = (char *)pin_init_.need(total);
+        char *q = h;
+        memcpy(q, a.data(), sizeof(InitDesc) * a.size()); q += s1;
+        memcpy(q, ap.data(), 8 * ap.size()); q += s2;
+        memcpy(q, b.data(), sizeof(RehashDesc) * b.size()); q += s3;
+        memcpy(q, bp.data(), 8 * bp.size()); q += s4;
+        memcpy(q, c.data(), sizeof(TransposeDesc) * c.size()); q += s5;
+        memcpy(q, cp.data(), 8 * cp.size());
+        char *d = dev_need(init_blob_, init_blob_cap_, total);
+        HIPCHK(hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, stream_));
+        HIPCHK(hipStreamSynchronize(stream_));   // staging reused by the next init
+        return d;
+    }
+
+    void prof_begin(int c) {
+        if (opt.profile) {
+            HIPCHK(hipEventRecord(ev_[2 * c], stream_));
+            prof_used_[c] = true;
+        }
+    }
+    void prof_end(int c) {
+        if (opt.profile) HIPCHK(hipEventRecord(ev_[2 * c + 1], stream_));
+    }
+    void prof_collect() {
+        if (!opt.profile) return;
+        for (int c = 0; c < 7; ++c) {
+            if (!prof_used_[c]) continue;
+            float ms = 0;
+            HIPCHK(hipEventSynchronize(ev_[2 * c + 1]));
+            HIPCHK(hipEventElapsedTime(&ms, ev_[2 * c], ev_[2 * c + 1]));
+            stats_.ms[c] += ms;
+            prof_used_[c] = false;
+        }
+    }
+
+    int device_;
+    Backing backing_;
+    hipStream_t stream_ = nullptr, own_stream_ = nullptr;
+    std::unique_ptr<Pool> pool_;
+    hipEvent_t ev_[16];
+    bool prof_used_[8] = {};
+    Pinned pin_delta_, pin_step_, pin_res_, pin_trace_, pin_init_, pin_misc_;
+    void *step_blob_ = nullptr, *trace_blob_ = nullptr, *init_blob_ = nullptr, *rehash_blob_ = nullptr;
+    int64_t step_blob_cap_ = 0, trace_blob_cap_ = 0, init_blob_cap_ = 0, misc_blob_cap_ = 0;
+    u64 *d_res_ = nullptr;
+    int64_t res_cap_ = 0;
+    u32 *d_cnt_ = nullptr, *d_off_ = nullptr;
+    int64_t cblk_cap_ = 0;
+    Problem *kept_ = nullptr;
+};
+
+// Rough device footprint of a solve, used for admission only (growth is
+// checked against the budget anyway).  Visited sets of random automata grow
+// about exponentially in n: log10(sets) ~ 2.7 + n/80 (k = 2), 3.2 + n/56
+// (k = 3), 3.0 + n/42 (k >= 4), fitted on sizes measured with the oracle.
+static int64_t estimate_bytes(int n, int k) {
+    const int W = (n + 63) / 64;
+    double e;
+    if (k <= 2) e = 2.7 + n / 80.0;
+    else if (k == 3) e = 3.2 + n / 56.0;
+    else e = 3.0 + n / 42.0;
+    const double sets = std::pow(10.0, std::min(e, 10.0));
+    const double bytes = sets * (8.0 * W * 1.5 + 4 + 16) + 4.0 * 64 * (1 << 20) / 64;
+    return (int64_t)std::min(bytes, 4e11);
+}
+
+static Problem *make_problem(int32_t n, int32_t k, const int32_t *delta) {
+    Problem *p = new Problem();
+    p->n = n;
+    p->k = k;
+    p->W = (n + 63) / 64;
+    p->delta.assign(delta, delta + (size_t)n * k);
+    p->t_submit = now_ms();
+    p->est_bytes = estimate_bytes(n, k);
+    return p;
+}
+
+// ------------------------------------------------------- default context
+
+struct Context {
+    std::mutex mu;
+    Backing backing;
+    hipStream_t stream = nullptr;
+    std::unique_ptr<Engine> eng;
+    Options opt;
+    int64_t budget = 0;
+};
+
+// never destroyed: a destructor running after the HIP runtime (or the
+// caller's allocator) has shut down at process exit would crash
+static Context &ctx() {
+    static Context *c = new Context();
+    return *c;
+}
+
+static Engine *engine_locked(Context &c) {
+    if (!c.eng) {
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
+            (void)hipGetLastError();
+            throw HipFailure{hipErrorNoDevice, "no HIP device"};
+        }
+        c.eng.reset(new Engine(0, c.backing, c.budget, c.stream));
+        c.eng->opt = c.opt;
+    }
+    return c.eng.get();
+}
+
+static int device_error(const HipFailure &f) {
+    return set_error(SRW_EDEVICE, std::string("HIP error ") + hipGetErrorString(f.e) + " in " + f.where);
+}
+
+}  // namespace srw
+
+using namespace srw;
+
+// ================================================================ C ABI
+
+extern "C" {
+
+const char *srw_last_error(void) { return t_err.c_str(); }
+
+int srw_check_sync(int32_t n, int32_t k, const int32_t *delta) {
+    const int rc = check_input(n, k, delta);
+    if (rc) return rc;
+    return is_synchronizing(n, k, delta) ? 1 : 0;
+}
+
+int srw_verify(int32_t n, int32_t k, const int32_t *delta, const uint8_t *word, int64_t len) {
+    const int rc = check_input(n, k, delta);
+    if (rc) return rc;
+    if (len < 0 || (len > 0 && !word)) return set_error(SRW_EINVAL, "bad word");
+    return verify_word(n, k, delta, word, len) ? 1 : 0;
+}
+
+int srw_set_allocator(void *(*alloc)(size_t, void *), void (*free_fn)(void *, void *), void *c) {
+    if ((alloc == nullptr) != (free_fn == nullptr)) return set_error(SRW_EINVAL, "set both or neither");
+    Context &x = ctx();
+    std::lock_guard<std::mutex> g(x.mu);
+    x.backing = Backing{alloc, free_fn, c};
+    x.eng.reset();
+    return SRW_OK;
+}
+
+int srw_set_stream(void *s) {
+    Context &x = ctx();
+    std::lock_guard<std::mutex> g(x.mu);
+    if (x.stream != (hipStream_t)s) {
+        x.stream = (hipStream_t)s;
+        x.eng.reset();
+    }
+    return SRW_OK;
+}
+
+int srw_set_option(const char *key, int64_t v) {
+    if (!key) return set_error(SRW_EINVAL, "key is NULL");
+    Context &x = ctx();
+    std::lock_guard<std::mutex> g(x.mu);
+    std::string k(key);
+    if (k == "budget") {
+        x.budget = v;
+        if (x.eng) {
+            try {
+                x.eng->set_budget(v);
+            } catch (const HipFailure &f) {
+                return device_error(f);
+            }
+        }
+        return SRW_OK;
+    }
+    if (k == "max_slots") { if (v < 1) return set_error(SRW_EINVAL, "max_slots < 1"); x.opt.max_slots = v; }
+    else if (k == "profile") x.opt.profile = v != 0;
+    else if (k == "schedule") { if (v < 0 || v > 2) return set_error(SRW_EINVAL, "schedule"); x.opt.schedule = (int)v; }
+    else if (k == "sched_seed") x.opt.sched_seed = (uint64_t)v;
+    else if (k == "meet_tiles") { if (v < 0 || v > kMeetTileWords) return set_error(SRW_EINVAL, "meet_tiles"); x.opt.meet_tiles = (int)v; }
+    else if (k == "keep_levels") x.opt.keep_levels = v != 0;
+    else return set_error(SRW_EINVAL, "unknown option " + k);
+    if (x.eng) x.eng->opt = x.opt;
+    return SRW_OK;
+}
+
+int srw_get_stats(srw_stats *out) {
+    if (!out) return set_error(SRW_EINVAL, "out is NULL");
+    Context &x = ctx();
+    std::lock_guard<std::mutex> g(x.mu);
+    if (x.eng) *out = x.eng->stats_;
+    else memset(out, 0, sizeof *out);
+    return SRW_OK;
+}
+
+int srw_reset_stats(void) {
+    Context &x = ctx();
+    std::lock_guard<std::mutex> g(x.mu);
+    if (x.eng) memset(&x.eng->stats_, 0, sizeof x.eng->stats_);
+    return SRW_OK;
+}
+
+int srw_solve_batch(int32_t count, const int32_t *n, const int32_t *k, const int64_t *delta_off,
+                    const int32_t *delta, int32_t *r, int32_t *status, const int64_t *word_off,
+                    uint8_t *words, const int64_t *word_cap) {
+    if (count < 0 || (count > 0 && (!n || !k || !delta_off || !delta || !r || !status)))
+        return set_error(SRW_EINVAL, "null argument");
+    if (words && (!word_off || !word_cap)) return set_error(SRW_EINVAL, "words without offsets");
+    Context &x = ctx();
+    std::lock_guard<std::mutex> g(x.mu);
+    std::vector<std::unique_ptr<Problem>> own;
+    std::vector<Problem *> work;
+    for (int32_t i = 0; i < count; ++i) {
+        r[i] = -1;
+        const int32_t *d = delta + delta_off[i];
+        int rc = check_input(n[i], k[i], d);
+        if (rc) { status[i] = rc; continue; }
+        if (!is_synchronizing(n[i], k[i], d)) { status[i] = SRW_ENOTSYNC; continue; }
+        if (n[i] == 1) { status[i] = SRW_OK; r[i] = 0; continue; }
+        Problem *p = make_problem(n[i], k[i], d);
+        p->index = i;
+        own.emplace_back(p);
+        work.push_back(p);
+    }
+    if (!work.empty()) {
+        try {
+            Engine *e = engine_locked(x);
+            e->release_kept();
+            const bool keep = e->opt.keep_levels;
+            e->opt.keep_levels = false;
+            e->run(work);
+            e->opt.keep_levels = keep;
+        } catch (const HipFailure &f) {
+            for (Problem *p : work) status[p->index] = SRW_EDEVICE;
+            x.eng.reset();
+            return device_error(f);
+        }
+    }
+    for (Problem *p : work) {
+        const int i = (int)p->index;
+        status[i] = p->status;
+        r[i] = p->status == SRW_OK ? p->r : -1;
+        if (p->status == SRW_OK && words) {
+            if (word_cap[i] < p->r) status[i] = SRW_EWORDCAP;
+            else memcpy(words + word_off[i], p->word.data(), p->r);
+        }
+    }
+    return SRW_OK;
+}
+
+int srw_solve(int32_t n, int32_t k, const int32_t *delta, int32_t *r, uint8_t *word, int64_t word_cap) {
+    if (!r) return set_error(SRW_EINVAL, "r is NULL");
+    *r = -1;
+    int rc = check_input(n, k, delta);
+    if (rc) return rc;
+    if (!is_synchronizing(n, k, delta)) return set_error(SRW_ENOTSYNC, "automaton is not synchronizing");
+    if (n == 1) { *r = 0; return SRW_OK; }
+    Context &x = ctx();
+    std::lock_guard<std::mutex> g(x.mu);
+    Problem *p = make_problem(n, k, delta);
+    p->index = 0;
+    std::vector<Problem *> work{p};
+    try {
+        Engine *e = engine_locked(x);
+        e->release_kept();
+        e->run(work);
+        if (e->opt.keep_levels) e->keep(p);
+    } catch (const HipFailure &f) {
+        x.eng.reset();
+        delete p;
+        return device_error(f);
+    }
+    rc = p->status;
+    if (rc == SRW_OK) {
+        *r = p->r;
+        if (word) {
+            if (word_cap < p->r) rc = set_error(SRW_EWORDCAP, "word_cap too small");
+            else memcpy(word, p->word.data(), p->r);
+        }
+    } else if (rc < 0 && t_err.empty()) {
+        set_error(rc, "solve failed");
+    }
+    if (!x.eng || x.eng->kept() != p) delete p;
+    return rc;
+}
+
+int srw_last_levels(int32_t side, int32_t *nlev, int64_t *nrows, int64_t *off, uint64_t *rows, uint32_t *par) {
+    if (side < 0 || side > 1 || !nlev || !nrows) return set_error(SRW_EINVAL, "bad arguments");
+    Context &x = ctx();
+    std::lock_guard<std::mutex> g(x.mu);
+    if (!x.eng || !x.eng->kept()) return set_error(SRW_EINVAL, "no kept solve (set keep_levels)");
+    Problem *p = x.eng->kept();
+    const SideState &s = p->s[side];
+    *nlev = s.nlev();
+    *nrows = s.nrows;
+    if (!rows) return SRW_OK;
+    if (!off || !par) return set_error(SRW_EINVAL, "off/par NULL");
+    try {
+        HIPCHK(hipSetDevice(x.eng->device()));
+        memcpy(off, s.off.data(), 8 * s.off.size());
+        HIPCHK(hipMemcpyAsync(rows, s.rows, (size_t)s.nrows * p->W * 8, hipMemcpyDeviceToHost, x.eng->stream()));
+        HIPCHK(hipMemcpyAsync(par, s.par, (size_t)s.nrows * 4, hipMemcpyDeviceToHost, x.eng->stream()));
+        HIPCHK(hipStreamSynchronize(x.eng->stream()));
+    } catch (const HipFailure &f) {
+        return device_error(f);
+    }
+    return SRW_OK;
+}
+
+}  // extern "C"
+
+// ================================================================ serving
+
+struct srw_server {
+    std::unique_ptr<Engine> eng;
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv_in, cv_out;
+    std::deque<Problem *> inbox;
+    std::deque<Problem *> outbox;
+    std::vector<Problem *> returned;   // owned until the next poll
+    bool stop = false;
+    int64_t submitted = 0, polled = 0;
+    int max_slots = 4096;
+    std::string fatal;
+};
+
+static void server_loop(srw_server *s) {
+    std::deque<Problem *> pending;
+    std::vector<Problem *> active;
+    try {
+        HIPCHK(hipSetDevice(s->eng->device()));
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(s->mu);
+                if (active.empty() && pending.empty())
+                    s->cv_in.wait(lk, [&] { return s->stop || !s->inbox.empty(); });
+                if (s->stop) break;
+                while (!s->inbox.empty()) {
+                    pending.push_back(s->inbox.front());
+                    s->inbox.pop_front();
+                }
+            }
+            std::vector<Problem *> fresh;
+            std::vector<Problem *> done_now;
+            while (!pending.empty() && (int)active.size() < s->max_slots) {
+                Problem *p = pending.front();
+                if (!active.empty() && s->eng->in_use() + p->est_bytes > s->eng->budget()) break;
+                pending.pop_front();
+                if (s->eng->admit(p)) {
+                    active.push_back(p);
+                    fresh.push_back(p);
+                } else if (active.empty()) {
+                    s->eng->finish_error(p, SRW_ENOMEM);
+                    done_now.push_back(p);
+                } else {
+                    pending.push_front(p);
+                    break;
+                }
+            }
+            if (!fresh.empty()) s->eng->init(fresh);
+            if (!active.empty()) s->eng->step(active);
+            std::vector<Problem *> still;
+            for (Problem *p : active) (p->status == 1 ? still : done_now).push_back(p);
+            active.swap(still);
+            if (!done_now.empty()) {
+                std::lock_guard<std::mutex> lk(s->mu);
+                for (Problem *p : done_now) s->outbox.push_back(p);
+                s->cv_out.notify_all();
+            }
+        }
+    } catch (const HipFailure &f) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->fatal = std::string("HIP error ") + hipGetErrorString(f.e) + " in " + f.where;
+        for (Problem *p : active) { p->status = SRW_EDEVICE; s->outbox.push_back(p); }
+        for (Problem *p : pending) { p->status = SRW_EDEVICE; s->outbox.push_back(p); }
+        s->cv_out.notify_all();
+        return;
+    }
+    for (Problem *p : active) delete p;     // stopped with work in flight
+    for (Problem *p : pending) delete p;
+}
+
+extern "C" {
+
+int srw_server_create(srw_server **out, const srw_config *cfg) {
+    if (!out) return set_error(SRW_EINVAL, "out is NULL");
+    *out = nullptr;
+    srw_config c{0, 0, 0};
+    if (cfg) c = *cfg;
+    Backing b;
+    {
+        Context &x = ctx();
+        std::lock_guard<std::mutex> g(x.mu);
+        b = x.backing;
+    }
+    srw_server *s = new srw_server();
+    try {
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || count <= c.device) {
+            (void)hipGetLastError();
+            delete s;
+            return set_error(SRW_EDEVICE, "no such HIP device");
+        }
+        s->eng.reset(new Engine(c.device, b, c.hbm_budget, nullptr));
+    } catch (const HipFailure &f) {
+        delete s;
+        return device_error(f);
+    }
+    s->max_slots = c.max_slots > 0 ? c.max_slots : 4096;
+    s->worker = std::thread(server_loop, s);
+    *out = s;
+    return SRW_OK;
+}
+
+int srw_server_submit(srw_server *s, int32_t n, int32_t k, const int32_t *delta, uint64_t tag) {
+    if (!s) return set_error(SRW_EINVAL, "server is NULL");
+    int rc = check_input(n, k, delta);
+    if (rc) return rc;
+    Problem *p = make_problem(n, k, delta);
+    p->tag = tag;
+    bool immediate = false;
+    if (!is_synchronizing(n, k, delta)) {
+        p->status = SRW_ENOTSYNC;
+        immediate = true;
+    } else if (n == 1) {
+        p->status = SRW_OK;
+        p->r = 0;
+        immediate = true;
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!s->fatal.empty()) {
+        delete p;
+        return set_error(SRW_EDEVICE, s->fatal);
+    }
+    s->submitted++;
+    if (immediate) {
+        p->t_admit = p->t_done = now_ms();
+        s->outbox.push_back(p);
+        s->cv_out.notify_all();
+    } else {
+        s->inbox.push_back(p);
+        s->cv_in.notify_all();
+    }
+    return SRW_OK;
+}
+
+int srw_server_poll(srw_server *s, srw_result *out, int32_t max, int32_t timeout_us) {
+    if (!s || !out || max < 1) return set_error(SRW_EINVAL, "bad arguments");
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (Problem *p : s->returned) delete p;
+    s->returned.clear();
+    if (s->outbox.empty() && timeout_us > 0)
+        s->cv_out.wait_for(lk, std::chrono::microseconds(timeout_us), [&] { return !s->outbox.empty(); });
+    if (s->outbox.empty()) return SRW_ETIMEOUT;
+    int cnt = 0;
+    while (cnt < max && !s->outbox.empty()) {
+        Problem *p = s->outbox.front();
+        s->outbox.pop_front();
+        srw_result &r = out[cnt++];
+        r.tag = p->tag;
+        r.status = p->status;
+        r.r = p->status == SRW_OK ? p->r : -1;
+        r.word = p->word.empty() ? nullptr : p->word.data();
+        r.latency_ms = p->t_done - p->t_submit;
+        r.queue_ms = p->t_admit - p->t_submit;
+        s->returned.push_back(p);
+        s->polled++;
+    }
+    return cnt;
+}
+
+int64_t srw_server_pending(srw_server *s) {
+    if (!s) return set_error(SRW_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(s->mu);
+    return s->submitted - s->polled;
+}
+
+void srw_server_destroy(srw_server *s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv_in.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    for (Problem *p : s->returned) delete p;
+    for (Problem *p : s->outbox) delete p;
+    for (Problem *p : s->inbox) delete p;
+    s->eng.reset();
+    delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,546 @@
+// srw_kernels.hip -- gfx950 kernels of one bidirectional-BFS step.
+//
+// Paper: Szykula & Zyzik, "An Improved Algorithm for Finding the Shortest
+// Synchronizing Words".  One step of Alg. 1 (plain variant: duplicate removal
+// only) for every segment (automaton) of a batch:
+//
+//   k_expand    CalculateImages / CalculatePreimages (Alg. 1; the image and
+//               preimage definitions of Section 2).  Candidate keys: forward
+//               g = i*k + a, inverse g = a*m + i (letter-major), so that key
+//               order is the lexicographic order of the words.
+//   k_insert    duplicate removal (Alg. 1 removes duplicates of the new list;
+//               here a device hash set per side also drops sets seen on an
+//               earlier level).  The least key of equal candidates wins.
+//   k_count, k_scan, k_compact
+//               stream compaction of the winners in key order into the new
+//               level, with the parent key stored per row (predecessor
+//               pointers, end of the Section 2 intro).
+//   k_transpose a new inverse level into 64-set tiles of column words.
+//   k_meet      the meet test of Alg. 1: least (i, j) with X_i subset of Y_j
+//               (Section 2: X in the BFS list, Y in the IBFS list).  Bit-
+//               sliced: for a tile of 64 sets Y, the AND of the columns of
+//               the states of X has bit j set iff X is a subset of Y_j.
+//   k_trace     walks the parent keys back to the reset word.
+//
+// All arithmetic is exact integer / bitwise.  Subsets are W = ceil(n/64)
+// 64-bit words; state q is bit q%64 of word q/64; bits >= n are zero.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "srw_device.h"
+
+namespace srw {
+
+// ---------------------------------------------------------------- helpers
+
+__device__ __forceinline__ int find_seg(const int64_t *pre, int nseg, int64_t b) {
+    int lo = 0, hi = nseg;  // pre[lo] <= b < pre[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (pre[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ u64 fmix64(u64 z) {
+    z ^= z >> 33;
+    z *= 0xff51afd7ed558ccdull;
+    z ^= z >> 33;
+    z *= 0xc4ceb9fe1a85ec53ull;
+    z ^= z >> 33;
+    return z;
+}
+
+template <int W>
+__device__ __forceinline__ u64 set_hash(const u64 (&x)[W]) {
+    u64 h = 0x6a09e667f3bcc909ull;
+#pragma unroll
+    for (int w = 0; w < W; ++w) h = fmix64(h ^ (x[w] + 0x9E3779B97F4A7C15ull * (u64)(w + 1)));
+    return h;
+}
+
+__device__ __forceinline__ u64 load_slot(u64 *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ u32 lanes_below(u64 mask) {
+    return __builtin_amdgcn_mbcnt_hi((u32)(mask >> 32), __builtin_amdgcn_mbcnt_lo((u32)mask, 0u));
+}
+
+__device__ __forceinline__ int lowest_bit(u64 v) { return __ffsll((unsigned long long)v) - 1; }
+
+#define SRW_SWITCH_W(Wv, CALL)                                   \
+    switch (Wv) {                                                \
+    case 1: { constexpr int W = 1; CALL; } break;                \
+    case 2: { constexpr int W = 2; CALL; } break;                \
+    case 3: { constexpr int W = 3; CALL; } break;                \
+    case 4: { constexpr int W = 4; CALL; } break;                \
+    case 5: { constexpr int W = 5; CALL; } break;                \
+    case 6: { constexpr int W = 6; CALL; } break;                \
+    case 7: { constexpr int W = 7; CALL; } break;                \
+    default: { constexpr int W = 8; CALL; } break;               \
+    }
+
+// ---------------------------------------------------------------- expand
+
+// Forward: X = delta(S, a) = { delta(q, a) | q in S }, scattering the set
+// bits of S.  Inverse: Y = delta^-1(S, a) = { q | delta(q, a) in S },
+// gathering one bit of S per state q.  Each thread owns a row of LDS for the
+// bit-addressed side (registers cannot be indexed by a run-time word).
+template <int W>
+__device__ void expand_w(const StepDesc &d, int64_t lb, u64 *lds) {
+    const int tid = threadIdx.x;
+    const int64_t g = lb * kBS + tid;
+    if (g >= d.C) return;
+    const int n = d.n;
+    if (d.dir == 0) {
+        const int64_t i = g / d.k;
+        const int a = (int)(g - i * d.k);
+        const u64 *S = d.par_rows + i * W;
+        const uint16_t *da = d.delta + (int64_t)a * n;
+#pragma unroll
+        for (int w = 0; w < W; ++w) lds[w * kBS + tid] = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            u64 bits = S[w];
+            while (bits) {
+                const int b = lowest_bit(bits);
+                bits &= bits - 1;
+                const int t = da[w * 64 + b];
+                lds[(t >> 6) * kBS + tid] |= 1ull << (t & 63);
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w) d.cand[g * W + w] = lds[w * kBS + tid];
+    } else {
+        const int a = (int)(g / d.m);
+        const int64_t i = g - (int64_t)a * d.m;
+        const u64 *S = d.par_rows + i * W;
+        const uint16_t *da = d.delta + (int64_t)a * n;
+#pragma unroll
+        for (int w = 0; w < W; ++w) lds[w * kBS + tid] = S[w];
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            u64 y = 0;
+            const int qn = min(64, n - 64 * w);
+            for (int b = 0; b < qn; ++b) {
+                const int t = da[64 * w + b];
+                const u64 sw = lds[(t >> 6) * kBS + tid];
+                y |= ((sw >> (t & 63)) & 1ull) << b;
+            }
+            d.cand[g * W + w] = y;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kBS) k_expand(const StepDesc *descs, const int64_t *pre, int nseg) {
+    __shared__ u64 lds[kMaxW * kBS];
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const StepDesc &d = descs[s];
+    const int64_t lb = (int64_t)blockIdx.x - pre[s];
+    SRW_SWITCH_W(d.W, expand_w<W>(d, lb, lds));
+}
+
+// ---------------------------------------------------------------- insert
+
+template <int W>
+__device__ void insert_w(const StepDesc &d, int64_t lb) {
+    const int64_t g = lb * kBS + threadIdx.x;
+    if (g >= d.C) return;
+    u64 x[W];
+    u64 any = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) { x[w] = d.cand[g * W + w]; any |= x[w]; }
+    if (any == 0) { d.cslot[g] = kDrop; return; }   // empty preimage
+    const u64 h = set_hash<W>(x);
+    const u32 fp = (u32)(h >> 32);
+    const u64 mine = ((u64)fp << 32) | (u64)(kCandBit | (u32)g);
+    u64 pos = h & d.tab_mask;
+    for (;;) {
+        u64 cur = load_slot(&d.tab[pos]);
+        if (cur == kEmpty) {
+            const u64 prev = atomicCAS(&d.tab[pos], kEmpty, mine);
+            if (prev == kEmpty) { d.cslot[g] = (u32)pos; return; }
+            cur = prev;
+        }
+        if ((u32)(cur >> 32) == fp) {
+            const u32 ref = (u32)cur;
+            const u64 *o = (ref & kCandBit) ? d.cand + (u64)(ref & ~kCandBit) * W
+                                            : d.vis_rows + (u64)ref * W;
+            bool eq = true;
+#pragma unroll
+            for (int w = 0; w < W; ++w) eq = eq && (o[w] == x[w]);
+            if (eq) {
+                if (ref & kCandBit) {
+                    // every value this slot ever holds names the same set,
+                    // so the minimum is the least key among equal candidates
+                    atomicMin(&d.tab[pos], mine);
+                    d.cslot[g] = (u32)pos;
+                } else {
+                    d.cslot[g] = kDrop;   // visited on an earlier level
+                }
+                return;
+            }
+        }
+        pos = (pos + 1) & d.tab_mask;
+    }
+}
+
+__global__ void __launch_bounds__(kBS) k_insert(const StepDesc *descs, const int64_t *pre, int nseg) {
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const StepDesc &d = descs[s];
+    const int64_t lb = (int64_t)blockIdx.x - pre[s];
+    SRW_SWITCH_W(d.W, insert_w<W>(d, lb));
+}
+
+// ------------------------------------------------------------ compaction
+
+__device__ __forceinline__ bool is_winner(const StepDesc &d, int64_t g) {
+    const u32 sl = d.cslot[g];
+    if (sl == kDrop) return false;
+    return (u32)d.tab[sl] == (kCandBit | (u32)g);
+}
+
+__global__ void __launch_bounds__(kBS) k_count(const StepDesc *descs, const int64_t *pre, int nseg,
+                                               u32 *blk_cnt) {
+    __shared__ u32 wsum[kBS / 64];
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const StepDesc &d = descs[s];
+    const int64_t lb = (int64_t)blockIdx.x - pre[s];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    u32 c = 0;
+#pragma unroll
+    for (int t = 0; t < kCB / kBS; ++t) {
+        const int64_t g = lb * kCB + t * kBS + tid;
+        const bool f = g < d.C && is_winner(d, g);
+        c += (u32)__popcll(__ballot(f));
+    }
+    if (lane == 0) wsum[wave] = c;
+    __syncthreads();
+    if (tid == 0) {
+        u32 tot = 0;
+        for (int w = 0; w < kBS / 64; ++w) tot += wsum[w];
+        blk_cnt[d.cblk_base + lb] = tot;
+    }
+}
+
+// one block per segment: exclusive scan of its compaction-block counts
+__global__ void __launch_bounds__(kBS) k_scan(const StepDesc *descs, int nseg, const u32 *blk_cnt,
+                                              u32 *blk_off) {
+    __shared__ u32 wsum[kBS / 64];
+    const int s = blockIdx.x;
+    if (s >= nseg) return;
+    const StepDesc &d = descs[s];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    u64 running = 0;
+    for (int64_t c0 = 0; c0 < d.ncblk; c0 += kBS) {
+        const int64_t idx = c0 + tid;
+        const u32 v = idx < d.ncblk ? blk_cnt[d.cblk_base + idx] : 0u;
+        u32 incl = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const u32 o = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += o;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        u32 wpre = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < kBS / 64; ++w) {
+            if (w < wave) wpre += wsum[w];
+            tot += wsum[w];
+        }
+        if (idx < d.ncblk) blk_off[d.cblk_base + idx] = (u32)(running + wpre + incl - v);
+        running += tot;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        d.res[0] = running;
+        d.res[1] = kEmpty;
+    }
+}
+
+__global__ void __launch_bounds__(kBS) k_compact(const StepDesc *descs, const int64_t *pre, int nseg,
+                                                 const u32 *blk_off) {
+    __shared__ u32 wsum[kBS / 64];
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const StepDesc &d = descs[s];
+    const int64_t lb = (int64_t)blockIdx.x - pre[s];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int W = d.W;
+    u32 rank0 = blk_off[d.cblk_base + lb];
+#pragma unroll
+    for (int t = 0; t < kCB / kBS; ++t) {
+        const int64_t g = lb * kCB + t * kBS + tid;
+        const bool f = g < d.C && is_winner(d, g);
+        const u64 mask = __ballot(f);
+        if (lane == 0) wsum[wave] = (u32)__popcll(mask);
+        __syncthreads();
+        u32 wpre = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < kBS / 64; ++w) {
+            if (w < wave) wpre += wsum[w];
+            tot += wsum[w];
+        }
+        if (f) {
+            const u64 rank = rank0 + wpre + lanes_below(mask);
+            for (int w = 0; w < W; ++w) d.out_rows[rank * W + w] = d.cand[g * W + w];
+            d.out_par[rank] = (u32)g;
+            const u32 sl = d.cslot[g];
+            const u64 e = d.tab[sl];
+            d.tab[sl] = (e & 0xFFFFFFFF00000000ull) | (u64)(u32)(d.out_base + (int64_t)rank);
+        }
+        rank0 += tot;
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ transpose
+
+// One wave transposes word w of the 64 rows of tile `tile`: lane l ends with
+// column q = 64*w + l, bit j = [state q in row 64*tile + j].
+__device__ __forceinline__ void transpose_tile(const u64 *rows, int64_t count, int W, u64 *YT,
+                                               int64_t tile, int w) {
+    const int lane = threadIdx.x & 63;
+    const int64_t j = tile * 64 + lane;
+    const u64 v = j < count ? rows[j * W + w] : 0ull;
+    u64 col = 0;
+    for (int b = 0; b < 64; ++b) {
+        const u64 m = __ballot((v >> b) & 1ull);
+        if (lane == b) col = m;
+    }
+    YT[(tile * W + w) * 64 + lane] = col;
+}
+
+__global__ void __launch_bounds__(kBS) k_transpose(const StepDesc *descs, const int64_t *pre, int nseg) {
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const StepDesc &d = descs[s];
+    const int64_t lb = (int64_t)blockIdx.x - pre[s];
+    const int64_t wv = lb * (kBS / 64) + (threadIdx.x >> 6);
+    if (wv >= d.ntr_waves) return;
+    const int64_t count = (int64_t)d.res[0];
+    const int64_t tile = wv / d.W;
+    const int w = (int)(wv - tile * d.W);
+    if (tile * 64 >= count) return;
+    transpose_tile(d.out_rows, count, d.W, d.YT, tile, w);
+}
+
+__global__ void __launch_bounds__(kBS) k_transpose_rows(const TransposeDesc *descs, const int64_t *pre,
+                                                        int nseg) {
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const TransposeDesc &d = descs[s];
+    const int64_t lb = (int64_t)blockIdx.x - pre[s];
+    const int64_t wv = lb * (kBS / 64) + (threadIdx.x >> 6);
+    const int64_t tiles = (d.count + 63) / 64;
+    if (wv >= tiles * d.W) return;
+    const int64_t tile = wv / d.W;
+    transpose_tile(d.rows, d.count, d.W, d.YT, tile, (int)(wv - tile * d.W));
+}
+
+// ------------------------------------------------------------------ meet
+
+template <int W>
+__device__ void meet_w(const StepDesc &d, int64_t lb, u64 *cols) {
+    const int tid = threadIdx.x;
+    const int64_t nX = d.nX >= 0 ? d.nX : (int64_t)d.res[0];
+    const int64_t nY = d.nY >= 0 ? d.nY : (int64_t)d.res[0];
+    const int64_t xb = lb % d.nXb, yc = lb / d.nXb;
+    const int64_t tiles = (nY + 63) / 64;
+    const int64_t t0 = yc * d.tpb;
+    const int64_t t1 = min(t0 + (int64_t)d.tpb, tiles);
+    if (t0 >= t1 || xb * kBS >= nX) return;  // whole block
+    const int64_t nw = (t1 - t0) * 64 * W;
+    const u64 *src = d.YT + t0 * 64 * W;
+    for (int64_t e = tid; e < nw; e += kBS) cols[e] = src[e];
+    __syncthreads();
+    const int64_t i = xb * kBS + tid;
+    if (i >= nX) return;
+    const u64 best = load_slot(d.res + 1);
+    if ((best >> 32) < (u64)i) return;       // a smaller i already met
+    u64 x[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) x[w] = d.X[i * W + w];
+    for (int64_t t = t0; t < t1; ++t) {
+        const u64 *c = cols + (t - t0) * 64 * W;
+        u64 M = ~0ull;
+        bool alive = true;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            if (!alive) break;
+            u64 bits = x[w];
+            while (bits) {
+                const int b = lowest_bit(bits);
+                bits &= bits - 1;
+                M &= c[64 * w + b];
+                if (M == 0) { alive = false; break; }
+            }
+        }
+        if (alive) {
+            const u64 j = (u64)t * 64 + (u64)lowest_bit(M);
+            atomicMin(d.res + 1, ((u64)i << 32) | j);
+            return;
+        }
+    }
+}
+
+// Grid-stride over work items (a work item is 256 sets X against up to
+// `tpb` tiles of 64 sets Y): the item count can exceed the grid limit.
+__global__ void __launch_bounds__(kBS) k_meet(const StepDesc *descs, const int64_t *pre, int nseg,
+                                              int64_t items) {
+    __shared__ u64 cols[kMeetTileWords * 64];
+    for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
+        const int s = find_seg(pre, nseg, it);
+        const StepDesc &d = descs[s];
+        __syncthreads();   // the previous item is done with cols
+        SRW_SWITCH_W(d.W, meet_w<W>(d, it - pre[s], cols));
+    }
+}
+
+// ------------------------------------------------------- init / rehash
+
+// level 0 of both sides: Q forward, the n singletons inverse (Alg. 1 init)
+__global__ void __launch_bounds__(kBS) k_init(const InitDesc *descs, const int64_t *pre, int nseg) {
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const InitDesc &d = descs[s];
+    const int64_t q = ((int64_t)blockIdx.x - pre[s]) * kBS + threadIdx.x;
+    if (q > d.n) return;
+    const int W = d.W;
+    if (q == d.n) {
+        for (int w = 0; w < W; ++w) {
+            const int lo = 64 * w;
+            const int cnt = d.n - lo >= 64 ? 64 : d.n - lo;
+            d.rows_f[w] = cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull);
+        }
+        d.par_f[0] = kDrop;
+        return;
+    }
+    for (int w = 0; w < W; ++w) d.rows_b[q * W + w] = (w == (q >> 6)) ? (1ull << (q & 63)) : 0ull;
+    d.par_b[q] = kDrop;
+}
+
+template <int W>
+__device__ void rehash_w(const RehashDesc &d, int64_t id) {
+    u64 x[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) x[w] = d.rows[id * W + w];
+    const u64 h = set_hash<W>(x);
+    const u64 e = (h & 0xFFFFFFFF00000000ull) | (u64)(u32)id;
+    u64 pos = h & d.tab_mask;
+    for (;;) {
+        if (load_slot(&d.tab[pos]) == kEmpty && atomicCAS(&d.tab[pos], kEmpty, e) == kEmpty) return;
+        pos = (pos + 1) & d.tab_mask;
+    }
+}
+
+// stored rows are pairwise distinct, so each just needs a free slot
+__global__ void __launch_bounds__(kBS) k_rehash(const RehashDesc *descs, const int64_t *pre, int nseg) {
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const RehashDesc &d = descs[s];
+    const int64_t id = ((int64_t)blockIdx.x - pre[s]) * kBS + threadIdx.x;
+    if (id >= d.count) return;
+    SRW_SWITCH_W(d.W, rehash_w<W>(d, id));
+}
+
+__global__ void __launch_bounds__(kBS) k_fill(u64 *p, int64_t count, u64 v) {
+    const int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * kBS;
+    for (int64_t e = i; e < count; e += stride) p[e] = v;
+}
+
+// ------------------------------------------------------------- traceback
+
+// Forward key g = i*k + a: parent i = g / k, letter a = g % k (word position
+// L-1).  Inverse key g = a*|L_prev| + i: letter a is the next letter of the
+// inverse half, read from its last level down.
+__global__ void k_trace(const TraceDesc *descs, int count) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const TraceDesc &d = descs[t];
+    int64_t i = d.i;
+    for (int L = d.f; L > 0; --L) {
+        const u32 g = d.par_f[d.off_f[L] + i];
+        d.out[L - 1] = (uint8_t)(g % (u32)d.k);
+        i = g / (u32)d.k;
+    }
+    int64_t j = d.j;
+    for (int L = d.b, pos = 0; L > 0; --L, ++pos) {
+        const u32 g = d.par_b[d.off_b[L] + j];
+        const int64_t prev = d.off_b[L] - d.off_b[L - 1];
+        d.out[d.f + pos] = (uint8_t)((int64_t)g / prev);
+        j = (int64_t)g % prev;
+    }
+}
+
+// ------------------------------------------------------------- launchers
+
+static inline hipError_t launch_checked() { return hipGetLastError(); }
+
+hipError_t launch_expand(const StepDesc *d, const int64_t *pre, int nseg, int64_t blocks, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_expand, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
+    return launch_checked();
+}
+hipError_t launch_insert(const StepDesc *d, const int64_t *pre, int nseg, int64_t blocks, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_insert, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
+    return launch_checked();
+}
+hipError_t launch_count(const StepDesc *d, const int64_t *pre, int nseg, int64_t blocks, u32 *cnt,
+                        hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg, cnt);
+    return launch_checked();
+}
+hipError_t launch_scan(const StepDesc *d, int nseg, const u32 *cnt, u32 *off, hipStream_t st) {
+    if (nseg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scan, dim3((unsigned)nseg), dim3(kBS), 0, st, d, nseg, cnt, off);
+    return launch_checked();
+}
+hipError_t launch_compact(const StepDesc *d, const int64_t *pre, int nseg, int64_t blocks,
+                          const u32 *off, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg, off);
+    return launch_checked();
+}
+hipError_t launch_transpose(const StepDesc *d, const int64_t *pre, int nseg, int64_t blocks,
+                            hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_transpose, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
+    return launch_checked();
+}
+hipError_t launch_transpose_rows(const TransposeDesc *d, const int64_t *pre, int nseg, int64_t blocks,
+                                 hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_transpose_rows, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
+    return launch_checked();
+}
+hipError_t launch_meet(const StepDesc *d, const int64_t *pre, int nseg, int64_t items, hipStream_t st) {
+    if (items <= 0) return hipSuccess;
+    const int64_t grid = items < kMeetMaxGrid ? items : kMeetMaxGrid;
+    hipLaunchKernelGGL(k_meet, dim3((unsigned)grid), dim3(kBS), 0, st, d, pre, nseg, items);
+    return launch_checked();
+}
+hipError_t launch_init(const InitDesc *d, const int64_t *pre, int nseg, int64_t blocks, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_init, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
+    return launch_checked();
+}
+hipError_t launch_rehash(const RehashDesc *d, const int64_t *pre, int nseg, int64_t blocks, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rehash, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
+    return launch_checked();
+}
+hipError_t launch_fill(u64 *p, int64_t count, u64 v, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + kBS - 1) / kBS;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(kBS), 0, st, p, count, v);
+    return launch_checked();
+}
+hipError_t launch_trace(const TraceDesc *d, int count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_trace, dim3((unsigned)((count + 63) / 64)), dim3(64), 0, st, d, count);
+    return launch_checked();
+}
+
+}  // namespace srw

@@ -1,0 +1,290 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Results (r and the lex-least reset word) are integers and words: the bar is
+bit-exact equality.  Per-level tests compare the device lists (sets, order,
+parent keys) with the oracle's level by level.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2207_05495_amd import inputs as I
+from paper_2207_05495_amd import srw
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    srw.use_torch(0)
+    for key, v in (("schedule", 0), ("meet_tiles", 0), ("keep_levels", 0), ("budget", 0)):
+        srw.set_option(key, v)
+    yield
+    for key, v in (("schedule", 0), ("meet_tiles", 0), ("keep_levels", 0), ("budget", 0)):
+        srw.set_option(key, v)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rand_sync(n, k, i, base=I.BASE_SEED):
+    d, _ = I.first_synchronizing(n, k, I.member_seed(base, i), O.is_synchronizing)
+    return d
+
+
+# --------------------------------------------------------------- golden
+
+def hand_cases():
+    from tests.test_oracle import load_hand_examples
+    return load_hand_examples()
+
+
+@pytest.mark.parametrize("case", hand_cases())
+def test_hand_examples(case):
+    n, k, d, r, w = case
+    say("hand", n, k, d)
+    if r == O.ENOTSYNC:
+        with pytest.raises(srw.SrwError) as e:
+            srw.solve(n, k, d)
+        assert e.value.code == srw.ENOTSYNC
+    else:
+        assert srw.solve(n, k, d) == (r, w)
+
+
+@pytest.mark.parametrize("n", list(range(2, 41)))
+def test_cerny(n):
+    say("cerny", n)
+    assert srw.solve(n, 2, I.cerny(n)) == ((n - 1) ** 2, I.cerny_word(n))
+
+
+# ------------------------------------------------------ random vs oracle
+
+def test_config1_n64_k2_100_seeds():
+    """n=64, k=2, one 64-bit word per subset: 100 seeds."""
+    for i in range(100):
+        d = rand_sync(64, 2, i)
+        say("n=64 seed", i)
+        assert srw.solve(64, 2, d) == O.bidir(64, 2, d)[:2]
+
+
+@pytest.mark.parametrize("n,k", [(63, 2), (65, 2), (127, 2), (128, 2), (129, 3), (191, 2),
+                                 (192, 2), (193, 2), (100, 4), (40, 7)])
+def test_ragged_widths(n, k):
+    for i in range(3):
+        d = rand_sync(n, k, i, base=77)
+        say("ragged", n, k, i)
+        assert srw.solve(n, k, d) == O.bidir(n, k, d)[:2]
+
+
+def max_size_automaton(n, seed):
+    """Letter 0 halves every state (q -> q // 2), letter 1 is a random
+    permutation: r <= ceil(log2 n), so the oracle is quick at n = 512."""
+    rng = np.random.default_rng(seed)
+    half = (np.arange(n) // 2).astype(np.int32)
+    perm = rng.permutation(n).astype(np.int32)
+    return np.concatenate([half, perm])
+
+
+@pytest.mark.parametrize("n", [449, 511, 512])
+def test_max_width(n):
+    for s in range(3):
+        d = max_size_automaton(n, s)
+        say("max width", n, s)
+        assert srw.solve(n, 2, d) == O.bidir(n, 2, d)[:2]
+
+
+# ------------------------------------------------------ per-level parity
+
+@pytest.mark.parametrize("n,k,i", [(20, 2, 0), (64, 2, 1), (100, 3, 2), (130, 2, 3),
+                                   (200, 2, 4), (70, 4, 5), (33, 3, 6)])
+def test_levels_match_oracle(n, k, i):
+    d = rand_sync(n, k, i, base=555)
+    say("levels", n, k, i)
+    srw.set_option("keep_levels", 1)
+    try:
+        got = srw.solve(n, k, d)
+        gl = [srw.last_levels(side, (n + 63) // 64) for side in (0, 1)]
+    finally:
+        srw.set_option("keep_levels", 0)
+    r, w, info = O.bidir(n, k, d, keep_levels=True)
+    assert got == (r, w)
+    for side in (0, 1):
+        ol = info["levels"][side]
+        assert len(gl[side]) == len(ol)
+        for L, ((grows, gpar), (orows, opar)) in enumerate(zip(gl[side], ol)):
+            assert np.array_equal(grows, orows), (side, L)
+            if L > 0:
+                assert np.array_equal(gpar.astype(np.int64), opar), (side, L)
+
+
+# ------------------------------------------------------ invariances
+
+@pytest.mark.parametrize("sched", [(1, 1), (1, 7), (1, 99), (2, 0)])
+def test_schedule_invariance(sched):
+    mode, seed = sched
+    cases = [(rand_sync(90, 2, j, base=31), 90, 2) for j in range(3)]
+    cases.append((I.cerny(20), 20, 2))
+    want = [srw.solve(n, k, d) for d, n, k in cases]
+    srw.set_option("schedule", mode)
+    srw.set_option("sched_seed", seed)
+    try:
+        for (d, n, k), w in zip(cases, want):
+            say("schedule", mode, seed, n)
+            assert srw.solve(n, k, d) == w
+    finally:
+        srw.set_option("schedule", 0)
+
+
+@pytest.mark.parametrize("tiles", [1, 2, 3, 8, 32])
+def test_meet_tile_shape_invariance(tiles):
+    d = rand_sync(150, 2, 4, base=8)
+    want = O.bidir(150, 2, d)[:2]
+    srw.set_option("meet_tiles", tiles)
+    try:
+        say("meet tiles", tiles)
+        assert srw.solve(150, 2, d) == want
+    finally:
+        srw.set_option("meet_tiles", 0)
+
+
+def test_relabel_invariance():
+    n, k = 120, 2
+    d = rand_sync(n, k, 9, base=17)
+    want = srw.solve(n, k, d)
+    for s in range(3):
+        perm = np.random.default_rng(s).permutation(n)
+        say("relabel", s)
+        assert srw.solve(n, k, I.relabel(d, n, k, perm)) == want
+
+
+# ------------------------------------------------------ batch and serving
+
+def mixed_cases(count, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        if i % 10 == 9:
+            n = int(rng.integers(8, 25))
+            out.append((n, 2, I.cerny(n)))
+        else:
+            n = int(rng.integers(24, 110))
+            k = int(rng.integers(2, 4))
+            out.append((n, k, rand_sync(n, k, i, base=seed)))
+    return out
+
+
+def test_batch_matches_oracle_and_single():
+    cases = mixed_cases(60, 1234)
+    cases.append((1, 2, [0, 0]))
+    cases.append((3, 2, [1, 2, 0, 0, 2, 1]))   # not synchronizing
+    say("batch", len(cases))
+    res = srw.solve_batch(cases)
+    for (n, k, d), (st, r, w) in zip(cases, res):
+        if n == 3:
+            assert st == srw.ENOTSYNC
+            continue
+        assert st == srw.OK
+        assert (r, w) == O.bidir(n, k, d)[:2]
+    # the same automaton alone gives the same answer
+    for (n, k, d), (st, r, w) in list(zip(cases, res))[:10]:
+        assert srw.solve(n, k, d) == (r, w)
+
+
+def test_batch_slot_limit_same_results():
+    cases = mixed_cases(40, 99)
+    want = srw.solve_batch(cases)
+    srw.set_option("max_slots", 7)
+    try:
+        say("batch max_slots 7")
+        assert srw.solve_batch(cases) == want
+    finally:
+        srw.set_option("max_slots", 4096)
+
+
+def test_server_results_same_alone_and_in_mix():
+    cases = mixed_cases(50, 4321)
+    alone = [srw.solve(n, k, d) for n, k, d in cases]
+    say("server", len(cases))
+    got = {}
+    with srw.Server(max_slots=16) as s:
+        for t, (n, k, d) in enumerate(cases):
+            s.submit(n, k, d, t)
+            if t % 5 == 0:
+                for x in s.poll(0):
+                    got[x["tag"]] = x
+        while len(got) < len(cases):
+            for x in s.poll(200000):
+                got[x["tag"]] = x
+        assert s.pending() == 0
+    for t, (n, k, d) in enumerate(cases):
+        x = got[t]
+        assert x["status"] == srw.OK
+        assert (x["r"], x["word"]) == alone[t]
+        assert x["latency_ms"] >= x["queue_ms"] >= 0
+
+
+# ------------------------------------------------------ limits and errors
+
+def test_budget_exhaustion_then_recovery():
+    d = rand_sync(200, 3, 1, base=5)
+    want = O.bidir(200, 3, d)[:2]
+    srw.set_option("budget", 96 << 20)
+    try:
+        say("tiny budget")
+        with pytest.raises(srw.SrwError) as e:
+            srw.solve(200, 3, d)
+        assert e.value.code == srw.ENOMEM
+    finally:
+        srw.set_option("budget", 0)
+    assert srw.solve(200, 3, d) == want
+
+
+def test_word_cap():
+    with pytest.raises(srw.SrwError) as e:
+        srw.solve(10, 2, I.cerny(10), word_cap=5)
+    assert e.value.code == srw.EWORDCAP
+
+
+def test_r_only():
+    assert srw.solve(12, 2, I.cerny(12), want_word=False)[0] == 121
+
+
+# ------------------------------------------------------ full-size config 2
+
+def golden(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} not generated")
+    with open(path) as f:
+        return json.load(f)["cases"]
+
+
+def test_config2_n256_against_stored_oracle_values():
+    """n=256, k=2, four 64-bit words per subset: r and word of every seed
+    equal the oracle's stored values (tests/golden/make_golden.py)."""
+    for c in golden("config2.json"):
+        n, k = c["n"], c["k"]
+        d = I.random_automaton(n, k, c["seed"], c["attempt"])
+        say("config2 seed", c["seed"])
+        r, w = srw.solve(n, k, d)
+        assert r == c["r"]
+        assert "".join(map(str, w)) == c["word"]
+
+
+def test_config2_batched_equals_stored():
+    cs = golden("config2.json")
+    probs = [(c["n"], c["k"], I.random_automaton(c["n"], c["k"], c["seed"], c["attempt"]))
+             for c in cs]
+    say("config2 batched")
+    res = srw.solve_batch(probs)
+    for c, (st, r, w) in zip(cs, res):
+        assert st == srw.OK and r == c["r"] and "".join(map(str, w)) == c["word"]

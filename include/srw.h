@@ -134,7 +134,11 @@ int srw_set_stream(void *hip_stream);
  *                 1: pseudo-random side per step from "sched_seed"
  *                 2: alternate forward / inverse
  *   "sched_seed"  seed of schedule 1
- *   "meet_tiles"  tiles of 64 inverse sets per meet block (0: auto)
+ *   "meet"        0: auto; 1: always test 256 sets X against LDS-staged
+ *                 tiles of 64 sets Y; 2: bucket-sort every forward level
+ *                 and test 64-set chunks of it (any choice gives the same
+ *                 results; auto sorts the large levels)
+ *   "meet_tiles"  tiles of 64 inverse sets per LDS meet block (0: auto)
  *   "keep_levels" 1: keep the device lists of the last srw_solve for
  *                 srw_last_levels
  * Unknown keys give SRW_EINVAL. */
@@ -156,7 +160,8 @@ typedef struct srw_stats {
     int64_t bytes_compact;     /* algorithmic bytes of count+compact */
     int64_t peak_device_bytes; /* device memory held at peak */
 } srw_stats;
-/* kernel classes: 0 expand, 1 insert, 2 count+scan+compact, 3 transpose,
+/* kernel classes: 0 expand, 1 insert, 2 count+scan+compact, 3 meet
+ * preparation (transpose of inverse levels, bucket sort of forward levels),
  * 4 meet, 5 trace, 6 init/rehash/fill/copies, 7 whole steps (host view) */
 
 int srw_get_stats(srw_stats *out);

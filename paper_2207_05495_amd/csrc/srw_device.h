@@ -20,6 +20,9 @@ constexpr int kBS = 256;                 // threads per block (4 wave64)
 constexpr int kCB = 1024;                // candidates per compaction block
 constexpr int kMeetTileWords = 32;       // LDS budget of the meet: tiles*W <= this
 constexpr int64_t kMeetMaxGrid = 65536;  // meet blocks per launch (grid-stride beyond)
+constexpr int kCommonMax = 8;            // chunked meet: common states used per chunk
+constexpr int kCommonRound = 2;          // common columns loaded per round
+constexpr int kRowBatchMax = 256;        // candidate rows per group tested directly
 
 // A hash-slot is 64 bits: high 32 = fingerprint of the set, low 32 = ref.
 // ref < 2^31: id of a stored (visited) row of this side;
@@ -45,18 +48,46 @@ struct StepDesc {
     int64_t out_base;          // store id of the first new row
     int64_t cblk_base;         // first compaction block of this segment
     int64_t ncblk;             // compaction blocks of this segment
-    // meet (X: forward level, Y: inverse level, transposed in tiles of 64)
-    const u64 *X;
+    // meet (X: forward level, Y: inverse level, transposed in tiles of 64
+    // sets; column q of tile t -- bit j says whether state q is in set
+    // 64t+j -- is YT[q * nt + t] (state-major, nt = ceil(|Y| / 64)) and
+    // YTt[t * 64W + q] (tile-major))
+    const u64 *X;              // mode 1: the level sorted by key
     int64_t nX;                // -1: the new level (count in res[0])
-    u64 *YT;                   // tiles of 64*W column words
+    u64 *YT;
+    u64 *YTt;
+    const u64 *Yrows;          // the inverse level's rows
     int64_t nY;                // -1: the new level (count in res[0])
-    int64_t nXb, nYc;          // meet grid of this segment (upper bounds)
-    int32_t tpb;               // tiles per meet block
-    int32_t pad0;
+    int64_t nXb, nYc;          // mode 0 grid of this segment (upper bounds)
+    int32_t tpb;               // mode 0: tiles per meet block
+    int32_t meet_mode;         // 0: LDS tiles, 1: sorted 64-set chunks
+    const u32 *Xidx;           // mode 1: rank of each sorted X in its level
+    const u64 *Xcom;           // mode 1: AND of the 64 sets of each chunk
+    int64_t gitems_ub;         // mode 1: work items per chunk (upper bound)
+    int64_t ngi;               // mode 1: tile groups (of 64 tiles) per item
     // transpose of a new inverse level into YT
     int64_t ntr_waves;         // upper bound of (tile, word) waves
     // results: res[0] = new level size, res[1] = least (i << 32 | j) meeting pair
     u64 *res;
+};
+
+constexpr int kKeyBits = 16;             // sort key: the 16 most frequent states
+constexpr int kSortBins = 1 << kKeyBits;
+
+// Bucket sort of a new forward level by the membership of its most frequent
+// states, so that 64 consecutive sets share as many states as possible.
+struct SortDesc {
+    int32_t n, W;
+    const u64 *X;              // the new level (unsorted)
+    const u64 *cnt;            // &res[0]: its size
+    int64_t nub;               // upper bound of its size
+    u32 *hist;                 // n state counts
+    int32_t *top;              // kKeyBits states, most frequent first
+    u32 *keys;                 // nub
+    u32 *bins;                 // kSortBins counters, then offsets
+    u64 *xs_rows;              // nub rows, sorted
+    u32 *xs_idx;               // nub ranks
+    u64 *xs_common;            // ceil(nub/64) rows
 };
 
 struct InitDesc {
@@ -78,7 +109,7 @@ struct TransposeDesc {
     int32_t W, pad;
     const u64 *rows;
     int64_t count;
-    u64 *YT;
+    u64 *YT, *YTt;
 };
 
 struct TraceDesc {

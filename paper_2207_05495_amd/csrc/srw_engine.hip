@@ -33,11 +33,12 @@ hipError_t launch_scan(const StepDesc *, int, const u32 *, u32 *, hipStream_t);
 hipError_t launch_compact(const StepDesc *, const int64_t *, int, int64_t, const u32 *, hipStream_t);
 hipError_t launch_transpose(const StepDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_transpose_rows(const TransposeDesc *, const int64_t *, int, int64_t, hipStream_t);
-hipError_t launch_meet(const StepDesc *, const int64_t *, int, int64_t, hipStream_t);
+hipError_t launch_meet(const StepDesc *, const int64_t *, int, int, int, int64_t, hipStream_t);
 hipError_t launch_init(const InitDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_rehash(const RehashDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_fill(u64 *, int64_t, u64, hipStream_t);
 hipError_t launch_trace(const TraceDesc *, int, hipStream_t);
+hipError_t launch_sort(const SortDesc *, const int64_t *const[3], const int64_t[3], int, hipStream_t);
 
 // ------------------------------------------------------------------ errors
 
@@ -307,12 +308,19 @@ struct Problem {
     std::vector<int32_t> delta;
     uint16_t *d_delta = nullptr;
     SideState s[2];
-    u64 *colT = nullptr;      // current inverse level, tiles of 64*W columns
+    u64 *colT = nullptr;      // current inverse level transposed: colT_cap words state-major, then colT_cap tile-major
     int64_t colT_cap = 0;     // words
     u64 *cand = nullptr;
     int64_t cand_cap = 0;     // rows
     u32 *cslot = nullptr;
     int64_t cslot_cap = 0;
+    // the current forward level bucket-sorted for the chunked meet
+    u64 *xs_rows = nullptr, *xs_com = nullptr;
+    u32 *xs_idx = nullptr, *xs_keys = nullptr, *xs_hist = nullptr, *xs_bins = nullptr;
+    int32_t *xs_top = nullptr;
+    int64_t xs_cap = 0;       // rows
+    bool xs_valid = false;    // xs_* hold the current forward level
+    bool sort_now = false;    // this step sorts its new forward level
     int status = 1;           // 1 running, else SRW_ status
     int32_t r = -1;
     std::vector<uint8_t> word;
@@ -324,7 +332,13 @@ struct Problem {
 
 // --------------------------------------------------------------- options
 
+// a new forward level is bucket-sorted for the chunked meet when its
+// candidates and the pairs it will be tested against are at least these
+constexpr int64_t kSortMinCand = 2048;
+constexpr double kSortMinPairs = double(1 << 22);
+
 struct Options {
+    int meet = 0;             // 0 auto, 1 LDS tiles only, 2 chunks whenever possible
     int schedule = 0;
     uint64_t sched_seed = 1;
     int meet_tiles = 0;
@@ -442,7 +456,7 @@ class Engine {
             s.tab = (u64 *)A((size_t)s.tab_cap * 8);
         }
         p->colT_cap = ceil_div(n, 64) * 64 * W;
-        p->colT = (u64 *)A((size_t)p->colT_cap * 8);
+        p->colT = (u64 *)A((size_t)p->colT_cap * 16);   // state-major, then tile-major
         if (!ok) {
             release(p);
             return false;
@@ -487,7 +501,7 @@ class Engine {
                                            (u64)(p->s[sd].tab_cap - 1)});
                 rpre.push_back(rpre.back() + ceil_div(p->s[sd].nrows, kBS));
             }
-            tdesc[i] = TransposeDesc{p->W, 0, p->s[1].rows, p->n, p->colT};
+            tdesc[i] = TransposeDesc{p->W, 0, p->s[1].rows, p->n, p->colT, p->colT + p->colT_cap};
             tpre[i + 1] = tpre[i] + ceil_div(ceil_div(p->n, 64) * p->W, kBS / 64);
         }
         prof_begin(6);
@@ -551,10 +565,22 @@ class Engine {
         prof_end(6);
         const int nseg = (int)segp.size();
         if (nseg == 0) return;
+        {   // segments of equal width side by side: the meet launches per width
+            std::vector<int> ord(nseg);
+            for (int i = 0; i < nseg; ++i) ord[i] = i;
+            std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return segp[a]->W < segp[b]->W; });
+            std::vector<Problem *> sp(nseg);
+            std::vector<int> sd(nseg);
+            for (int i = 0; i < nseg; ++i) { sp[i] = segp[ord[i]]; sd[i] = segdir[ord[i]]; }
+            segp.swap(sp);
+            segdir.swap(sd);
+        }
 
         // descriptors
         std::vector<StepDesc> D(nseg);
         std::vector<int64_t> pe(nseg + 1, 0), pc(nseg + 1, 0), pt(nseg + 1, 0), pm(nseg + 1, 0);
+        std::vector<SortDesc> S;
+        std::vector<int64_t> pz(1, 0), pr(1, 0), pch(1, 0);
         if ((int64_t)nseg * 2 > res_cap_) {
             pool_->free(d_res_);
             res_cap_ = std::max<int64_t>((int64_t)nseg * 2, 2 * res_cap_);
@@ -592,6 +618,8 @@ class Engine {
                 d.nX = -1;
                 nx_ub = d.C;
                 d.YT = p->colT;
+                d.YTt = p->colT + p->colT_cap;
+                d.Yrows = p->s[1].rows + p->s[1].cur_start() * W;
                 d.nY = p->s[1].cur();
                 ny_ub = d.nY;
             } else {
@@ -599,19 +627,42 @@ class Engine {
                 d.nX = p->s[0].cur();
                 nx_ub = d.nX;
                 d.YT = p->colT;
+                d.YTt = p->colT + p->colT_cap;
+                d.Yrows = d.out_rows;
                 d.nY = -1;
                 ny_ub = d.C;
             }
-            const int tmax = std::max(1, kMeetTileWords / W);   // LDS holds tpb*64*W words
-            d.tpb = opt.meet_tiles > 0 ? std::min(opt.meet_tiles, tmax) : tmax;
-            d.nXb = ceil_div(nx_ub, kBS);
-            d.nYc = ceil_div(ceil_div(ny_ub, 64), d.tpb);
-            d.ntr_waves = dir == 1 ? ceil_div(d.C, 64) * W : 0;
             d.res = d_res_ + 2 * i;
+            // chunked meet over the sorted forward level when it exists
+            if ((dir == 0 && p->sort_now) || (dir == 1 && p->xs_valid && opt.meet != 1)) {
+                d.meet_mode = 1;
+                d.X = p->xs_rows;
+                d.Xidx = p->xs_idx;
+                d.Xcom = p->xs_com;
+            }
+            if (dir == 0 && p->sort_now) {
+                S.push_back(SortDesc{p->n, W, d.out_rows, d.res, d.C, p->xs_hist, p->xs_top, p->xs_keys,
+                                     p->xs_bins, p->xs_rows, p->xs_idx, p->xs_com});
+                pz.push_back(pz.back() + ceil_div(kSortBins + p->n, kBS));
+                pr.push_back(pr.back() + ceil_div(d.C, kBS));
+                pch.push_back(pch.back() + ceil_div(ceil_div(d.C, 64), kBS / 64));
+            }
+            if (d.meet_mode == 0) {
+                const int tmax = std::max(1, kMeetTileWords / W);   // LDS holds tpb*64*W words
+                d.tpb = opt.meet_tiles > 0 ? std::min(opt.meet_tiles, tmax) : tmax;
+                d.nXb = ceil_div(nx_ub, kBS);
+                d.nYc = ceil_div(ceil_div(ny_ub, 64), d.tpb);
+                pm[i + 1] = pm[i] + d.nXb * d.nYc;
+            } else {
+                const int64_t ng_ub = ceil_div(ceil_div(ny_ub, 64), 64);   // groups of 64 tiles
+                d.ngi = std::max<int64_t>(1, std::min<int64_t>(8, ng_ub / 4));
+                d.gitems_ub = ceil_div(ng_ub, d.ngi);
+                pm[i + 1] = pm[i] + ceil_div(ceil_div(nx_ub, 64) * d.gitems_ub, kBS / 64);
+            }
+            d.ntr_waves = dir == 1 ? ceil_div(d.C, 64) * W : 0;
             pe[i + 1] = pe[i] + ceil_div(d.C, kBS);
             pc[i + 1] = pc[i] + d.ncblk;
             pt[i + 1] = pt[i] + ceil_div(d.ntr_waves, kBS / 64);
-            pm[i + 1] = pm[i] + d.nXb * d.nYc;
             stats_.candidates += d.C;
             stats_.cand_words += d.C * W;
             stats_.bytes_expand += 8 * W * (d.m + d.C);
@@ -628,14 +679,21 @@ class Engine {
             if (!d_cnt_ || !d_off_) throw HipFailure{hipErrorOutOfMemory, "compaction counters"};
         }
         // upload descriptors + the four block prefixes in one copy
+        const int nsort = (int)S.size();
         const size_t szD = align8(sizeof(StepDesc) * nseg), szP = align8(8 * (nseg + 1));
-        const size_t total = szD + 4 * szP;
+        const size_t szS = align8(sizeof(SortDesc) * nsort), szQ = align8(8 * (nsort + 1));
+        const size_t total = szD + 4 * szP + szS + 3 * szQ;
         char *h = (char *)pin_step_.need(total);
         memcpy(h, D.data(), sizeof(StepDesc) * nseg);
         memcpy(h + szD, pe.data(), 8 * (nseg + 1));
         memcpy(h + szD + szP, pc.data(), 8 * (nseg + 1));
         memcpy(h + szD + 2 * szP, pt.data(), 8 * (nseg + 1));
         memcpy(h + szD + 3 * szP, pm.data(), 8 * (nseg + 1));
+        const size_t oS = szD + 4 * szP;
+        if (nsort) memcpy(h + oS, S.data(), sizeof(SortDesc) * nsort);
+        memcpy(h + oS + szS, pz.data(), 8 * (nsort + 1));
+        memcpy(h + oS + szS + szQ, pr.data(), 8 * (nsort + 1));
+        memcpy(h + oS + szS + 2 * szQ, pch.data(), 8 * (nsort + 1));
         char *dblob = dev_need(step_blob_, step_blob_cap_, total);
         HIPCHK(hipMemcpyAsync(dblob, h, total, hipMemcpyHostToDevice, stream_));
         const StepDesc *dD = (const StepDesc *)dblob;
@@ -643,6 +701,11 @@ class Engine {
         const int64_t *dpc = (const int64_t *)(dblob + szD + szP);
         const int64_t *dpt = (const int64_t *)(dblob + szD + 2 * szP);
         const int64_t *dpm = (const int64_t *)(dblob + szD + 3 * szP);
+        const SortDesc *dS = (const SortDesc *)(dblob + oS);
+        const int64_t *const dsp[3] = {(const int64_t *)(dblob + oS + szS),
+                                       (const int64_t *)(dblob + oS + szS + szQ),
+                                       (const int64_t *)(dblob + oS + szS + 2 * szQ)};
+        const int64_t sblocks[3] = {pz.back(), pr.back(), pch.back()};
 
         prof_begin(0);
         HIPCHK(launch_expand(dD, dpe, nseg, pe[nseg], stream_));
@@ -655,14 +718,20 @@ class Engine {
         HIPCHK(launch_scan(dD, nseg, d_cnt_, d_off_, stream_));
         HIPCHK(launch_compact(dD, dpc, nseg, pc[nseg], d_off_, stream_));
         prof_end(2);
-        if (pt[nseg] > 0) {
+        if (pt[nseg] > 0 || nsort > 0) {
             prof_begin(3);
             HIPCHK(launch_transpose(dD, dpt, nseg, pt[nseg], stream_));
+            HIPCHK(launch_sort(dS, dsp, sblocks, nsort, stream_));
             prof_end(3);
             stats_.launches[3]++;
         }
         prof_begin(4);
-        HIPCHK(launch_meet(dD, dpm, nseg, pm[nseg], stream_));
+        for (int s0 = 0; s0 < nseg;) {
+            int s1 = s0;
+            while (s1 < nseg && segp[s1]->W == segp[s0]->W) ++s1;
+            HIPCHK(launch_meet(dD, dpm, s0, s1, segp[s0]->W, pm[s1] - pm[s0], stream_));
+            s0 = s1;
+        }
         prof_end(4);
         stats_.launches[0]++;
         stats_.launches[1]++;
@@ -685,6 +754,8 @@ class Engine {
             const StepDesc &d = D[i];
             s.nrows += U;
             s.off.push_back(s.nrows);
+            if (dir == 0) p->xs_valid = p->sort_now;
+            p->sort_now = false;
             p->steps++;
             stats_.steps++;
             stats_.unique += U;
@@ -792,10 +863,41 @@ class Engine {
         }
         if (dir == 1) {
             pp = p->colT; cap = p->colT_cap;
-            if (!dev_grow(pp, cap, ceil_div(C, 64) * 64 * W, 8, 0)) return set_error(SRW_ENOMEM, "device budget (tiles)");
+            if (!dev_grow(pp, cap, ceil_div(C, 64) * 64 * W, 16, 0)) return set_error(SRW_ENOMEM, "device budget (tiles)");
             p->colT = (u64 *)pp; p->colT_cap = cap;
         }
+        p->sort_now = false;
+        if (dir == 0 && opt.meet != 1) {
+            const bool want = opt.meet == 2 ||
+                              (C >= kSortMinCand && (double)C * (double)p->s[1].cur() >= kSortMinPairs);
+            if (want) p->sort_now = ensure_sort(p, C);   // no room: the LDS-tile meet serves
+        }
         return 0;
+    }
+
+    bool ensure_sort(Problem *p, int64_t rows) {
+        const int W = p->W;
+        if (!p->xs_bins) {
+            p->xs_bins = (u32 *)pool_->alloc((size_t)kSortBins * 4);
+            p->xs_hist = (u32 *)pool_->alloc((size_t)kMaxW * 64 * 4);
+            p->xs_top = (int32_t *)pool_->alloc((size_t)kKeyBits * 4);
+            if (!p->xs_bins || !p->xs_hist || !p->xs_top) return false;
+        }
+        if (rows > p->xs_cap) {
+            p->xs_valid = false;
+            pool_->free(p->xs_rows);
+            pool_->free(p->xs_idx);
+            pool_->free(p->xs_keys);
+            pool_->free(p->xs_com);
+            const int64_t nc = std::max(rows, 2 * p->xs_cap);
+            p->xs_rows = (u64 *)pool_->alloc((size_t)nc * W * 8);
+            p->xs_idx = (u32 *)pool_->alloc((size_t)nc * 4);
+            p->xs_keys = (u32 *)pool_->alloc((size_t)nc * 4);
+            p->xs_com = (u64 *)pool_->alloc((size_t)ceil_div(nc, 64) * W * 8);
+            p->xs_cap = (p->xs_rows && p->xs_idx && p->xs_keys && p->xs_com) ? nc : 0;
+            if (!p->xs_cap) return false;
+        }
+        return true;
     }
 
     void trace(std::vector<Problem *> &met, std::vector<u64> &best) {
@@ -871,6 +973,14 @@ class Engine {
         pool_->free(p->colT); p->colT = nullptr; p->colT_cap = 0;
         pool_->free(p->cand); p->cand = nullptr; p->cand_cap = 0;
         pool_->free(p->cslot); p->cslot = nullptr; p->cslot_cap = 0;
+        for (void *q : {(void *)p->xs_rows, (void *)p->xs_com, (void *)p->xs_idx, (void *)p->xs_keys,
+                        (void *)p->xs_hist, (void *)p->xs_bins, (void *)p->xs_top})
+            pool_->free(q);
+        p->xs_rows = p->xs_com = nullptr;
+        p->xs_idx = p->xs_keys = p->xs_hist = p->xs_bins = nullptr;
+        p->xs_top = nullptr;
+        p->xs_cap = 0;
+        p->xs_valid = false;
         stats_.peak_device_bytes = std::max<int64_t>(stats_.peak_device_bytes, pool_->peak());
     }
 
@@ -1081,6 +1191,7 @@ int srw_set_option(const char *key, int64_t v) {
     else if (k == "sched_seed") x.opt.sched_seed = (uint64_t)v;
     else if (k == "meet_tiles") { if (v < 0 || v > kMeetTileWords) return set_error(SRW_EINVAL, "meet_tiles"); x.opt.meet_tiles = (int)v; }
     else if (k == "keep_levels") x.opt.keep_levels = v != 0;
+    else if (k == "meet") { if (v < 0 || v > 2) return set_error(SRW_EINVAL, "meet"); x.opt.meet = (int)v; }
     else return set_error(SRW_EINVAL, "unknown option " + k);
     if (x.eng) x.eng->opt = x.opt;
     return SRW_OK;

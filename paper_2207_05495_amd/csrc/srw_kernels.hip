@@ -298,18 +298,22 @@ __global__ void __launch_bounds__(kBS) k_compact(const StepDesc *descs, const in
 // ------------------------------------------------------------ transpose
 
 // One wave transposes word w of the 64 rows of tile `tile`: lane l ends with
-// column q = 64*w + l, bit j = [state q in row 64*tile + j].
+// column q = 64*w + l, bit j = [state q in row 64*tile + j], stored
+// state-major at YT[q * nt + tile] (nt = number of tiles) and tile-major at
+// YTt[tile * 64W + q].
 __device__ __forceinline__ void transpose_tile(const u64 *rows, int64_t count, int W, u64 *YT,
-                                               int64_t tile, int w) {
+                                               u64 *YTt, int64_t tile, int w) {
     const int lane = threadIdx.x & 63;
     const int64_t j = tile * 64 + lane;
+    const int64_t nt = (count + 63) / 64;
     const u64 v = j < count ? rows[j * W + w] : 0ull;
     u64 col = 0;
     for (int b = 0; b < 64; ++b) {
         const u64 m = __ballot((v >> b) & 1ull);
         if (lane == b) col = m;
     }
-    YT[(tile * W + w) * 64 + lane] = col;
+    YT[(int64_t)(64 * w + lane) * nt + tile] = col;
+    YTt[(tile * W + w) * 64 + lane] = col;
 }
 
 __global__ void __launch_bounds__(kBS) k_transpose(const StepDesc *descs, const int64_t *pre, int nseg) {
@@ -322,7 +326,7 @@ __global__ void __launch_bounds__(kBS) k_transpose(const StepDesc *descs, const 
     const int64_t tile = wv / d.W;
     const int w = (int)(wv - tile * d.W);
     if (tile * 64 >= count) return;
-    transpose_tile(d.out_rows, count, d.W, d.YT, tile, w);
+    transpose_tile(d.out_rows, count, d.W, d.YT, d.YTt, tile, w);
 }
 
 __global__ void __launch_bounds__(kBS) k_transpose_rows(const TransposeDesc *descs, const int64_t *pre,
@@ -334,7 +338,7 @@ __global__ void __launch_bounds__(kBS) k_transpose_rows(const TransposeDesc *des
     const int64_t tiles = (d.count + 63) / 64;
     if (wv >= tiles * d.W) return;
     const int64_t tile = wv / d.W;
-    transpose_tile(d.rows, d.count, d.W, d.YT, tile, (int)(wv - tile * d.W));
+    transpose_tile(d.rows, d.count, d.W, d.YT, d.YTt, tile, (int)(wv - tile * d.W));
 }
 
 // ------------------------------------------------------------------ meet
@@ -350,7 +354,7 @@ __device__ void meet_w(const StepDesc &d, int64_t lb, u64 *cols) {
     const int64_t t1 = min(t0 + (int64_t)d.tpb, tiles);
     if (t0 >= t1 || xb * kBS >= nX) return;  // whole block
     const int64_t nw = (t1 - t0) * 64 * W;
-    const u64 *src = d.YT + t0 * 64 * W;
+    const u64 *src = d.YTt + t0 * 64 * W;            // tiles t0..t1-1, contiguous
     for (int64_t e = tid; e < nw; e += kBS) cols[e] = src[e];
     __syncthreads();
     const int64_t i = xb * kBS + tid;
@@ -383,16 +387,311 @@ __device__ void meet_w(const StepDesc &d, int64_t lb, u64 *cols) {
     }
 }
 
-// Grid-stride over work items (a work item is 256 sets X against up to
-// `tpb` tiles of 64 sets Y): the item count can exceed the grid limit.
-__global__ void __launch_bounds__(kBS) k_meet(const StepDesc *descs, const int64_t *pre, int nseg,
-                                              int64_t items) {
+__device__ __forceinline__ u64 shfl64(u64 v, int src) {
+    const u32 lo = (u32)__shfl((int)(u32)v, src, 64);
+    const u32 hi = (u32)__shfl((int)(u32)(v >> 32), src, 64);
+    return ((u64)hi << 32) | lo;
+}
+
+// Mode 1: one wave per work item = (chunk c of 64 sorted sets X, a range of
+// groups of 64 tiles).  C = the states common to the whole chunk.  A set Y
+// can contain some X of the chunk only if it contains C, so each lane takes
+// one tile of a group and ANDs the columns of (at most kCommonMax states of)
+// C over it: coalesced loads, issued a few at a time without waiting on each
+// other.  The surviving (tile, bit) pairs are the candidate sets Y_j; lane l
+// fetches the row of candidate l into the wave's slice of LDS and every lane
+// checks X minus C against every candidate row.  Candidates go in increasing
+// j, so a lane's first hit is its least j.  When a group has very many
+// candidates (chunks with almost no common state) the remaining states of
+// each X are ANDed over the columns of each surviving tile instead.
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int W>
+__device__ void meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nX = d.nX >= 0 ? d.nX : (int64_t)d.res[0];
+    const int64_t nY = d.nY >= 0 ? d.nY : (int64_t)d.res[0];
+    const int64_t nt = (nY + 63) / 64;
+    const int64_t ngroups = (nt + 63) / 64;
+    const int64_t c = item / d.gitems_ub, gi = item - c * d.gitems_ub;
+    if (c * 64 >= nX) return;                      // whole wave
+    const int64_t g0 = gi * d.ngi;
+    const int64_t g1 = min(g0 + d.ngi, ngroups);
+    if (g0 >= g1) return;                          // whole wave
+    const int64_t is = c * 64 + lane;
+    const bool valid = is < nX;
+    // the first kCommonMax states of C (-1: none); only those are filtered
+    // on, so only those are taken out of each X
+    int cq[kCommonMax];
+    u64 x[W];
+    {
+        u64 cur[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) cur[w] = d.Xcom[c * W + w];
+        u64 used[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) used[w] = cur[w];
+#pragma unroll
+        for (int r = 0; r < kCommonMax; ++r) {
+            int qq = -1;
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                if (qq < 0 && cur[w]) {
+                    qq = 64 * w + lowest_bit(cur[w]);
+                    cur[w] &= cur[w] - 1;
+                }
+            cq[r] = qq;
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+            used[w] &= ~cur[w];                    // states of C left unfiltered stay in x
+            x[w] = valid ? (d.X[is * W + w] & ~used[w]) : 0ull;
+        }
+    }
+    const u32 orig = valid ? d.Xidx[is] : 0xFFFFFFFFu;
+    bool done = !valid || (load_slot(d.res + 1) >> 32) < (u64)orig;
+    u32 *jl = (u32 *)slice;
+    for (int64_t g = g0; g < g1; ++g) {
+        if (__ballot(!done) == 0) break;
+        const int64_t t = g * 64 + lane;
+        const bool tv = t < nt;
+        // rows of tile t that exist (the last tile may be partial)
+        const int64_t rows_left = nY - t * 64;
+        u64 m = !tv ? 0ull : (rows_left >= 64 ? ~0ull : ((1ull << rows_left) - 1ull));
+        // common columns, in rounds of independent loads
+#pragma unroll
+        for (int r0 = 0; r0 < kCommonMax; r0 += kCommonRound) {
+            if (cq[r0] < 0 || __ballot(m != 0) == 0) break;
+            u64 v[kCommonRound];
+#pragma unroll
+            for (int r = 0; r < kCommonRound; ++r)
+                v[r] = (tv && cq[r0 + r] >= 0) ? d.YT[(int64_t)cq[r0 + r] * nt + t] : ~0ull;
+#pragma unroll
+            for (int r = 0; r < kCommonRound; ++r) m &= v[r];
+        }
+        // number the candidates: lane order (tile), then bit order
+        const u32 pc = (u32)__popcll(m);
+        u32 incl = pc;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const u32 o = (u32)__shfl_up((int)incl, off, 64);
+            if (lane >= off) incl += o;
+        }
+        const u32 K = (u32)__shfl((int)incl, 63, 64);
+        if (K == 0) continue;
+        if (K <= kRowBatchMax) {
+            for (u32 base = 0; base < K; base += 64) {
+                wave_sync_lds();                   // the previous batch is read
+                u64 mm = m;
+                for (u32 idx = incl - pc; mm; ++idx) {
+                    const int b = lowest_bit(mm);
+                    mm &= mm - 1;
+                    if (idx >= base && idx < base + 64) jl[idx - base] = (u32)(t * 64 + b);
+                }
+                wave_sync_lds();
+                const u32 cnt = min(64u, K - base);
+                const bool has = (u32)lane < cnt;
+                const u32 jj = has ? jl[lane] : 0u;
+                u64 row[W];
+#pragma unroll
+                for (int w = 0; w < W; ++w) row[w] = has ? d.Yrows[(int64_t)jj * W + w] : 0ull;
+                wave_sync_lds();                   // jl is read: rows go over it
+#pragma unroll
+                for (int w = 0; w < W; ++w) slice[lane * W + w] = row[w];
+                wave_sync_lds();
+                for (u32 cc = 0; cc < cnt; ++cc) {
+                    u64 out = 0;
+#pragma unroll
+                    for (int w = 0; w < W; ++w) out |= x[w] & ~slice[cc * W + w];
+                    const u32 jc = (u32)__shfl((int)jj, (int)cc, 64);
+                    if (!done && out == 0) {
+                        atomicMin(d.res + 1, ((u64)orig << 32) | (u64)jc);
+                        done = true;
+                    }
+                }
+            }
+            continue;
+        }
+        u64 surv = __ballot(m != 0);
+        while (surv) {
+            const int lt = lowest_bit(surv);
+            surv &= surv - 1;
+            const u64 mc = shfl64(m, lt);
+            const int64_t tt = g * 64 + lt;
+            if (__ballot(!done) == 0) break;
+            if (done) continue;
+            u64 M = mc;
+            bool alive = true;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                if (!alive) break;
+                u64 b = x[w];
+                while (b) {
+                    const int q = 64 * w + lowest_bit(b);
+                    b &= b - 1;
+                    M &= d.YT[(int64_t)q * nt + tt];
+                    if (M == 0) { alive = false; break; }
+                }
+            }
+            if (alive) {
+                atomicMin(d.res + 1, ((u64)orig << 32) | (u64)(tt * 64 + lowest_bit(M)));
+                done = true;
+            }
+        }
+    }
+}
+
+// Grid-stride over work items: mode 0 items are blocks (256 sets X against
+// up to `tpb` tiles staged in LDS), mode 1 items are waves (4 per block).
+// The item count can exceed the grid limit.  One launch covers segments
+// s0..s1-1, which all have W words per set (a kernel per width keeps the
+// register count of the narrow widths low).
+template <int W>
+__global__ void __launch_bounds__(kBS) k_meet(const StepDesc *descs, const int64_t *pre, int s0, int s1) {
     __shared__ u64 cols[kMeetTileWords * 64];
+    const int64_t base = pre[s0], items = pre[s1] - base;
     for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
-        const int s = find_seg(pre, nseg, it);
+        const int s = s0 + find_seg(pre + s0, s1 - s0, base + it);
         const StepDesc &d = descs[s];
+        const int64_t li = base + it - pre[s];
         __syncthreads();   // the previous item is done with cols
-        SRW_SWITCH_W(d.W, meet_w<W>(d, it - pre[s], cols));
+        if (d.meet_mode == 0) {
+            meet_w<W>(d, li, cols);
+        } else {
+            const int wave = threadIdx.x >> 6;
+            meet_chunk_w<W>(d, li * (kBS / 64) + wave, cols + wave * 64 * kMaxW);
+        }
+    }
+}
+
+// ------------------------------------------------- sort of forward levels
+
+// zero the state histogram and the key bins
+__global__ void __launch_bounds__(kBS) k_sort_zero(const SortDesc *descs, const int64_t *pre, int nseg) {
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const SortDesc &d = descs[s];
+    const int64_t e = ((int64_t)blockIdx.x - pre[s]) * kBS + threadIdx.x;
+    if (e < kSortBins) d.bins[e] = 0;
+    else if (e < kSortBins + d.n) d.hist[e - kSortBins] = 0;
+}
+
+// how many sets of the level contain each state
+__global__ void __launch_bounds__(kBS) k_sort_hist(const SortDesc *descs, const int64_t *pre, int nseg) {
+    __shared__ u32 h[kMaxW * 64];
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const SortDesc &d = descs[s];
+    const int64_t i = ((int64_t)blockIdx.x - pre[s]) * kBS + threadIdx.x;
+    const int64_t cnt = (int64_t)*d.cnt;
+    for (int q = threadIdx.x; q < kMaxW * 64; q += kBS) h[q] = 0;
+    __syncthreads();
+    if (i < cnt) {
+        for (int w = 0; w < d.W; ++w) {
+            u64 b = d.X[i * d.W + w];
+            while (b) {
+                atomicAdd(&h[64 * w + lowest_bit(b)], 1u);
+                b &= b - 1;
+            }
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < d.n; q += kBS)
+        if (h[q]) atomicAdd(&d.hist[q], h[q]);
+}
+
+// one block per segment: the kKeyBits most frequent states (ties: lower q)
+__global__ void __launch_bounds__(512) k_sort_top(const SortDesc *descs, int nseg) {
+    __shared__ u32 h[kMaxW * 64];
+    if ((int)blockIdx.x >= nseg) return;
+    const SortDesc &d = descs[blockIdx.x];
+    const int q = threadIdx.x;
+    h[q] = q < d.n ? d.hist[q] : 0u;
+    __syncthreads();
+    if (q < kKeyBits && q >= d.n) d.top[q] = -1;
+    if (q >= d.n) return;
+    const u32 c = h[q];
+    int rank = 0;
+    for (int o = 0; o < d.n; ++o) rank += (h[o] > c) || (h[o] == c && o < q);
+    if (rank < kKeyBits) d.top[rank] = q;
+}
+
+__global__ void __launch_bounds__(kBS) k_sort_key(const SortDesc *descs, const int64_t *pre, int nseg) {
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const SortDesc &d = descs[s];
+    const int64_t i = ((int64_t)blockIdx.x - pre[s]) * kBS + threadIdx.x;
+    if (i >= (int64_t)*d.cnt) return;
+    u32 key = 0;
+    for (int r = 0; r < kKeyBits; ++r) {
+        const int q = d.top[r];
+        const u32 bit = q >= 0 ? (u32)((d.X[i * d.W + (q >> 6)] >> (q & 63)) & 1ull) : 0u;
+        key = (key << 1) | bit;
+    }
+    d.keys[i] = key;
+    atomicAdd(&d.bins[key], 1u);
+}
+
+// one block per segment: exclusive scan of the key bins in place
+__global__ void __launch_bounds__(kBS) k_sort_scan(const SortDesc *descs, int nseg) {
+    __shared__ u32 wsum[kBS / 64];
+    if ((int)blockIdx.x >= nseg) return;
+    const SortDesc &d = descs[blockIdx.x];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    u32 running = 0;
+    for (int c0 = 0; c0 < kSortBins; c0 += kBS) {
+        const u32 v = d.bins[c0 + tid];
+        u32 incl = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const u32 o = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += o;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        u32 wpre = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < kBS / 64; ++w) {
+            if (w < wave) wpre += wsum[w];
+            tot += wsum[w];
+        }
+        d.bins[c0 + tid] = running + wpre + incl - v;
+        running += tot;
+        __syncthreads();
+    }
+}
+
+// place every set at its bucket (order inside a bucket is arbitrary: the
+// meet keeps the original ranks, so its answer does not depend on it)
+__global__ void __launch_bounds__(kBS) k_sort_scatter(const SortDesc *descs, const int64_t *pre, int nseg) {
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const SortDesc &d = descs[s];
+    const int64_t i = ((int64_t)blockIdx.x - pre[s]) * kBS + threadIdx.x;
+    if (i >= (int64_t)*d.cnt) return;
+    const u32 pos = atomicAdd(&d.bins[d.keys[i]], 1u);
+    for (int w = 0; w < d.W; ++w) d.xs_rows[(int64_t)pos * d.W + w] = d.X[i * d.W + w];
+    d.xs_idx[pos] = (u32)i;
+}
+
+// AND of the 64 sorted sets of each chunk (one wave per chunk)
+__global__ void __launch_bounds__(kBS) k_sort_chunk(const SortDesc *descs, const int64_t *pre, int nseg) {
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const SortDesc &d = descs[s];
+    const int64_t c = ((int64_t)blockIdx.x - pre[s]) * (kBS / 64) + (threadIdx.x >> 6);
+    const int64_t cnt = (int64_t)*d.cnt;
+    if (c * 64 >= cnt) return;                     // whole wave
+    const int lane = threadIdx.x & 63;
+    const int64_t i = c * 64 + lane;
+    for (int w = 0; w < d.W; ++w) {
+        u64 v = i < cnt ? d.xs_rows[i * d.W + w] : ~0ull;
+        u32 lo = (u32)v, hi = (u32)(v >> 32);
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            lo &= (u32)__shfl_xor((int)lo, off, 64);
+            hi &= (u32)__shfl_xor((int)hi, off, 64);
+        }
+        if (lane == 0) d.xs_common[c * d.W + w] = ((u64)hi << 32) | lo;
     }
 }
 
@@ -514,12 +813,30 @@ hipError_t launch_transpose_rows(const TransposeDesc *d, const int64_t *pre, int
     hipLaunchKernelGGL(k_transpose_rows, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
     return launch_checked();
 }
-hipError_t launch_meet(const StepDesc *d, const int64_t *pre, int nseg, int64_t items, hipStream_t st) {
+// segments s0..s1-1 all have width W; `items` = pre[s1] - pre[s0]
+hipError_t launch_meet(const StepDesc *d, const int64_t *pre, int s0, int s1, int W, int64_t items,
+                       hipStream_t st) {
     if (items <= 0) return hipSuccess;
-    const int64_t grid = items < kMeetMaxGrid ? items : kMeetMaxGrid;
-    hipLaunchKernelGGL(k_meet, dim3((unsigned)grid), dim3(kBS), 0, st, d, pre, nseg, items);
+    const unsigned grid = (unsigned)(items < kMeetMaxGrid ? items : kMeetMaxGrid);
+    SRW_SWITCH_W(W, hipLaunchKernelGGL(k_meet<W>, dim3(grid), dim3(kBS), 0, st, d, pre, s0, s1));
     return launch_checked();
 }
+// sort pipeline: pre[0..4] are the block prefixes of zero, hist (= key =
+// scatter, rows), chunk; the top and scan kernels take one block per segment
+hipError_t launch_sort(const SortDesc *d, const int64_t *const pre[3], const int64_t blocks[3], int nseg,
+                       hipStream_t st) {
+    if (nseg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sort_zero, dim3((unsigned)blocks[0]), dim3(kBS), 0, st, d, pre[0], nseg);
+    hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)blocks[1]), dim3(kBS), 0, st, d, pre[1], nseg);
+    hipLaunchKernelGGL(k_sort_top, dim3((unsigned)nseg), dim3(512), 0, st, d, nseg);
+    hipLaunchKernelGGL(k_sort_key, dim3((unsigned)blocks[1]), dim3(kBS), 0, st, d, pre[1], nseg);
+    hipLaunchKernelGGL(k_sort_scan, dim3((unsigned)nseg), dim3(kBS), 0, st, d, nseg);
+    hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)blocks[1]), dim3(kBS), 0, st, d, pre[1], nseg);
+    if (blocks[2] > 0)
+        hipLaunchKernelGGL(k_sort_chunk, dim3((unsigned)blocks[2]), dim3(kBS), 0, st, d, pre[2], nseg);
+    return launch_checked();
+}
+
 hipError_t launch_init(const InitDesc *d, const int64_t *pre, int nseg, int64_t blocks, hipStream_t st) {
     if (blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_init, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);

@@ -30,7 +30,7 @@ EXPORTS = ("srw_solve", "srw_solve_batch", "srw_check_sync", "srw_verify",
            "srw_set_stream", "srw_set_option", "srw_get_stats", "srw_reset_stats",
            "srw_last_levels", "srw_last_error")
 
-KERNEL_CLASSES = ("expand", "insert", "compact", "transpose", "meet", "trace", "setup", "step")
+KERNEL_CLASSES = ("expand", "insert", "compact", "prep", "meet", "trace", "setup", "step")
 
 
 class SrwError(RuntimeError):
@@ -86,6 +86,14 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it first (python -c "
                           "'import __graft_entry__ as g; g.build()')")
+    # PyTorch-ROCm ships its own HIP runtime.  Importing torch first (this
+    # does not initialise the GPU) lets libsrw bind to that runtime instead of
+    # loading a second one from /opt/rocm: with two HSA runtimes in a process
+    # the one initialised second finds no device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(path)
     L.srw_solve.argtypes = [ctypes.c_int32, ctypes.c_int32, i32p, i32p, u8p, ctypes.c_int64]
     L.srw_solve_batch.argtypes = [ctypes.c_int32, i32p, i32p, i64p, i32p, i32p, i32p,

@@ -34,6 +34,15 @@ def test_header_lists_the_binding_exports():
     assert declared_symbols() == sorted(srw.EXPORTS)
 
 
+def test_one_hip_runtime_in_process():
+    """The binding loads libsrw after torch, so the process maps a single
+    HIP runtime (two HSA runtimes in one process leave the second one without
+    a device)."""
+    srw.load()
+    maps = {line.split()[-1] for line in open("/proc/self/maps") if "libamdhip64" in line}
+    assert len(maps) == 1, maps
+
+
 def test_library_exports_every_declared_symbol():
     lib = srw.load()
     for name in declared_symbols():

@@ -25,11 +25,15 @@ def gpu():
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     torch.cuda.set_device(0)
     srw.use_torch(0)
-    for key, v in (("schedule", 0), ("meet_tiles", 0), ("keep_levels", 0), ("budget", 0)):
+    for key, v in DEFAULTS:
         srw.set_option(key, v)
     yield
-    for key, v in (("schedule", 0), ("meet_tiles", 0), ("keep_levels", 0), ("budget", 0)):
+    for key, v in DEFAULTS:
         srw.set_option(key, v)
+
+
+DEFAULTS = (("schedule", 0), ("meet_tiles", 0), ("keep_levels", 0), ("budget", 0), ("meet", 0),
+            ("max_slots", 4096))
 
 
 def say(*a):
@@ -156,6 +160,65 @@ def test_meet_tile_shape_invariance(tiles):
         srw.set_option("meet_tiles", 0)
 
 
+@pytest.mark.parametrize("mode", [1, 2])
+def test_meet_modes_agree(mode):
+    """Mode 1 tests every X against LDS tiles; mode 2 bucket-sorts every
+    forward level and tests 64-set chunks (including tiny levels and chunks
+    with no common state).  Both must reproduce the oracle."""
+    cases = [(64, 2), (150, 2), (200, 3), (129, 2), (40, 4), (255, 2), (90, 3)]
+    srw.set_option("meet", mode)
+    try:
+        for j, (n, k) in enumerate(cases):
+            d = rand_sync(n, k, j, base=61)
+            say("meet mode", mode, n, k)
+            assert srw.solve(n, k, d) == O.bidir(n, k, d)[:2]
+        for n in (5, 17, 33):
+            assert srw.solve(n, 2, I.cerny(n)) == ((n - 1) ** 2, I.cerny_word(n))
+    finally:
+        srw.set_option("meet", 0)
+
+
+def many_common_states(n, seed):
+    """Letter 0 fixes every state >= 16 and scrambles 0..15; letter 1 is a
+    random map.  Forward sets reached through 0s share dozens of states, so
+    64-set chunks have far more than 8 common states."""
+    rng = np.random.default_rng(seed)
+    a = np.arange(n, dtype=np.int32)
+    a[:16] = rng.integers(0, 16, 16)
+    b = rng.integers(0, n, n).astype(np.int32)
+    return np.concatenate([a, b])
+
+
+@pytest.mark.parametrize("n", [70, 130, 200])
+def test_chunked_meet_with_large_common_sets(n):
+    srw.set_option("meet", 2)
+    try:
+        for s in range(4):
+            d = many_common_states(n, s)
+            if not O.is_synchronizing(n, 2, d):
+                continue
+            say("many common states", n, s)
+            assert srw.solve(n, 2, d) == O.bidir(n, 2, d)[:2]
+    finally:
+        srw.set_option("meet", 0)
+
+
+def test_meet_mode_levels_and_batch():
+    """Forced chunked meet with schedule changes and a batch of mixed sizes."""
+    cases = mixed_cases(30, 2024)
+    want = [O.bidir(n, k, d)[:2] for n, k, d in cases]
+    srw.set_option("meet", 2)
+    srw.set_option("schedule", 1)
+    srw.set_option("sched_seed", 5)
+    try:
+        say("meet mode 2 batch")
+        res = srw.solve_batch(cases)
+        assert [(r, w) for _, r, w in res] == want
+    finally:
+        srw.set_option("meet", 0)
+        srw.set_option("schedule", 0)
+
+
 def test_relabel_invariance():
     n, k = 120, 2
     d = rand_sync(n, k, 9, base=17)
@@ -278,6 +341,19 @@ def test_config2_n256_against_stored_oracle_values():
         r, w = srw.solve(n, k, d)
         assert r == c["r"]
         assert "".join(map(str, w)) == c["word"]
+
+
+def test_config2_lds_tile_meet_equals_stored():
+    cs = golden("config2.json")[:2]
+    srw.set_option("meet", 1)
+    try:
+        for c in cs:
+            d = I.random_automaton(c["n"], c["k"], c["seed"], c["attempt"])
+            say("config2 lds-tile meet seed", c["seed"])
+            r, w = srw.solve(c["n"], c["k"], d)
+            assert r == c["r"] and "".join(map(str, w)) == c["word"]
+    finally:
+        srw.set_option("meet", 0)
 
 
 def test_config2_batched_equals_stored():

@@ -36,9 +36,16 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 CLASSES = ("expand", "insert", "compact", "prep", "meet", "trace", "setup")
 
 
-def workload(name, srw):
+def workload(name, srw, count=None, nmax=None):
     """List of (n, k, delta, label)."""
     out = []
+    if name == "config3":
+        # the seeded 4096-member batch: n uniform in [32, 320], k in {2, 3};
+        # optionally only its first `count` members and those with n <= nmax
+        for m in I.config_mixed(count or 4096, 32, 320, (2, 3), srw.check_sync):
+            if nmax is None or m["n"] <= nmax:
+                out.append((m["n"], m["k"], m["delta"], f"mix{m['n']}k{m['k']}"))
+        return out
     if name == "config2":
         for i in range(10):
             d, _ = I.first_synchronizing(256, 2, I.member_seed(I.BASE_SEED, i), srw.check_sync)
@@ -144,6 +151,99 @@ def class_table(stats):
     return out
 
 
+def serve_requests(count, nmax, kmax, srw, base=I.BASE_SEED ^ 5):
+    """Request mix of the serving workload: 90% random automata (n uniform in
+    [64, nmax], k uniform in 2..kmax), 10% Černý C_n with n uniform in [8, 40]."""
+    rng = np.random.default_rng(base & 0xFFFFFFFF)
+    out = []
+    for i in range(count):
+        if rng.random() < 0.1:
+            n = int(rng.integers(8, 41))
+            out.append((n, 2, I.cerny(n), "cerny"))
+        else:
+            n = int(rng.integers(64, nmax + 1))
+            k = int(rng.integers(2, kmax + 1))
+            d, _ = I.first_synchronizing(n, k, I.member_seed(base, i), srw.check_sync)
+            out.append((n, k, d, f"k{k}" + ("big" if n > 300 else "")))
+    return out
+
+
+def serve_bench(args, srw):
+    """Poisson arrivals into one srw_server (continuous batching): latency
+    percentiles and completed solves per second."""
+    reqs = serve_requests(args.requests, args.serve_nmax, args.serve_kmax, srw)
+    rng = np.random.default_rng(7)
+    last = [time.perf_counter()]
+
+    def progress(msg):
+        if time.perf_counter() - last[0] > 10:
+            last[0] = time.perf_counter()
+            print(msg, file=sys.stderr, flush=True)
+
+    rate = args.rate
+    if rate <= 0:
+        # capacity: a closed-loop pass of the first 64 requests
+        m = min(64, len(reqs))
+        with srw.Server(deadline_ms=args.deadline_ms) as s:
+            t = time.perf_counter()
+            for i, (n, k, d, _) in enumerate(reqs[:m]):
+                s.submit(n, k, d, i)
+            got = 0
+            while got < m and time.perf_counter() - t < args.serve_seconds:
+                got += len(s.poll(100000))
+                progress(f"capacity pass: {got}/{m} done")
+            cap = got / (time.perf_counter() - t)
+        rate = 0.7 * cap
+        print(f"capacity ~{cap:.2f}/s; arrival rate {rate:.2f}/s", file=sys.stderr, flush=True)
+    gaps = rng.exponential(1.0 / rate, size=len(reqs))
+    done = {}
+    with srw.Server(deadline_ms=args.deadline_ms) as s:
+        t0 = time.perf_counter()
+        nxt = t0
+        for i, (n, k, d, _) in enumerate(reqs):
+            nxt += gaps[i]
+            while True:
+                for x in s.poll(0):
+                    done[x["tag"]] = x
+                progress(f"submitted {i}/{len(reqs)}, completed {len(done)}")
+                if time.perf_counter() >= nxt:
+                    break
+                time.sleep(min(0.002, max(0.0, nxt - time.perf_counter())))
+            s.submit(n, k, d, i)
+        t_sub = time.perf_counter()
+        while len(done) < len(reqs) and time.perf_counter() - t_sub < args.serve_seconds:
+            for x in s.poll(100000):
+                done[x["tag"]] = x
+            progress(f"all submitted, completed {len(done)}/{len(reqs)}")
+        elapsed = time.perf_counter() - t0
+        pending = s.pending()
+    ok = [x for x in done.values() if x["status"] == srw.OK]
+    lat = np.array([x["latency_ms"] for x in ok]) if ok else np.zeros(1)
+    per = {}
+    for cls in sorted({r[3] for r in reqs}):
+        ls = [done[i]["latency_ms"] for i, r in enumerate(reqs) if r[3] == cls and i in done
+              and done[i]["status"] == srw.OK]
+        if ls:
+            per[cls] = {"n": len(ls), "p50_ms": float(np.percentile(ls, 50)),
+                        "p99_ms": float(np.percentile(ls, 99))}
+    return {
+        "metric": "subsets expanded/s + automata solved/s (batched vs plain, 1 GPU), p99 latency",
+        "value": len(ok) / elapsed, "unit": "automata solved/s",
+        "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": elapsed * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "config5", "requests": len(reqs), "rate_per_s": rate,
+                   "mix": f"90% random n~U[64,{args.serve_nmax}] k~U{{2..{args.serve_kmax}}}, "
+                          "10% Cerny n~U[8,40]", "path": "srw_server (continuous batching)"},
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "completed": len(ok), "failed": len(done) - len(ok), "unfinished": int(pending),
+        "status_counts": {srw.STATUS_NAMES.get(st, st): sum(1 for x in done.values() if x["status"] == st)
+                          for st in sorted({x["status"] for x in done.values()})},
+        "deadline_ms": args.deadline_ms,
+        "per_class": per,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +256,19 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--oracle-one", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--count", type=int, default=None,
+                    help="config3: first COUNT members of the seeded 4096-member batch")
+    ap.add_argument("--nmax", type=int, default=None,
+                    help="config3: keep only members with n <= NMAX")
+    ap.add_argument("--requests", type=int, default=400, help="config5: requests")
+    ap.add_argument("--deadline-ms", type=int, default=20000,
+                    help="config5: per-request deadline on the device (0: none)")
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="config5: Poisson arrivals per second (0: 0.7 x measured capacity)")
+    ap.add_argument("--serve-nmax", type=int, default=400, help="config5: largest random n")
+    ap.add_argument("--serve-kmax", type=int, default=4, help="config5: largest alphabet")
+    ap.add_argument("--serve-seconds", type=float, default=90.0,
+                    help="config5: stop waiting for completions after this long")
     args = ap.parse_args()
     if args.oracle_one:
         oracle_one(args.oracle_one)
@@ -166,7 +279,13 @@ def main():
         sys.exit(2)
 
     from paper_2207_05495_amd import srw
-    probs = workload(args.workload, srw)          # host-only calls so far
+    if args.workload == "config5":
+        import torch
+        torch.cuda.set_device(0)
+        srw.use_torch(0)
+        print(json.dumps(serve_bench(args, srw)))
+        return
+    probs = workload(args.workload, srw, args.count, args.nmax)   # host-only calls so far
     cpu = None if args.no_cpu else cpu_baseline(probs, args.cpu_budget)
 
     import torch
@@ -213,9 +332,13 @@ def main():
         "dtype": "u64", "data": "synthetic",
         "config": {"workload": args.workload,
                    "automata": len(probs),
-                   "sizes": sorted({(n, k) for n, k, _, _ in probs if n > 40})
-                   if args.workload != "config2" else
-                   "10 x random n=256 k=2 (uniform delta, seeded SplitMix64) + Cerny C_16..C_32",
+                   "sizes": {
+                       "config1": "100 x random n=64 k=2",
+                       "config2": "10 x random n=256 k=2 + Cerny C_16..C_32",
+                       "config3": f"first {len(probs)} of the 4096-member batch, "
+                                  "n~U[32,320], k~U{2,3}",
+                       "config4": "1 x random n=450 k=2"}[args.workload]
+                   + " (uniform delta, seeded SplitMix64, first synchronizing draw)",
                    "path": "srw_solve_batch"},
         "automata_per_s": len(probs) / per_step,
         "subsets_per_step": cand,

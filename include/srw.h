@@ -53,7 +53,7 @@ extern "C" {
 #define SRW_ENOMEM (-4)        /* device memory budget exhausted before the searches met */
 #define SRW_EWORDCAP (-5)      /* *r written, the word did not fit word_cap */
 #define SRW_EDEVICE (-6)       /* HIP error or no usable GPU; srw_last_error() has the text */
-#define SRW_ETIMEOUT (-7)      /* srw_server_poll: nothing completed within the timeout */
+#define SRW_ETIMEOUT (-7)      /* srw_server_poll: nothing completed in time; a solve: its deadline passed */
 #define SRW_EINTERNAL (-8)     /* internal check failed (e.g. the word did not verify) */
 
 /* Solve one automaton.  r: out, the reset threshold.  word: out, may be NULL
@@ -87,6 +87,7 @@ typedef struct srw_config {
     int32_t device;        /* HIP device ordinal */
     int32_t max_slots;     /* automata resident on the device at once (0: 4096) */
     int64_t hbm_budget;    /* bytes of device memory the server may hold (0: 80% of free) */
+    int64_t deadline_ms;   /* per request, from admission: SRW_ETIMEOUT after this long (0: none) */
 } srw_config;
 
 typedef struct srw_result {
@@ -139,6 +140,12 @@ int srw_set_stream(void *hip_stream);
  *                 and test 64-set chunks of it (any choice gives the same
  *                 results; auto sorts the large levels)
  *   "meet_tiles"  tiles of 64 inverse sets per LDS meet block (0: auto)
+ *   "meet_rows"   chunked meet: groups of 64 tiles with at most this many
+ *                 candidate sets test rows directly, larger ones AND columns
+ *   "meet_groups" chunked meet: groups of 64 tiles per work item (at most)
+ *   "deadline_ms" per automaton, from its admission: a solve still running
+ *                 after this long ends with SRW_ETIMEOUT (0: no deadline)
+ *   "verbose"     1: one line per step of a single solve on stderr
  *   "keep_levels" 1: keep the device lists of the last srw_solve for
  *                 srw_last_levels
  * Unknown keys give SRW_EINVAL. */

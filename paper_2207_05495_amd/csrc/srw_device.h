@@ -19,10 +19,10 @@ constexpr u32 kDrop = 0xFFFFFFFFu;       // candidate dropped (empty or seen bef
 constexpr int kBS = 256;                 // threads per block (4 wave64)
 constexpr int kCB = 1024;                // candidates per compaction block
 constexpr int kMeetTileWords = 32;       // LDS budget of the meet: tiles*W <= this
-constexpr int64_t kMeetMaxGrid = 65536;  // meet blocks per launch (grid-stride beyond)
+constexpr int64_t kMeetMaxGrid = 0x7fffffff;  // meet blocks per launch (grid-stride beyond)
 constexpr int kCommonMax = 8;            // chunked meet: common states used per chunk
-constexpr int kCommonRound = 2;          // common columns loaded per round
-constexpr int kRowBatchMax = 256;        // candidate rows per group tested directly
+constexpr int kCommonRound = 4;          // common columns loaded per round
+constexpr int kRowBatchMax = 512;        // default: candidate rows per group tested directly
 
 // A hash-slot is 64 bits: high 32 = fingerprint of the set, low 32 = ref.
 // ref < 2^31: id of a stored (visited) row of this side;
@@ -65,6 +65,7 @@ struct StepDesc {
     const u64 *Xcom;           // mode 1: AND of the 64 sets of each chunk
     int64_t gitems_ub;         // mode 1: work items per chunk (upper bound)
     int64_t ngi;               // mode 1: tile groups (of 64 tiles) per item
+    int64_t row_batch_max;     // mode 1: more candidates per group than this: column chains
     // transpose of a new inverse level into YT
     int64_t ntr_waves;         // upper bound of (tile, word) waves
     // results: res[0] = new level size, res[1] = least (i << 32 | j) meeting pair

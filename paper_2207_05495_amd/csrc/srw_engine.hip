@@ -33,10 +33,11 @@ hipError_t launch_scan(const StepDesc *, int, const u32 *, u32 *, hipStream_t);
 hipError_t launch_compact(const StepDesc *, const int64_t *, int, int64_t, const u32 *, hipStream_t);
 hipError_t launch_transpose(const StepDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_transpose_rows(const TransposeDesc *, const int64_t *, int, int64_t, hipStream_t);
-hipError_t launch_meet(const StepDesc *, const int64_t *, int, int, int, int64_t, hipStream_t);
+hipError_t launch_meet(const StepDesc *, const int64_t *, int, int, int, int64_t, int64_t, hipStream_t);
 hipError_t launch_init(const InitDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_rehash(const RehashDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_fill(u64 *, int64_t, u64, hipStream_t);
+hipError_t launch_clear_tables(const RehashDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_trace(const TraceDesc *, int, hipStream_t);
 hipError_t launch_sort(const SortDesc *, const int64_t *const[3], const int64_t[3], int, hipStream_t);
 
@@ -342,9 +343,14 @@ struct Options {
     int schedule = 0;
     uint64_t sched_seed = 1;
     int meet_tiles = 0;
+    int64_t meet_rows = kRowBatchMax;   // chunked meet: row tests up to this many candidates per group
+    int64_t meet_groups = 8;            // chunked meet: tile groups per work item (upper limit)
+    int64_t meet_grid = 0;              // meet blocks per launch (0: one per work item)
     bool profile = false;
     bool keep_levels = false;
+    bool verbose = false;          // one stderr line per step of a single solve
     int64_t max_slots = 4096;
+    double deadline_ms = 0;        // per automaton, from admission (0: none)
 };
 
 static uint64_t mix64(uint64_t z) {
@@ -410,26 +416,36 @@ class Engine {
         std::vector<Problem *> active;
         while (!pending.empty() || !active.empty()) {
             std::vector<Problem *> fresh;
-            while (!pending.empty() && (int64_t)active.size() < opt.max_slots) {
+            // in order; one whose estimated footprint does not fit yet waits
+            // without blocking smaller ones behind it
+            std::deque<Problem *> waiting;
+            while (!pending.empty()) {
                 Problem *p = pending.front();
-                if (!active.empty() && in_use() + p->est_bytes > budget()) break;
                 pending.pop_front();
+                if ((int64_t)active.size() >= opt.max_slots ||
+                    (!active.empty() && in_use() + p->est_bytes > budget())) {
+                    waiting.push_back(p);
+                    continue;
+                }
                 if (admit(p)) {
                     active.push_back(p);
                     fresh.push_back(p);
                 } else if (active.empty()) {
                     finish_error(p, SRW_ENOMEM);
                 } else {
-                    pending.push_front(p);
-                    break;
+                    waiting.push_back(p);
                 }
             }
+            pending.swap(waiting);
             if (!fresh.empty()) init(fresh);
             if (active.empty()) continue;
             step(active);
             std::vector<Problem *> still;
-            for (Problem *p : active)
+            for (Problem *p : active) {
+                if (p->status == 1 && opt.deadline_ms > 0 && now_ms() - p->t_admit > opt.deadline_ms)
+                    finish_error(p, SRW_ETIMEOUT, "deadline passed before the searches met");
                 if (p->status == 1) still.push_back(p);
+            }
             active.swap(still);
         }
     }
@@ -482,10 +498,7 @@ class Engine {
             HIPCHK(hipMemcpyAsync(p->d_delta, hd + o, cnt * 2, hipMemcpyHostToDevice, stream_));
             o += cnt;
         }
-        // fill both tables, write level 0, insert it, transpose inverse level 0
-        for (Problem *p : ps)
-            for (int sd = 0; sd < 2; ++sd)
-                HIPCHK(launch_fill(p->s[sd].tab, p->s[sd].tab_cap, kEmpty, stream_));
+        // clear both tables, write level 0, insert it, transpose inverse level 0
         std::vector<InitDesc> idesc(nseg);
         std::vector<int64_t> ipre(nseg + 1, 0);
         std::vector<RehashDesc> rdesc;
@@ -516,11 +529,27 @@ class Engine {
         const int64_t *dRp = (const int64_t *)b; b += align8(a4);
         const TransposeDesc *dT = (const TransposeDesc *)b; b += align8(a5);
         const int64_t *dTp = (const int64_t *)b;
+        clear_tables(rdesc);
         HIPCHK(launch_init(dI, dIp, nseg, ipre[nseg], stream_));
         HIPCHK(launch_rehash(dR, dRp, (int)rdesc.size(), rpre.back(), stream_));
         HIPCHK(launch_transpose_rows(dT, dTp, nseg, tpre[nseg], stream_));
         prof_end(6);
-        stats_.launches[6] += 3;
+        stats_.launches[6] += 4;
+    }
+
+    // one launch marks every slot of all these tables free
+    void clear_tables(const std::vector<RehashDesc> &t) {
+        std::vector<int64_t> cpre(1, 0);
+        for (const RehashDesc &r : t) cpre.push_back(cpre.back() + ceil_div((int64_t)r.tab_mask + 1, kBS));
+        const size_t a = align8(sizeof(RehashDesc) * t.size()), b = align8(8 * cpre.size());
+        char *h = (char *)pin_clear_.need(a + b);
+        memcpy(h, t.data(), sizeof(RehashDesc) * t.size());
+        memcpy(h + a, cpre.data(), 8 * cpre.size());
+        char *d = dev_need(clear_blob_, clear_blob_cap_, a + b);
+        HIPCHK(hipMemcpyAsync(d, h, a + b, hipMemcpyHostToDevice, stream_));
+        HIPCHK(launch_clear_tables((const RehashDesc *)d, (const int64_t *)(d + a), (int)t.size(),
+                                   cpre.back(), stream_));
+        HIPCHK(hipStreamSynchronize(stream_));   // staging reused by the next clear
     }
 
     // One global step: every active problem expands one side.
@@ -556,7 +585,7 @@ class Engine {
             finish_error(big, SRW_ENOMEM, "device memory budget exhausted before the searches met");
         }
         if (!grow.empty()) {
-            for (auto &g : grow) HIPCHK(launch_fill(g.tab, (int64_t)g.tab_mask + 1, kEmpty, stream_));
+            clear_tables(grow);
             const RehashDesc *dR = (const RehashDesc *)upload_simple(grow, growpre, rehash_blob_);
             const int64_t *dRp = (const int64_t *)((char *)dR + align8(sizeof(RehashDesc) * grow.size()));
             HIPCHK(launch_rehash(dR, dRp, (int)grow.size(), growpre.back(), stream_));
@@ -655,7 +684,8 @@ class Engine {
                 pm[i + 1] = pm[i] + d.nXb * d.nYc;
             } else {
                 const int64_t ng_ub = ceil_div(ceil_div(ny_ub, 64), 64);   // groups of 64 tiles
-                d.ngi = std::max<int64_t>(1, std::min<int64_t>(8, ng_ub / 4));
+                d.ngi = std::max<int64_t>(1, std::min<int64_t>(opt.meet_groups, ng_ub / 4));
+                d.row_batch_max = opt.meet_rows;
                 d.gitems_ub = ceil_div(ng_ub, d.ngi);
                 pm[i + 1] = pm[i] + ceil_div(ceil_div(nx_ub, 64) * d.gitems_ub, kBS / 64);
             }
@@ -729,7 +759,7 @@ class Engine {
         for (int s0 = 0; s0 < nseg;) {
             int s1 = s0;
             while (s1 < nseg && segp[s1]->W == segp[s0]->W) ++s1;
-            HIPCHK(launch_meet(dD, dpm, s0, s1, segp[s0]->W, pm[s1] - pm[s0], stream_));
+            HIPCHK(launch_meet(dD, dpm, s0, s1, segp[s0]->W, pm[s1] - pm[s0], opt.meet_grid, stream_));
             s0 = s1;
         }
         prof_end(4);
@@ -764,6 +794,11 @@ class Engine {
             const int64_t ny = dir == 0 ? d.nY : U;
             stats_.pairs += nx * ny;
             stats_.pair_words += nx * ny * p->W;
+            if (opt.verbose && nseg == 1)
+                fprintf(stderr, "srw step %d %s f=%d b=%d cand=%lld new=%lld |X|=%lld |Y|=%lld meet=%s %.1f ms\n",
+                        p->steps, dir ? "inv" : "fwd", p->s[0].nlev() - 1, p->s[1].nlev() - 1,
+                        (long long)d.C, (long long)U, (long long)nx, (long long)ny,
+                        d.meet_mode ? "chunks" : "tiles", now_ms() - t0);
             if (best != kEmpty) {
                 met.push_back(p);
                 metbest.push_back(best);
@@ -1056,9 +1091,11 @@ class Engine {
     std::unique_ptr<Pool> pool_;
     hipEvent_t ev_[16];
     bool prof_used_[8] = {};
-    Pinned pin_delta_, pin_step_, pin_res_, pin_trace_, pin_init_, pin_misc_;
-    void *step_blob_ = nullptr, *trace_blob_ = nullptr, *init_blob_ = nullptr, *rehash_blob_ = nullptr;
-    int64_t step_blob_cap_ = 0, trace_blob_cap_ = 0, init_blob_cap_ = 0, misc_blob_cap_ = 0;
+    Pinned pin_delta_, pin_step_, pin_res_, pin_trace_, pin_init_, pin_misc_, pin_clear_;
+    void *step_blob_ = nullptr, *trace_blob_ = nullptr, *init_blob_ = nullptr, *rehash_blob_ = nullptr,
+         *clear_blob_ = nullptr;
+    int64_t step_blob_cap_ = 0, trace_blob_cap_ = 0, init_blob_cap_ = 0, misc_blob_cap_ = 0,
+            clear_blob_cap_ = 0;
     u64 *d_res_ = nullptr;
     int64_t res_cap_ = 0;
     u32 *d_cnt_ = nullptr, *d_off_ = nullptr;
@@ -1191,7 +1228,12 @@ int srw_set_option(const char *key, int64_t v) {
     else if (k == "sched_seed") x.opt.sched_seed = (uint64_t)v;
     else if (k == "meet_tiles") { if (v < 0 || v > kMeetTileWords) return set_error(SRW_EINVAL, "meet_tiles"); x.opt.meet_tiles = (int)v; }
     else if (k == "keep_levels") x.opt.keep_levels = v != 0;
+    else if (k == "verbose") x.opt.verbose = v != 0;
+    else if (k == "deadline_ms") { if (v < 0) return set_error(SRW_EINVAL, "deadline_ms"); x.opt.deadline_ms = (double)v; }
     else if (k == "meet") { if (v < 0 || v > 2) return set_error(SRW_EINVAL, "meet"); x.opt.meet = (int)v; }
+    else if (k == "meet_rows") { if (v < 0) return set_error(SRW_EINVAL, "meet_rows"); x.opt.meet_rows = v; }
+    else if (k == "meet_groups") { if (v < 1 || v > 4096) return set_error(SRW_EINVAL, "meet_groups"); x.opt.meet_groups = v; }
+    else if (k == "meet_grid") { if (v < 0) return set_error(SRW_EINVAL, "meet_grid"); x.opt.meet_grid = v; }
     else return set_error(SRW_EINVAL, "unknown option " + k);
     if (x.eng) x.eng->opt = x.opt;
     return SRW_OK;
@@ -1324,57 +1366,89 @@ int srw_last_levels(int32_t side, int32_t *nlev, int64_t *nrows, int64_t *off, u
 
 // ================================================================ serving
 
-struct srw_server {
+// Requests go to one of three lanes by estimated footprint.  Each lane has
+// its own engine, stream and worker thread and batches its requests
+// continuously; a global step of a heavier lane (seconds at large n) never
+// holds up the steps of a lighter one, and the streams share the GPU.
+constexpr int kLanes = 3;
+constexpr int64_t kLaneBytes[kLanes - 1] = {(int64_t)64 << 20, (int64_t)2 << 30};
+constexpr double kLaneShare[kLanes] = {0.10, 0.25, 0.65};   // of the memory budget
+
+static int lane_of(int64_t est) {
+    int li = 0;
+    while (li < kLanes - 1 && est > kLaneBytes[li]) ++li;
+    return li;
+}
+
+struct ServerLane {
     std::unique_ptr<Engine> eng;
     std::thread worker;
+    std::deque<Problem *> inbox;
+};
+
+struct srw_server {
+    ServerLane lane[kLanes];
     std::mutex mu;
     std::condition_variable cv_in, cv_out;
-    std::deque<Problem *> inbox;
     std::deque<Problem *> outbox;
     std::vector<Problem *> returned;   // owned until the next poll
     bool stop = false;
     int64_t submitted = 0, polled = 0;
     int max_slots = 4096;
+    double deadline_ms = 0;
     std::string fatal;
 };
 
-static void server_loop(srw_server *s) {
+static void server_loop(srw_server *s, int li) {
     std::deque<Problem *> pending;
     std::vector<Problem *> active;
+    Engine *eng = s->lane[li].eng.get();
+    std::deque<Problem *> &inbox = s->lane[li].inbox;
     try {
-        HIPCHK(hipSetDevice(s->eng->device()));
+        HIPCHK(hipSetDevice(eng->device()));
         for (;;) {
             {
                 std::unique_lock<std::mutex> lk(s->mu);
                 if (active.empty() && pending.empty())
-                    s->cv_in.wait(lk, [&] { return s->stop || !s->inbox.empty(); });
+                    s->cv_in.wait(lk, [&] { return s->stop || !inbox.empty(); });
                 if (s->stop) break;
-                while (!s->inbox.empty()) {
-                    pending.push_back(s->inbox.front());
-                    s->inbox.pop_front();
+                while (!inbox.empty()) {
+                    pending.push_back(inbox.front());
+                    inbox.pop_front();
                 }
             }
             std::vector<Problem *> fresh;
             std::vector<Problem *> done_now;
-            while (!pending.empty() && (int)active.size() < s->max_slots) {
+            // admit in arrival order; a request whose estimated footprint
+            // does not fit waits without blocking smaller ones behind it
+            std::deque<Problem *> waiting;
+            while (!pending.empty()) {
                 Problem *p = pending.front();
-                if (!active.empty() && s->eng->in_use() + p->est_bytes > s->eng->budget()) break;
                 pending.pop_front();
-                if (s->eng->admit(p)) {
+                if ((int)active.size() >= s->max_slots ||
+                    (!active.empty() && eng->in_use() + p->est_bytes > eng->budget())) {
+                    waiting.push_back(p);
+                    continue;
+                }
+                if (eng->admit(p)) {
                     active.push_back(p);
                     fresh.push_back(p);
                 } else if (active.empty()) {
-                    s->eng->finish_error(p, SRW_ENOMEM);
+                    eng->finish_error(p, SRW_ENOMEM);
                     done_now.push_back(p);
                 } else {
-                    pending.push_front(p);
-                    break;
+                    waiting.push_back(p);
                 }
             }
-            if (!fresh.empty()) s->eng->init(fresh);
-            if (!active.empty()) s->eng->step(active);
+            pending.swap(waiting);
+            if (!fresh.empty()) eng->init(fresh);
+            if (!active.empty()) eng->step(active);
             std::vector<Problem *> still;
-            for (Problem *p : active) (p->status == 1 ? still : done_now).push_back(p);
+            for (Problem *p : active) {
+                if (p->status == 1 && s->deadline_ms > 0 && now_ms() - p->t_admit > s->deadline_ms)
+                    eng->finish_error(p, SRW_ETIMEOUT, "deadline passed before the searches met");
+                (p->status == 1 ? still : done_now).push_back(p);
+            }
             active.swap(still);
             if (!done_now.empty()) {
                 std::lock_guard<std::mutex> lk(s->mu);
@@ -1399,7 +1473,7 @@ extern "C" {
 int srw_server_create(srw_server **out, const srw_config *cfg) {
     if (!out) return set_error(SRW_EINVAL, "out is NULL");
     *out = nullptr;
-    srw_config c{0, 0, 0};
+    srw_config c{0, 0, 0, 0};
     if (cfg) c = *cfg;
     Backing b;
     {
@@ -1415,13 +1489,22 @@ int srw_server_create(srw_server **out, const srw_config *cfg) {
             delete s;
             return set_error(SRW_EDEVICE, "no such HIP device");
         }
-        s->eng.reset(new Engine(c.device, b, c.hbm_budget, nullptr));
+        int64_t total = c.hbm_budget;
+        if (total <= 0) {
+            size_t fr = 0, tot = 0;
+            HIPCHK(hipSetDevice(c.device));
+            HIPCHK(hipMemGetInfo(&fr, &tot));
+            total = (int64_t)(fr * 0.8);
+        }
+        for (int li = 0; li < kLanes; ++li)
+            s->lane[li].eng.reset(new Engine(c.device, b, (int64_t)(total * kLaneShare[li]), nullptr));
     } catch (const HipFailure &f) {
         delete s;
         return device_error(f);
     }
     s->max_slots = c.max_slots > 0 ? c.max_slots : 4096;
-    s->worker = std::thread(server_loop, s);
+    s->deadline_ms = c.deadline_ms > 0 ? (double)c.deadline_ms : 0.0;
+    for (int li = 0; li < kLanes; ++li) s->lane[li].worker = std::thread(server_loop, s, li);
     *out = s;
     return SRW_OK;
 }
@@ -1452,7 +1535,7 @@ int srw_server_submit(srw_server *s, int32_t n, int32_t k, const int32_t *delta,
         s->outbox.push_back(p);
         s->cv_out.notify_all();
     } else {
-        s->inbox.push_back(p);
+        s->lane[lane_of(p->est_bytes)].inbox.push_back(p);
         s->cv_in.notify_all();
     }
     return SRW_OK;
@@ -1496,11 +1579,14 @@ void srw_server_destroy(srw_server *s) {
         s->stop = true;
         s->cv_in.notify_all();
     }
-    if (s->worker.joinable()) s->worker.join();
+    for (int li = 0; li < kLanes; ++li)
+        if (s->lane[li].worker.joinable()) s->lane[li].worker.join();
     for (Problem *p : s->returned) delete p;
     for (Problem *p : s->outbox) delete p;
-    for (Problem *p : s->inbox) delete p;
-    s->eng.reset();
+    for (int li = 0; li < kLanes; ++li) {
+        for (Problem *p : s->lane[li].inbox) delete p;
+        s->lane[li].eng.reset();
+    }
     delete s;
 }
 

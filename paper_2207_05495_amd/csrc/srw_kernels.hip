@@ -27,6 +27,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "srw_device.h"
 
 namespace srw {
@@ -455,6 +457,15 @@ __device__ void meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
     const u32 orig = valid ? d.Xidx[is] : 0xFFFFFFFFu;
     bool done = !valid || (load_slot(d.res + 1) >> 32) < (u64)orig;
     u32 *jl = (u32 *)slice;
+    // first round of common columns of group gg (loaded one group ahead)
+    auto first_round = [&](int64_t gg, u64 *v) {
+        const int64_t tg = gg * 64 + lane;
+#pragma unroll
+        for (int r = 0; r < kCommonRound; ++r)
+            v[r] = (tg < nt && cq[r] >= 0) ? d.YT[(int64_t)cq[r] * nt + tg] : ~0ull;
+    };
+    u64 pre[kCommonRound];
+    first_round(g0, pre);
     for (int64_t g = g0; g < g1; ++g) {
         if (__ballot(!done) == 0) break;
         const int64_t t = g * 64 + lane;
@@ -462,9 +473,12 @@ __device__ void meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
         // rows of tile t that exist (the last tile may be partial)
         const int64_t rows_left = nY - t * 64;
         u64 m = !tv ? 0ull : (rows_left >= 64 ? ~0ull : ((1ull << rows_left) - 1ull));
-        // common columns, in rounds of independent loads
 #pragma unroll
-        for (int r0 = 0; r0 < kCommonMax; r0 += kCommonRound) {
+        for (int r = 0; r < kCommonRound; ++r) m &= pre[r];
+        if (g + 1 < g1) first_round(g + 1, pre);
+        // further common columns, in rounds of independent loads
+#pragma unroll
+        for (int r0 = kCommonRound; r0 < kCommonMax; r0 += kCommonRound) {
             if (cq[r0] < 0 || __ballot(m != 0) == 0) break;
             u64 v[kCommonRound];
 #pragma unroll
@@ -483,7 +497,7 @@ __device__ void meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
         }
         const u32 K = (u32)__shfl((int)incl, 63, 64);
         if (K == 0) continue;
-        if (K <= kRowBatchMax) {
+        if (K <= (u32)d.row_batch_max) {
             for (u32 base = 0; base < K; base += 64) {
                 wave_sync_lds();                   // the previous batch is read
                 u64 mm = m;
@@ -516,6 +530,8 @@ __device__ void meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
             }
             continue;
         }
+        // many candidates: per surviving tile, stage its columns in LDS
+        // (coalesced, tile-major) and AND the remaining states of each X
         u64 surv = __ballot(m != 0);
         while (surv) {
             const int lt = lowest_bit(surv);
@@ -523,6 +539,10 @@ __device__ void meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
             const u64 mc = shfl64(m, lt);
             const int64_t tt = g * 64 + lt;
             if (__ballot(!done) == 0) break;
+            wave_sync_lds();                       // the last tile is read
+#pragma unroll
+            for (int w = 0; w < W; ++w) slice[64 * w + lane] = d.YTt[tt * 64 * W + 64 * w + lane];
+            wave_sync_lds();
             if (done) continue;
             u64 M = mc;
             bool alive = true;
@@ -533,7 +553,7 @@ __device__ void meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
                 while (b) {
                     const int q = 64 * w + lowest_bit(b);
                     b &= b - 1;
-                    M &= d.YT[(int64_t)q * nt + tt];
+                    M &= slice[q];
                     if (M == 0) { alive = false; break; }
                 }
             }
@@ -740,6 +760,14 @@ __global__ void __launch_bounds__(kBS) k_rehash(const RehashDesc *descs, const i
     SRW_SWITCH_W(d.W, rehash_w<W>(d, id));
 }
 
+// mark every slot of each segment's (new) hash table free
+__global__ void __launch_bounds__(kBS) k_clear_tables(const RehashDesc *descs, const int64_t *pre, int nseg) {
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const RehashDesc &d = descs[s];
+    const int64_t e = ((int64_t)blockIdx.x - pre[s]) * kBS + threadIdx.x;
+    if (e <= (int64_t)d.tab_mask) d.tab[e] = kEmpty;
+}
+
 __global__ void __launch_bounds__(kBS) k_fill(u64 *p, int64_t count, u64 v) {
     const int64_t i = (int64_t)blockIdx.x * kBS + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * kBS;
@@ -813,11 +841,14 @@ hipError_t launch_transpose_rows(const TransposeDesc *d, const int64_t *pre, int
     hipLaunchKernelGGL(k_transpose_rows, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
     return launch_checked();
 }
-// segments s0..s1-1 all have width W; `items` = pre[s1] - pre[s0]
+// segments s0..s1-1 all have width W; `items` = pre[s1] - pre[s0].  At most
+// max_grid blocks (each then loops over several items); short-lived blocks
+// let kernels of other streams onto the GPU between them.
 hipError_t launch_meet(const StepDesc *d, const int64_t *pre, int s0, int s1, int W, int64_t items,
-                       hipStream_t st) {
+                       int64_t max_grid, hipStream_t st) {
     if (items <= 0) return hipSuccess;
-    const unsigned grid = (unsigned)(items < kMeetMaxGrid ? items : kMeetMaxGrid);
+    const int64_t cap = max_grid > 0 ? std::min<int64_t>(max_grid, kMeetMaxGrid) : kMeetMaxGrid;
+    const unsigned grid = (unsigned)(items < cap ? items : cap);
     SRW_SWITCH_W(W, hipLaunchKernelGGL(k_meet<W>, dim3(grid), dim3(kBS), 0, st, d, pre, s0, s1));
     return launch_checked();
 }
@@ -847,6 +878,14 @@ hipError_t launch_rehash(const RehashDesc *d, const int64_t *pre, int nseg, int6
     hipLaunchKernelGGL(k_rehash, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
     return launch_checked();
 }
+// pre: block prefix of ceil(capacity / kBS) per table
+hipError_t launch_clear_tables(const RehashDesc *d, const int64_t *pre, int nseg, int64_t blocks,
+                               hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_clear_tables, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
+    return launch_checked();
+}
+
 hipError_t launch_fill(u64 *p, int64_t count, u64 v, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     int64_t blocks = (count + kBS - 1) / kBS;

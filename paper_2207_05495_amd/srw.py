@@ -57,7 +57,7 @@ class Stats(ctypes.Structure):
 
 class Config(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_slots", ctypes.c_int32),
-                ("hbm_budget", ctypes.c_int64)]
+                ("hbm_budget", ctypes.c_int64), ("deadline_ms", ctypes.c_int64)]
 
 
 class Result(ctypes.Structure):
@@ -276,9 +276,9 @@ def last_levels(side: int, W: int):
 class Server:
     """Continuous-batching server (srw_server_*)."""
 
-    def __init__(self, device=0, max_slots=0, hbm_budget=0):
+    def __init__(self, device=0, max_slots=0, hbm_budget=0, deadline_ms=0):
         self._h = ctypes.c_void_p(None)
-        cfg = Config(device, max_slots, hbm_budget)
+        cfg = Config(device, max_slots, hbm_budget, deadline_ms)
         rc = load().srw_server_create(ctypes.byref(self._h), ctypes.byref(cfg))
         if rc:
             raise SrwError(rc, "server_create")

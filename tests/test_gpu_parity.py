@@ -33,7 +33,8 @@ def gpu():
 
 
 DEFAULTS = (("schedule", 0), ("meet_tiles", 0), ("keep_levels", 0), ("budget", 0), ("meet", 0),
-            ("max_slots", 4096))
+            ("max_slots", 4096), ("meet_rows", 512), ("meet_groups", 8), ("deadline_ms", 0),
+            ("verbose", 0))
 
 
 def say(*a):
@@ -309,6 +310,36 @@ def test_budget_exhaustion_then_recovery():
     finally:
         srw.set_option("budget", 0)
     assert srw.solve(200, 3, d) == want
+
+
+def test_deadline_then_recovery():
+    """A solve still running after its deadline ends with ETIMEOUT, and the
+    context keeps working."""
+    d = I.cerny(40)
+    srw.set_option("deadline_ms", 1)
+    try:
+        say("deadline")
+        with pytest.raises(srw.SrwError) as e:
+            srw.solve(40, 2, d)
+        assert e.value.code == srw.ETIMEOUT
+    finally:
+        srw.set_option("deadline_ms", 0)
+    assert srw.solve(40, 2, d) == (39 ** 2, I.cerny_word(40))
+
+
+@pytest.mark.parametrize("rows,groups", [(0, 1), (8, 3), (100000, 64)])
+def test_meet_tuning_options_keep_results(rows, groups):
+    cs = [(150, 2, 4), (200, 3, 1), (90, 4, 2)]
+    srw.set_option("meet_rows", rows)
+    srw.set_option("meet_groups", groups)
+    try:
+        for n, k, i in cs:
+            d = rand_sync(n, k, i, base=71)
+            say("meet tuning", rows, groups, n, k)
+            assert srw.solve(n, k, d) == O.bidir(n, k, d)[:2]
+    finally:
+        srw.set_option("meet_rows", 512)
+        srw.set_option("meet_groups", 8)
 
 
 def test_word_cap():

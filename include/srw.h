@@ -143,6 +143,10 @@ int srw_set_stream(void *hip_stream);
  *   "meet_rows"   chunked meet: groups of 64 tiles with at most this many
  *                 candidate sets test rows directly, larger ones AND columns
  *   "meet_groups" chunked meet: groups of 64 tiles per work item (at most)
+ *   "meet_order"  chunked meet work items: 1 chunk-major (default), 0 tile-
+ *                 range-major (consecutive items share one range of tiles)
+ *   "meet_grid"   meet blocks per launch, grid-striding over the work items
+ *                 (0: one block per work item, up to 2^31-1)
  *   "deadline_ms" per automaton, from its admission: a solve still running
  *                 after this long ends with SRW_ETIMEOUT (0: no deadline)
  *   "verbose"     1: one line per step of a single solve on stderr
@@ -166,6 +170,12 @@ typedef struct srw_stats {
     int64_t bytes_insert;      /* algorithmic bytes of the insert kernel */
     int64_t bytes_compact;     /* algorithmic bytes of count+compact */
     int64_t peak_device_bytes; /* device memory held at peak */
+    int64_t meet_launches_w[8];/* meet kernel launches per set width W = index + 1 */
+    double meet_ms_w[8];       /* their time, with "profile" on */
+    int64_t pair_words_w[8];   /* their brute-force pair-word count */
+    int64_t meet_ops_w[8];     /* set operations they performed, in 32-bit lane-ops
+                                  (2 per 64-bit AND, 4 per word of a subset test),
+                                  with "profile" on */
 } srw_stats;
 /* kernel classes: 0 expand, 1 insert, 2 count+scan+compact, 3 meet
  * preparation (transpose of inverse levels, bucket sort of forward levels),

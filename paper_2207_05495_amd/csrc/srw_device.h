@@ -66,6 +66,8 @@ struct StepDesc {
     int64_t gitems_ub;         // mode 1: work items per chunk (upper bound)
     int64_t ngi;               // mode 1: tile groups (of 64 tiles) per item
     int64_t row_batch_max;     // mode 1: more candidates per group than this: column chains
+    int64_t nch_ub;            // mode 1: chunks (upper bound)
+    int64_t item_order;        // mode 1: 0 tile-range-major items, 1 chunk-major
     // transpose of a new inverse level into YT
     int64_t ntr_waves;         // upper bound of (tile, word) waves
     // results: res[0] = new level size, res[1] = least (i << 32 | j) meeting pair

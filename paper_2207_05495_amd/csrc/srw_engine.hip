@@ -33,7 +33,7 @@ hipError_t launch_scan(const StepDesc *, int, const u32 *, u32 *, hipStream_t);
 hipError_t launch_compact(const StepDesc *, const int64_t *, int, int64_t, const u32 *, hipStream_t);
 hipError_t launch_transpose(const StepDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_transpose_rows(const TransposeDesc *, const int64_t *, int, int64_t, hipStream_t);
-hipError_t launch_meet(const StepDesc *, const int64_t *, int, int, int, int64_t, int64_t, hipStream_t);
+hipError_t launch_meet(const StepDesc *, const int64_t *, int, int, int, int64_t, int64_t, u64 *, hipStream_t);
 hipError_t launch_init(const InitDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_rehash(const RehashDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_fill(u64 *, int64_t, u64, hipStream_t);
@@ -346,6 +346,7 @@ struct Options {
     int64_t meet_rows = kRowBatchMax;   // chunked meet: row tests up to this many candidates per group
     int64_t meet_groups = 8;            // chunked meet: tile groups per work item (upper limit)
     int64_t meet_grid = 0;              // meet blocks per launch (0: one per work item)
+    int64_t meet_order = 1;             // chunked meet items: 0 tile-range-major, 1 chunk-major
     bool profile = false;
     bool keep_levels = false;
     bool verbose = false;          // one stderr line per step of a single solve
@@ -382,6 +383,7 @@ class Engine {
         }
         pool_.reset(new Pool(backing_, budget));
         for (int c = 0; c < 16; ++c) HIPCHK(hipEventCreate(&ev_[c]));
+        for (int c = 0; c < 2 * kMaxW; ++c) HIPCHK(hipEventCreate(&ev_meet_[c]));
         memset(&stats_, 0, sizeof stats_);
     }
     ~Engine() {
@@ -390,6 +392,7 @@ class Engine {
         release_kept();
         pool_.reset();
         for (int c = 0; c < 16; ++c) (void)hipEventDestroy(ev_[c]);
+        for (int c = 0; c < 2 * kMaxW; ++c) (void)hipEventDestroy(ev_meet_[c]);
         if (own_stream_) (void)hipStreamDestroy(own_stream_);
     }
 
@@ -686,6 +689,8 @@ class Engine {
                 const int64_t ng_ub = ceil_div(ceil_div(ny_ub, 64), 64);   // groups of 64 tiles
                 d.ngi = std::max<int64_t>(1, std::min<int64_t>(opt.meet_groups, ng_ub / 4));
                 d.row_batch_max = opt.meet_rows;
+                d.nch_ub = ceil_div(nx_ub, 64);
+                d.item_order = opt.meet_order;
                 d.gitems_ub = ceil_div(ng_ub, d.ngi);
                 pm[i + 1] = pm[i] + ceil_div(ceil_div(nx_ub, 64) * d.gitems_ub, kBS / 64);
             }
@@ -756,10 +761,23 @@ class Engine {
             stats_.launches[3]++;
         }
         prof_begin(4);
+        if (opt.profile && !d_ops_) {
+            d_ops_ = (u64 *)pool_->alloc(kMaxW * sizeof(u64));
+            if (!d_ops_) throw HipFailure{hipErrorOutOfMemory, "meet counters"};
+            HIPCHK(launch_fill(d_ops_, kMaxW, 0, stream_));
+        }
         for (int s0 = 0; s0 < nseg;) {
             int s1 = s0;
-            while (s1 < nseg && segp[s1]->W == segp[s0]->W) ++s1;
-            HIPCHK(launch_meet(dD, dpm, s0, s1, segp[s0]->W, pm[s1] - pm[s0], opt.meet_grid, stream_));
+            const int W = segp[s0]->W;
+            while (s1 < nseg && segp[s1]->W == W) ++s1;
+            if (opt.profile) {
+                HIPCHK(hipEventRecord(ev_meet_[2 * (W - 1)], stream_));
+                meet_used_[W - 1] = true;
+            }
+            HIPCHK(launch_meet(dD, dpm, s0, s1, W, pm[s1] - pm[s0], opt.meet_grid,
+                               opt.profile ? d_ops_ + (W - 1) : nullptr, stream_));
+            if (opt.profile) HIPCHK(hipEventRecord(ev_meet_[2 * (W - 1) + 1], stream_));
+            stats_.meet_launches_w[W - 1]++;
             s0 = s1;
         }
         prof_end(4);
@@ -794,6 +812,7 @@ class Engine {
             const int64_t ny = dir == 0 ? d.nY : U;
             stats_.pairs += nx * ny;
             stats_.pair_words += nx * ny * p->W;
+            stats_.pair_words_w[p->W - 1] += nx * ny * p->W;
             if (opt.verbose && nseg == 1)
                 fprintf(stderr, "srw step %d %s f=%d b=%d cand=%lld new=%lld |X|=%lld |Y|=%lld meet=%s %.1f ms\n",
                         p->steps, dir ? "inv" : "fwd", p->s[0].nlev() - 1, p->s[1].nlev() - 1,
@@ -1083,20 +1102,36 @@ class Engine {
             stats_.ms[c] += ms;
             prof_used_[c] = false;
         }
+        for (int w = 0; w < kMaxW; ++w) {
+            if (!meet_used_[w]) continue;
+            float ms = 0;
+            HIPCHK(hipEventSynchronize(ev_meet_[2 * w + 1]));
+            HIPCHK(hipEventElapsedTime(&ms, ev_meet_[2 * w], ev_meet_[2 * w + 1]));
+            stats_.meet_ms_w[w] += ms;
+            meet_used_[w] = false;
+        }
+        if (d_ops_) {
+            u64 *h = (u64 *)pin_misc_.need(kMaxW * sizeof(u64));
+            HIPCHK(hipMemcpyAsync(h, d_ops_, kMaxW * sizeof(u64), hipMemcpyDeviceToHost, stream_));
+            HIPCHK(hipStreamSynchronize(stream_));
+            for (int w = 0; w < kMaxW; ++w) stats_.meet_ops_w[w] += (int64_t)h[w];
+            HIPCHK(launch_fill(d_ops_, kMaxW, 0, stream_));
+        }
     }
 
     int device_;
     Backing backing_;
     hipStream_t stream_ = nullptr, own_stream_ = nullptr;
     std::unique_ptr<Pool> pool_;
-    hipEvent_t ev_[16];
+    hipEvent_t ev_[16], ev_meet_[2 * kMaxW];
+    bool meet_used_[kMaxW] = {};
     bool prof_used_[8] = {};
     Pinned pin_delta_, pin_step_, pin_res_, pin_trace_, pin_init_, pin_misc_, pin_clear_;
     void *step_blob_ = nullptr, *trace_blob_ = nullptr, *init_blob_ = nullptr, *rehash_blob_ = nullptr,
          *clear_blob_ = nullptr;
     int64_t step_blob_cap_ = 0, trace_blob_cap_ = 0, init_blob_cap_ = 0, misc_blob_cap_ = 0,
             clear_blob_cap_ = 0;
-    u64 *d_res_ = nullptr;
+    u64 *d_res_ = nullptr, *d_ops_ = nullptr;
     int64_t res_cap_ = 0;
     u32 *d_cnt_ = nullptr, *d_off_ = nullptr;
     int64_t cblk_cap_ = 0;
@@ -1234,6 +1269,7 @@ int srw_set_option(const char *key, int64_t v) {
     else if (k == "meet_rows") { if (v < 0) return set_error(SRW_EINVAL, "meet_rows"); x.opt.meet_rows = v; }
     else if (k == "meet_groups") { if (v < 1 || v > 4096) return set_error(SRW_EINVAL, "meet_groups"); x.opt.meet_groups = v; }
     else if (k == "meet_grid") { if (v < 0) return set_error(SRW_EINVAL, "meet_grid"); x.opt.meet_grid = v; }
+    else if (k == "meet_order") { if (v < 0 || v > 1) return set_error(SRW_EINVAL, "meet_order"); x.opt.meet_order = v; }
     else return set_error(SRW_EINVAL, "unknown option " + k);
     if (x.eng) x.eng->opt = x.opt;
     return SRW_OK;

@@ -346,7 +346,7 @@ __global__ void __launch_bounds__(kBS) k_transpose_rows(const TransposeDesc *des
 // ------------------------------------------------------------------ meet
 
 template <int W>
-__device__ void meet_w(const StepDesc &d, int64_t lb, u64 *cols) {
+__device__ u32 meet_w(const StepDesc &d, int64_t lb, u64 *cols) {
     const int tid = threadIdx.x;
     const int64_t nX = d.nX >= 0 ? d.nX : (int64_t)d.res[0];
     const int64_t nY = d.nY >= 0 ? d.nY : (int64_t)d.res[0];
@@ -354,15 +354,16 @@ __device__ void meet_w(const StepDesc &d, int64_t lb, u64 *cols) {
     const int64_t tiles = (nY + 63) / 64;
     const int64_t t0 = yc * d.tpb;
     const int64_t t1 = min(t0 + (int64_t)d.tpb, tiles);
-    if (t0 >= t1 || xb * kBS >= nX) return;  // whole block
+    if (t0 >= t1 || xb * kBS >= nX) return 0;  // whole block
     const int64_t nw = (t1 - t0) * 64 * W;
     const u64 *src = d.YTt + t0 * 64 * W;            // tiles t0..t1-1, contiguous
     for (int64_t e = tid; e < nw; e += kBS) cols[e] = src[e];
     __syncthreads();
     const int64_t i = xb * kBS + tid;
-    if (i >= nX) return;
+    if (i >= nX) return 0;
     const u64 best = load_slot(d.res + 1);
-    if ((best >> 32) < (u64)i) return;       // a smaller i already met
+    if ((best >> 32) < (u64)i) return 0;     // a smaller i already met
+    u32 nops = 0;                            // 32-bit lane-ops: 2 per 64-bit AND
     u64 x[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) x[w] = d.X[i * W + w];
@@ -378,15 +379,17 @@ __device__ void meet_w(const StepDesc &d, int64_t lb, u64 *cols) {
                 const int b = lowest_bit(bits);
                 bits &= bits - 1;
                 M &= c[64 * w + b];
+                nops += 2;
                 if (M == 0) { alive = false; break; }
             }
         }
         if (alive) {
             const u64 j = (u64)t * 64 + (u64)lowest_bit(M);
             atomicMin(d.res + 1, ((u64)i << 32) | j);
-            return;
+            return nops;
         }
     }
+    return nops;
 }
 
 __device__ __forceinline__ u64 shfl64(u64 v, int src) {
@@ -413,17 +416,21 @@ __device__ __forceinline__ void wave_sync_lds() {
 }
 
 template <int W>
-__device__ void meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
+__device__ u32 meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
     const int lane = threadIdx.x & 63;
     const int64_t nX = d.nX >= 0 ? d.nX : (int64_t)d.res[0];
     const int64_t nY = d.nY >= 0 ? d.nY : (int64_t)d.res[0];
     const int64_t nt = (nY + 63) / 64;
     const int64_t ngroups = (nt + 63) / 64;
-    const int64_t c = item / d.gitems_ub, gi = item - c * d.gitems_ub;
-    if (c * 64 >= nX) return;                      // whole wave
+    // tile-range-major: the items in flight share one range of tiles, so its
+    // columns and rows stay in L2 (every XCD works on the same range)
+    int64_t c, gi;
+    if (d.item_order == 0) { gi = item / d.nch_ub; c = item - gi * d.nch_ub; }
+    else { c = item / d.gitems_ub; gi = item - c * d.gitems_ub; }
+    if (c * 64 >= nX) return 0;                    // whole wave
     const int64_t g0 = gi * d.ngi;
     const int64_t g1 = min(g0 + d.ngi, ngroups);
-    if (g0 >= g1) return;                          // whole wave
+    if (g0 >= g1) return 0;                        // whole wave
     const int64_t is = c * 64 + lane;
     const bool valid = is < nX;
     // the first kCommonMax states of C (-1: none); only those are filtered
@@ -454,6 +461,12 @@ __device__ void meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
             x[w] = valid ? (d.X[is * W + w] & ~used[w]) : 0ull;
         }
     }
+    int nc = 0;                                    // states of C filtered on
+#pragma unroll
+    for (int r = 0; r < kCommonMax; ++r) nc += cq[r] >= 0;
+    // the set operations this lane performs, in 32-bit lane-ops: 2 per
+    // 64-bit AND of a column, 4 per word of a row test (and-not, or)
+    u32 nops = 0;
     const u32 orig = valid ? d.Xidx[is] : 0xFFFFFFFFu;
     bool done = !valid || (load_slot(d.res + 1) >> 32) < (u64)orig;
     u32 *jl = (u32 *)slice;
@@ -475,6 +488,7 @@ __device__ void meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
         u64 m = !tv ? 0ull : (rows_left >= 64 ? ~0ull : ((1ull << rows_left) - 1ull));
 #pragma unroll
         for (int r = 0; r < kCommonRound; ++r) m &= pre[r];
+        if (tv) nops += 2 * min(nc, kCommonRound);
         if (g + 1 < g1) first_round(g + 1, pre);
         // further common columns, in rounds of independent loads
 #pragma unroll
@@ -486,6 +500,7 @@ __device__ void meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
                 v[r] = (tv && cq[r0 + r] >= 0) ? d.YT[(int64_t)cq[r0 + r] * nt + t] : ~0ull;
 #pragma unroll
             for (int r = 0; r < kCommonRound; ++r) m &= v[r];
+            if (tv) nops += 2 * min(nc - r0, kCommonRound);
         }
         // number the candidates: lane order (tile), then bit order
         const u32 pc = (u32)__popcll(m);
@@ -517,6 +532,7 @@ __device__ void meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
 #pragma unroll
                 for (int w = 0; w < W; ++w) slice[lane * W + w] = row[w];
                 wave_sync_lds();
+                if (!done) nops += cnt * 4 * W;
                 for (u32 cc = 0; cc < cnt; ++cc) {
                     u64 out = 0;
 #pragma unroll
@@ -554,6 +570,7 @@ __device__ void meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
                     const int q = 64 * w + lowest_bit(b);
                     b &= b - 1;
                     M &= slice[q];
+                    nops += 2;
                     if (M == 0) { alive = false; break; }
                 }
             }
@@ -563,15 +580,17 @@ __device__ void meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
             }
         }
     }
+    return nops;
 }
 
 // Grid-stride over work items: mode 0 items are blocks (256 sets X against
 // up to `tpb` tiles staged in LDS), mode 1 items are waves (4 per block).
 // The item count can exceed the grid limit.  One launch covers segments
 // s0..s1-1, which all have W words per set (a kernel per width keeps the
-// register count of the narrow widths low).
+// register count of the narrow widths low).  With `ops` set, the set
+// operations the launch performed (32-bit lane-ops) are added to *ops.
 template <int W>
-__global__ void __launch_bounds__(kBS) k_meet(const StepDesc *descs, const int64_t *pre, int s0, int s1) {
+__global__ void __launch_bounds__(kBS) k_meet(const StepDesc *descs, const int64_t *pre, int s0, int s1, u64 *ops) {
     __shared__ u64 cols[kMeetTileWords * 64];
     const int64_t base = pre[s0], items = pre[s1] - base;
     for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
@@ -579,11 +598,18 @@ __global__ void __launch_bounds__(kBS) k_meet(const StepDesc *descs, const int64
         const StepDesc &d = descs[s];
         const int64_t li = base + it - pre[s];
         __syncthreads();   // the previous item is done with cols
+        u32 nops;
         if (d.meet_mode == 0) {
-            meet_w<W>(d, li, cols);
+            nops = meet_w<W>(d, li, cols);
         } else {
             const int wave = threadIdx.x >> 6;
-            meet_chunk_w<W>(d, li * (kBS / 64) + wave, cols + wave * 64 * kMaxW);
+            nops = meet_chunk_w<W>(d, li * (kBS / 64) + wave, cols + wave * 64 * kMaxW);
+        }
+        if (ops) {
+            u32 sum = nops;   // at most a few million per wave and item
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) sum += (u32)__shfl_xor((int)sum, off, 64);
+            if ((threadIdx.x & 63) == 0 && sum) atomicAdd((unsigned long long *)ops, (unsigned long long)sum);
         }
     }
 }
@@ -845,11 +871,11 @@ hipError_t launch_transpose_rows(const TransposeDesc *d, const int64_t *pre, int
 // max_grid blocks (each then loops over several items); short-lived blocks
 // let kernels of other streams onto the GPU between them.
 hipError_t launch_meet(const StepDesc *d, const int64_t *pre, int s0, int s1, int W, int64_t items,
-                       int64_t max_grid, hipStream_t st) {
+                       int64_t max_grid, u64 *ops, hipStream_t st) {
     if (items <= 0) return hipSuccess;
     const int64_t cap = max_grid > 0 ? std::min<int64_t>(max_grid, kMeetMaxGrid) : kMeetMaxGrid;
     const unsigned grid = (unsigned)(items < cap ? items : cap);
-    SRW_SWITCH_W(W, hipLaunchKernelGGL(k_meet<W>, dim3(grid), dim3(kBS), 0, st, d, pre, s0, s1));
+    SRW_SWITCH_W(W, hipLaunchKernelGGL(k_meet<W>, dim3(grid), dim3(kBS), 0, st, d, pre, s0, s1, ops));
     return launch_checked();
 }
 // sort pipeline: pre[0..4] are the block prefixes of zero, hist (= key =

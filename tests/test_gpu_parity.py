@@ -33,8 +33,8 @@ def gpu():
 
 
 DEFAULTS = (("schedule", 0), ("meet_tiles", 0), ("keep_levels", 0), ("budget", 0), ("meet", 0),
-            ("max_slots", 4096), ("meet_rows", 512), ("meet_groups", 8), ("deadline_ms", 0),
-            ("verbose", 0))
+            ("max_slots", 4096), ("meet_rows", 512), ("meet_groups", 8), ("meet_order", 1),
+            ("meet_grid", 0), ("deadline_ms", 0), ("verbose", 0))
 
 
 def say(*a):
@@ -327,19 +327,24 @@ def test_deadline_then_recovery():
     assert srw.solve(40, 2, d) == (39 ** 2, I.cerny_word(40))
 
 
-@pytest.mark.parametrize("rows,groups", [(0, 1), (8, 3), (100000, 64)])
-def test_meet_tuning_options_keep_results(rows, groups):
+@pytest.mark.parametrize("rows,groups,order,grid", [(0, 1, 0, 0), (8, 3, 1, 0), (100000, 64, 0, 7),
+                                                   (512, 8, 1, 65536)])
+def test_meet_tuning_options_keep_results(rows, groups, order, grid):
     cs = [(150, 2, 4), (200, 3, 1), (90, 4, 2)]
     srw.set_option("meet_rows", rows)
     srw.set_option("meet_groups", groups)
+    srw.set_option("meet_order", order)
+    srw.set_option("meet_grid", grid)
     try:
         for n, k, i in cs:
             d = rand_sync(n, k, i, base=71)
-            say("meet tuning", rows, groups, n, k)
+            say("meet tuning", rows, groups, order, grid, n, k)
             assert srw.solve(n, k, d) == O.bidir(n, k, d)[:2]
     finally:
         srw.set_option("meet_rows", 512)
         srw.set_option("meet_groups", 8)
+        srw.set_option("meet_order", 1)
+        srw.set_option("meet_grid", 0)
 
 
 def test_word_cap():
@@ -395,3 +400,23 @@ def test_config2_batched_equals_stored():
     res = srw.solve_batch(probs)
     for c, (st, r, w) in zip(cs, res):
         assert st == srw.OK and r == c["r"] and "".join(map(str, w)) == c["word"]
+
+
+def test_profile_counters_per_width():
+    """With profiling on, the per-width meet counters add up to the totals
+    and the meet reports the set operations it performed."""
+    probs = [(150, 2, rand_sync(150, 2, 0, base=73)), (60, 3, rand_sync(60, 3, 1, base=73))]
+    srw.reset_stats()
+    srw.set_option("profile", 1)
+    try:
+        say("profile counters")
+        res = srw.solve_batch(probs)
+    finally:
+        srw.set_option("profile", 0)
+    assert all(st == srw.OK for st, _, _ in res)
+    st = srw.get_stats()
+    mw = st["meet_w"]
+    assert set(mw) == {1, 3}                       # n=60 -> W=1, n=150 -> W=3
+    assert sum(m["pair_words"] for m in mw.values()) == st["pair_words"]
+    for m in mw.values():
+        assert m["launches"] > 0 and m["ms"] > 0 and m["ops"] > 0

@@ -111,15 +111,76 @@ def cpu_baseline(probs, budget_s):
             "automata_per_s": len(solved) / busy if busy else None}
 
 
+def kernel_short_name(name):
+    """'void srw::k_meet<4>(srw::StepDesc const*, ...)' -> 'k_meet<4>'."""
+    name = name.split("(")[0].strip()
+    if name.startswith("void "):
+        name = name[5:]
+    return name.replace("srw::", "")
+
+
+KERNEL_SRC = os.path.join(ROOT, "paper_2207_05495_amd", "csrc", "srw_kernels.hip")
+
+
+def source_sha1(path=KERNEL_SRC):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()
+
+
+def pmc_summary(fetch_csv, write_csv, workload, out_path, src=KERNEL_SRC):
+    """HBM bytes per launch of every kernel from two rocprofv3 --pmc runs of
+    the same command (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch).  The
+    command first runs three device copies of 256 MiB (--calib-copy-mb 256);
+    each counter is scaled by the bytes one copy moves over what the counter
+    read for it.  The kernel source the counters were taken with is recorded
+    by its SHA-1, so that a later change to it voids the figures."""
+    import csv
+    import collections
+
+    def load(path):
+        d = collections.defaultdict(list)
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                d[kernel_short_name(row["Kernel_Name"])].append(float(row["Counter_Value"]))
+        return d
+    fe, wr = load(fetch_csv), load(write_csv)
+    copy = "__amd_rocclr_copyBuffer"
+    moved = 256.0 * 1024                          # KiB read (and written) by one copy
+    f_fac = moved / (sum(fe[copy][:3]) / 3)
+    w_fac = moved / (sum(wr[copy][:3]) / 3)
+    per = {}
+    print(f"calibration: 256 MiB copy -> FETCH_SIZE {fe[copy][0]:.0f} KiB, WRITE_SIZE "
+          f"{wr[copy][0]:.0f} KiB; factors fetch {f_fac:.3f}, write {w_fac:.3f}")
+    print("| kernel | dispatches | fetch MiB | write MiB | MiB per dispatch |")
+    print("|---|---|---|---|---|")
+    for k in sorted(fe, key=lambda k: -sum(fe[k])):
+        if k == copy:
+            continue
+        n = len(fe[k])
+        F = sum(fe[k]) * f_fac / 1024
+        Wm = sum(wr.get(k, [0.0])) * w_fac / 1024
+        per[k] = (F + Wm) * 2 ** 20 / n
+        print(f"| `{k}` | {n} | {F:.1f} | {Wm:.1f} | {(F + Wm) / n:.2f} |")
+    if out_path:
+        with open(out_path, "w") as f:
+            json.dump({workload: per, "_factors": {"fetch": f_fac, "write": w_fac},
+                       "_kernel_source_sha1": source_sha1(src)}, f, indent=1)
+
+
 def measured_traffic(workload, kernel):
     """HBM bytes per launch of `kernel` on `workload`, from the rocprofv3
     FETCH_SIZE / WRITE_SIZE passes recorded in profiles/hbm_traffic.json
-    (None when no counters were taken for this kernel and workload)."""
+    (None when no counters were taken for this kernel and workload, or when
+    the kernel source changed since)."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
-        return json.load(f).get(workload, {}).get(kernel)
+        rec = json.load(f)
+    if rec.get("_kernel_source_sha1") != source_sha1():
+        return None
+    return rec.get(workload, {}).get(kernel)
 
 
 def roofline(stats, workload):
@@ -278,6 +339,12 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--oracle-one", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
+                    help="summarize rocprofv3 FETCH_SIZE / WRITE_SIZE counter files of a run "
+                         "with --calib-copy-mb 256 and exit (no GPU)")
+    ap.add_argument("--pmc-out", default=None, help="with --pmc-summary: write the JSON here")
+    ap.add_argument("--pmc-src", default=KERNEL_SRC,
+                    help="with --pmc-summary: the kernel source the counters were taken with")
     ap.add_argument("--count", type=int, default=None,
                     help="config3: first COUNT members of the seeded 4096-member batch")
     ap.add_argument("--nmax", type=int, default=None,
@@ -295,9 +362,13 @@ def main():
     if args.oracle_one:
         oracle_one(args.oracle_one)
         return
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.workload, args.pmc_out,
+                    args.pmc_src)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the search of one automaton is not sharded "
-              "across GPUs in this library (see DESIGN.md); run with --gpus 1", file=sys.stderr)
+              "across GPUs in this library; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     from paper_2207_05495_amd import srw

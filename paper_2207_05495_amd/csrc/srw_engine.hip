@@ -399,6 +399,25 @@ class Engine {
     Options opt;
     srw_stats stats_;
 
+    // statistics with the device-side meet counters folded in
+    srw_stats stats() {
+        srw_stats out = stats_;
+        if (d_ops_) {
+            u64 *h = (u64 *)pin_misc_.need(kMaxW * sizeof(u64));
+            HIPCHK(hipMemcpyAsync(h, d_ops_, kMaxW * sizeof(u64), hipMemcpyDeviceToHost, stream_));
+            HIPCHK(hipStreamSynchronize(stream_));
+            for (int w = 0; w < kMaxW; ++w) out.meet_ops_w[w] = (int64_t)h[w];
+        }
+        return out;
+    }
+    void reset_stats() {
+        memset(&stats_, 0, sizeof stats_);
+        if (d_ops_) {
+            HIPCHK(launch_fill(d_ops_, kMaxW, 0, stream_));
+            HIPCHK(hipStreamSynchronize(stream_));
+        }
+    }
+
     void set_budget(int64_t b) {
         if (b <= 0) {
             size_t fr = 0, tot = 0;
@@ -1110,13 +1129,6 @@ class Engine {
             stats_.meet_ms_w[w] += ms;
             meet_used_[w] = false;
         }
-        if (d_ops_) {
-            u64 *h = (u64 *)pin_misc_.need(kMaxW * sizeof(u64));
-            HIPCHK(hipMemcpyAsync(h, d_ops_, kMaxW * sizeof(u64), hipMemcpyDeviceToHost, stream_));
-            HIPCHK(hipStreamSynchronize(stream_));
-            for (int w = 0; w < kMaxW; ++w) stats_.meet_ops_w[w] += (int64_t)h[w];
-            HIPCHK(launch_fill(d_ops_, kMaxW, 0, stream_));
-        }
     }
 
     int device_;
@@ -1279,15 +1291,27 @@ int srw_get_stats(srw_stats *out) {
     if (!out) return set_error(SRW_EINVAL, "out is NULL");
     Context &x = ctx();
     std::lock_guard<std::mutex> g(x.mu);
-    if (x.eng) *out = x.eng->stats_;
-    else memset(out, 0, sizeof *out);
+    if (!x.eng) {
+        memset(out, 0, sizeof *out);
+        return SRW_OK;
+    }
+    try {
+        *out = x.eng->stats();
+    } catch (const HipFailure &e) {
+        return device_error(e);
+    }
     return SRW_OK;
 }
 
 int srw_reset_stats(void) {
     Context &x = ctx();
     std::lock_guard<std::mutex> g(x.mu);
-    if (x.eng) memset(&x.eng->stats_, 0, sizeof x.eng->stats_);
+    if (!x.eng) return SRW_OK;
+    try {
+        x.eng->reset_stats();
+    } catch (const HipFailure &e) {
+        return device_error(e);
+    }
     return SRW_OK;
 }
 

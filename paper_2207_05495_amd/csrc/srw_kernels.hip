@@ -405,7 +405,10 @@ __device__ __forceinline__ u64 shfl64(u64 v, int src) {
 // C over it: coalesced loads, issued a few at a time without waiting on each
 // other.  The surviving (tile, bit) pairs are the candidate sets Y_j; lane l
 // fetches the row of candidate l into the wave's slice of LDS and every lane
-// checks X minus C against every candidate row.  Candidates go in increasing
+// checks X minus C against every candidate row.  For 2..6 words per set the
+// check goes through a one-word signature first: the OR of a set's words,
+// since X subset of Y implies OR(X) subset of OR(Y); only a lane whose
+// signature test passes reads the whole row.  Candidates go in increasing
 // j, so a lane's first hit is its least j.  When a group has very many
 // candidates (chunks with almost no common state) the remaining states of
 // each X are ANDed over the columns of each surviving tile instead.
@@ -470,6 +473,12 @@ __device__ u32 meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
     const u32 orig = valid ? d.Xidx[is] : 0xFFFFFFFFu;
     bool done = !valid || (load_slot(d.res + 1) >> 32) < (u64)orig;
     u32 *jl = (u32 *)slice;
+    // signature layout: jl in words 0..31, signatures in 32..95, rows from 96
+    constexpr bool kSig = W >= 2 && 96 + 64 * W <= 64 * kMaxW;
+    u64 *sig = slice + 32, *srows = slice + 96;
+    u64 xs = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) xs |= x[w];
     // first round of common columns of group gg (loaded one group ahead)
     auto first_round = [&](int64_t gg, u64 *v) {
         const int64_t tg = gg * 64 + lane;
@@ -515,11 +524,13 @@ __device__ u32 meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
         if (K <= (u32)d.row_batch_max) {
             for (u32 base = 0; base < K; base += 64) {
                 wave_sync_lds();                   // the previous batch is read
-                u64 mm = m;
-                for (u32 idx = incl - pc; mm; ++idx) {
-                    const int b = lowest_bit(mm);
-                    mm &= mm - 1;
-                    if (idx >= base && idx < base + 64) jl[idx - base] = (u32)(t * 64 + b);
+                if (incl > base && incl - pc < base + 64) {
+                    u64 mm = m;
+                    for (u32 idx = incl - pc; mm; ++idx) {
+                        const int b = lowest_bit(mm);
+                        mm &= mm - 1;
+                        if (idx >= base && idx < base + 64) jl[idx - base] = (u32)(t * 64 + b);
+                    }
                 }
                 wave_sync_lds();
                 const u32 cnt = min(64u, K - base);
@@ -528,19 +539,51 @@ __device__ u32 meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
                 u64 row[W];
 #pragma unroll
                 for (int w = 0; w < W; ++w) row[w] = has ? d.Yrows[(int64_t)jj * W + w] : 0ull;
-                wave_sync_lds();                   // jl is read: rows go over it
+                if constexpr (kSig) {
+                    u64 f = 0;
 #pragma unroll
-                for (int w = 0; w < W; ++w) slice[lane * W + w] = row[w];
-                wave_sync_lds();
-                if (!done) nops += cnt * 4 * W;
-                for (u32 cc = 0; cc < cnt; ++cc) {
-                    u64 out = 0;
+                    for (int w = 0; w < W; ++w) {
+                        f |= row[w];
+                        srows[lane * W + w] = row[w];
+                    }
+                    sig[lane] = f;                 // 0 past cnt: fails unless X minus C is empty
+                    wave_sync_lds();
+                    if (!done) nops += cnt * 2;
+                    for (u32 c0 = 0; c0 < cnt; c0 += 4) {
+                        bool p = false;
 #pragma unroll
-                    for (int w = 0; w < W; ++w) out |= x[w] & ~slice[cc * W + w];
-                    const u32 jc = (u32)__shfl((int)jj, (int)cc, 64);
-                    if (!done && out == 0) {
-                        atomicMin(d.res + 1, ((u64)orig << 32) | (u64)jc);
-                        done = true;
+                        for (int u = 0; u < 4; ++u) p |= (xs & ~sig[c0 + u]) == 0;
+                        if (p && !done) {
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const u32 cc = c0 + u;
+                                if (done || cc >= cnt || (xs & ~sig[cc]) != 0) continue;
+                                u64 out = 0;
+#pragma unroll
+                                for (int w = 0; w < W; ++w) out |= x[w] & ~srows[cc * W + w];
+                                nops += 4 * W;
+                                if (out == 0) {
+                                    atomicMin(d.res + 1, ((u64)orig << 32) | (u64)jl[cc]);
+                                    done = true;
+                                }
+                            }
+                        }
+                    }
+                } else {
+                    wave_sync_lds();               // jl is read: rows go over it
+#pragma unroll
+                    for (int w = 0; w < W; ++w) slice[lane * W + w] = row[w];
+                    wave_sync_lds();
+                    if (!done) nops += cnt * 4 * W;
+                    for (u32 cc = 0; cc < cnt; ++cc) {
+                        u64 out = 0;
+#pragma unroll
+                        for (int w = 0; w < W; ++w) out |= x[w] & ~slice[cc * W + w];
+                        const u32 jc = (u32)__shfl((int)jj, (int)cc, 64);
+                        if (!done && out == 0) {
+                            atomicMin(d.res + 1, ((u64)orig << 32) | (u64)jc);
+                            done = true;
+                        }
                     }
                 }
             }
@@ -570,9 +613,9 @@ __device__ u32 meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
                     const int q = 64 * w + lowest_bit(b);
                     b &= b - 1;
                     M &= slice[q];
-                    nops += 2;
                     if (M == 0) { alive = false; break; }
                 }
+                nops += 2 * (u32)(__popcll(x[w]) - __popcll(b));
             }
             if (alive) {
                 atomicMin(d.res + 1, ((u64)orig << 32) | (u64)(tt * 64 + lowest_bit(M)));

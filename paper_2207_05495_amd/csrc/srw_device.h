@@ -22,7 +22,12 @@ constexpr int kMeetTileWords = 32;       // LDS budget of the meet: tiles*W <= t
 constexpr int64_t kMeetMaxGrid = 0x7fffffff;  // meet blocks per launch (grid-stride beyond)
 constexpr int kCommonMax = 8;            // chunked meet: common states used per chunk
 constexpr int kCommonRound = 4;          // common columns loaded per round
-constexpr int kRowBatchMax = 512;        // default: candidate rows per group tested directly
+constexpr int kRowBatchMax = 512;        // chunked meet: most candidates per group tested by signature
+// LDS words per wave of the chunked meet: kRowBatchMax candidate indices (u32)
+// and their signatures; also holds one tile of columns (64 * W words)
+constexpr int kSliceWords = kRowBatchMax / 2 + kRowBatchMax;
+constexpr int kMeetLdsWords = kMeetTileWords * 64 > (kBS / 64) * kSliceWords ? kMeetTileWords * 64
+                                                                               : (kBS / 64) * kSliceWords;
 
 // A hash-slot is 64 bits: high 32 = fingerprint of the set, low 32 = ref.
 // ref < 2^31: id of a stored (visited) row of this side;
@@ -57,6 +62,7 @@ struct StepDesc {
     u64 *YT;
     u64 *YTt;
     const u64 *Yrows;          // the inverse level's rows
+    u64 *Ysig;                 // signature of each inverse set: the OR of its W words
     int64_t nY;                // -1: the new level (count in res[0])
     int64_t nXb, nYc;          // mode 0 grid of this segment (upper bounds)
     int32_t tpb;               // mode 0: tiles per meet block
@@ -112,7 +118,7 @@ struct TransposeDesc {
     int32_t W, pad;
     const u64 *rows;
     int64_t count;
-    u64 *YT, *YTt;
+    u64 *YT, *YTt, *Ysig;
 };
 
 struct TraceDesc {

@@ -311,6 +311,8 @@ struct Problem {
     SideState s[2];
     u64 *colT = nullptr;      // current inverse level transposed: colT_cap words state-major, then colT_cap tile-major
     int64_t colT_cap = 0;     // words
+    u64 *ysig = nullptr;      // signature (OR of the words) of each set of the current inverse level
+    int64_t ysig_cap = 0;     // words
     u64 *cand = nullptr;
     int64_t cand_cap = 0;     // rows
     u32 *cslot = nullptr;
@@ -495,6 +497,8 @@ class Engine {
         }
         p->colT_cap = ceil_div(n, 64) * 64 * W;
         p->colT = (u64 *)A((size_t)p->colT_cap * 16);   // state-major, then tile-major
+        p->ysig_cap = ceil_div(n, 64) * 64;
+        p->ysig = (u64 *)A((size_t)p->ysig_cap * 8);
         if (!ok) {
             release(p);
             return false;
@@ -536,7 +540,7 @@ class Engine {
                                            (u64)(p->s[sd].tab_cap - 1)});
                 rpre.push_back(rpre.back() + ceil_div(p->s[sd].nrows, kBS));
             }
-            tdesc[i] = TransposeDesc{p->W, 0, p->s[1].rows, p->n, p->colT, p->colT + p->colT_cap};
+            tdesc[i] = TransposeDesc{p->W, 0, p->s[1].rows, p->n, p->colT, p->colT + p->colT_cap, p->ysig};
             tpre[i + 1] = tpre[i] + ceil_div(ceil_div(p->n, 64) * p->W, kBS / 64);
         }
         prof_begin(6);
@@ -671,6 +675,7 @@ class Engine {
                 d.YT = p->colT;
                 d.YTt = p->colT + p->colT_cap;
                 d.Yrows = p->s[1].rows + p->s[1].cur_start() * W;
+                d.Ysig = p->ysig;
                 d.nY = p->s[1].cur();
                 ny_ub = d.nY;
             } else {
@@ -680,6 +685,7 @@ class Engine {
                 d.YT = p->colT;
                 d.YTt = p->colT + p->colT_cap;
                 d.Yrows = d.out_rows;
+                d.Ysig = p->ysig;
                 d.nY = -1;
                 ny_ub = d.C;
             }
@@ -707,7 +713,7 @@ class Engine {
             } else {
                 const int64_t ng_ub = ceil_div(ceil_div(ny_ub, 64), 64);   // groups of 64 tiles
                 d.ngi = std::max<int64_t>(1, std::min<int64_t>(opt.meet_groups, ng_ub / 4));
-                d.row_batch_max = opt.meet_rows;
+                d.row_batch_max = std::min<int64_t>(opt.meet_rows, kRowBatchMax);
                 d.nch_ub = ceil_div(nx_ub, 64);
                 d.item_order = opt.meet_order;
                 d.gitems_ub = ceil_div(ng_ub, d.ngi);
@@ -938,6 +944,9 @@ class Engine {
             pp = p->colT; cap = p->colT_cap;
             if (!dev_grow(pp, cap, ceil_div(C, 64) * 64 * W, 16, 0)) return set_error(SRW_ENOMEM, "device budget (tiles)");
             p->colT = (u64 *)pp; p->colT_cap = cap;
+            pp = p->ysig; cap = p->ysig_cap;
+            if (!dev_grow(pp, cap, ceil_div(C, 64) * 64, 8, 0)) return set_error(SRW_ENOMEM, "device budget (signatures)");
+            p->ysig = (u64 *)pp; p->ysig_cap = cap;
         }
         p->sort_now = false;
         if (dir == 0 && opt.meet != 1) {
@@ -1044,6 +1053,7 @@ class Engine {
             p->s[sd].cap = p->s[sd].tab_cap = 0;
         }
         pool_->free(p->colT); p->colT = nullptr; p->colT_cap = 0;
+        pool_->free(p->ysig); p->ysig = nullptr; p->ysig_cap = 0;
         pool_->free(p->cand); p->cand = nullptr; p->cand_cap = 0;
         pool_->free(p->cslot); p->cslot = nullptr; p->cslot_cap = 0;
         for (void *q : {(void *)p->xs_rows, (void *)p->xs_com, (void *)p->xs_idx, (void *)p->xs_keys,

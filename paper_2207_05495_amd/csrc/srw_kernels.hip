@@ -35,11 +35,23 @@ namespace srw {
 
 // ---------------------------------------------------------------- helpers
 
+// Descriptors and block prefixes are written by the host before a launch and
+// only read by kernels: they are read through the constant address space, so
+// that their fields become scalar loads (through plain pointers they would be
+// vector loads once a kernel has stored or done an atomic, since the compiler
+// cannot rule out that the store changed them), and the pointers held in them
+// are taken as global ones.
+#define CONST_AS __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ const CONST_AS T &cref(const T *p) {
+    return *(const CONST_AS T *)p;
+}
+
 __device__ __forceinline__ int find_seg(const int64_t *pre, int nseg, int64_t b) {
     int lo = 0, hi = nseg;  // pre[lo] <= b < pre[hi]
     while (hi - lo > 1) {
         int mid = (lo + hi) >> 1;
-        if (pre[mid] <= b) lo = mid; else hi = mid;
+        if (cref(pre + mid) <= b) lo = mid; else hi = mid;
     }
     return lo;
 }
@@ -90,7 +102,7 @@ __device__ __forceinline__ int lowest_bit(u64 v) { return __ffsll((unsigned long
 // gathering one bit of S per state q.  Each thread owns a row of LDS for the
 // bit-addressed side (registers cannot be indexed by a run-time word).
 template <int W>
-__device__ void expand_w(const StepDesc &d, int64_t lb, u64 *lds) {
+__device__ void expand_w(const CONST_AS StepDesc &d, int64_t lb, u64 *lds) {
     const int tid = threadIdx.x;
     const int64_t g = lb * kBS + tid;
     if (g >= d.C) return;
@@ -138,15 +150,15 @@ __device__ void expand_w(const StepDesc &d, int64_t lb, u64 *lds) {
 __global__ void __launch_bounds__(kBS) k_expand(const StepDesc *descs, const int64_t *pre, int nseg) {
     __shared__ u64 lds[kMaxW * kBS];
     const int s = find_seg(pre, nseg, blockIdx.x);
-    const StepDesc &d = descs[s];
-    const int64_t lb = (int64_t)blockIdx.x - pre[s];
+    const CONST_AS StepDesc &d = cref(descs + s);
+    const int64_t lb = (int64_t)blockIdx.x - cref(pre + s);
     SRW_SWITCH_W(d.W, expand_w<W>(d, lb, lds));
 }
 
 // ---------------------------------------------------------------- insert
 
 template <int W>
-__device__ void insert_w(const StepDesc &d, int64_t lb) {
+__device__ void insert_w(const CONST_AS StepDesc &d, int64_t lb) {
     const int64_t g = lb * kBS + threadIdx.x;
     if (g >= d.C) return;
     u64 x[W];
@@ -190,14 +202,14 @@ __device__ void insert_w(const StepDesc &d, int64_t lb) {
 
 __global__ void __launch_bounds__(kBS) k_insert(const StepDesc *descs, const int64_t *pre, int nseg) {
     const int s = find_seg(pre, nseg, blockIdx.x);
-    const StepDesc &d = descs[s];
-    const int64_t lb = (int64_t)blockIdx.x - pre[s];
+    const CONST_AS StepDesc &d = cref(descs + s);
+    const int64_t lb = (int64_t)blockIdx.x - cref(pre + s);
     SRW_SWITCH_W(d.W, insert_w<W>(d, lb));
 }
 
 // ------------------------------------------------------------ compaction
 
-__device__ __forceinline__ bool is_winner(const StepDesc &d, int64_t g) {
+__device__ __forceinline__ bool is_winner(const CONST_AS StepDesc &d, int64_t g) {
     const u32 sl = d.cslot[g];
     if (sl == kDrop) return false;
     return (u32)d.tab[sl] == (kCandBit | (u32)g);
@@ -207,8 +219,8 @@ __global__ void __launch_bounds__(kBS) k_count(const StepDesc *descs, const int6
                                                u32 *blk_cnt) {
     __shared__ u32 wsum[kBS / 64];
     const int s = find_seg(pre, nseg, blockIdx.x);
-    const StepDesc &d = descs[s];
-    const int64_t lb = (int64_t)blockIdx.x - pre[s];
+    const CONST_AS StepDesc &d = cref(descs + s);
+    const int64_t lb = (int64_t)blockIdx.x - cref(pre + s);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     u32 c = 0;
 #pragma unroll
@@ -232,7 +244,7 @@ __global__ void __launch_bounds__(kBS) k_scan(const StepDesc *descs, int nseg, c
     __shared__ u32 wsum[kBS / 64];
     const int s = blockIdx.x;
     if (s >= nseg) return;
-    const StepDesc &d = descs[s];
+    const CONST_AS StepDesc &d = cref(descs + s);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     u64 running = 0;
     for (int64_t c0 = 0; c0 < d.ncblk; c0 += kBS) {
@@ -266,8 +278,8 @@ __global__ void __launch_bounds__(kBS) k_compact(const StepDesc *descs, const in
                                                  const u32 *blk_off) {
     __shared__ u32 wsum[kBS / 64];
     const int s = find_seg(pre, nseg, blockIdx.x);
-    const StepDesc &d = descs[s];
-    const int64_t lb = (int64_t)blockIdx.x - pre[s];
+    const CONST_AS StepDesc &d = cref(descs + s);
+    const int64_t lb = (int64_t)blockIdx.x - cref(pre + s);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int W = d.W;
     u32 rank0 = blk_off[d.cblk_base + lb];
@@ -304,11 +316,16 @@ __global__ void __launch_bounds__(kBS) k_compact(const StepDesc *descs, const in
 // state-major at YT[q * nt + tile] (nt = number of tiles) and tile-major at
 // YTt[tile * 64W + q].
 __device__ __forceinline__ void transpose_tile(const u64 *rows, int64_t count, int W, u64 *YT,
-                                               u64 *YTt, int64_t tile, int w) {
+                                               u64 *YTt, u64 *Ysig, int64_t tile, int w) {
     const int lane = threadIdx.x & 63;
     const int64_t j = tile * 64 + lane;
     const int64_t nt = (count + 63) / 64;
     const u64 v = j < count ? rows[j * W + w] : 0ull;
+    if (w == 0) {                       // the set's signature (0 past the end)
+        u64 f = 0;
+        for (int ww = 0; ww < W; ++ww) f |= j < count ? rows[j * W + ww] : 0ull;
+        Ysig[j] = f;
+    }
     u64 col = 0;
     for (int b = 0; b < 64; ++b) {
         const u64 m = __ballot((v >> b) & 1ull);
@@ -320,33 +337,33 @@ __device__ __forceinline__ void transpose_tile(const u64 *rows, int64_t count, i
 
 __global__ void __launch_bounds__(kBS) k_transpose(const StepDesc *descs, const int64_t *pre, int nseg) {
     const int s = find_seg(pre, nseg, blockIdx.x);
-    const StepDesc &d = descs[s];
-    const int64_t lb = (int64_t)blockIdx.x - pre[s];
+    const CONST_AS StepDesc &d = cref(descs + s);
+    const int64_t lb = (int64_t)blockIdx.x - cref(pre + s);
     const int64_t wv = lb * (kBS / 64) + (threadIdx.x >> 6);
     if (wv >= d.ntr_waves) return;
     const int64_t count = (int64_t)d.res[0];
     const int64_t tile = wv / d.W;
     const int w = (int)(wv - tile * d.W);
     if (tile * 64 >= count) return;
-    transpose_tile(d.out_rows, count, d.W, d.YT, d.YTt, tile, w);
+    transpose_tile(d.out_rows, count, d.W, d.YT, d.YTt, d.Ysig, tile, w);
 }
 
 __global__ void __launch_bounds__(kBS) k_transpose_rows(const TransposeDesc *descs, const int64_t *pre,
                                                         int nseg) {
     const int s = find_seg(pre, nseg, blockIdx.x);
-    const TransposeDesc &d = descs[s];
-    const int64_t lb = (int64_t)blockIdx.x - pre[s];
+    const CONST_AS TransposeDesc &d = cref(descs + s);
+    const int64_t lb = (int64_t)blockIdx.x - cref(pre + s);
     const int64_t wv = lb * (kBS / 64) + (threadIdx.x >> 6);
     const int64_t tiles = (d.count + 63) / 64;
     if (wv >= tiles * d.W) return;
     const int64_t tile = wv / d.W;
-    transpose_tile(d.rows, d.count, d.W, d.YT, d.YTt, tile, (int)(wv - tile * d.W));
+    transpose_tile(d.rows, d.count, d.W, d.YT, d.YTt, d.Ysig, tile, (int)(wv - tile * d.W));
 }
 
 // ------------------------------------------------------------------ meet
 
 template <int W>
-__device__ u32 meet_w(const StepDesc &d, int64_t lb, u64 *cols) {
+__device__ u32 meet_w(const CONST_AS StepDesc &d, int64_t lb, u64 *cols) {
     const int tid = threadIdx.x;
     const int64_t nX = d.nX >= 0 ? d.nX : (int64_t)d.res[0];
     const int64_t nY = d.nY >= 0 ? d.nY : (int64_t)d.res[0];
@@ -403,13 +420,14 @@ __device__ __forceinline__ u64 shfl64(u64 v, int src) {
 // can contain some X of the chunk only if it contains C, so each lane takes
 // one tile of a group and ANDs the columns of (at most kCommonMax states of)
 // C over it: coalesced loads, issued a few at a time without waiting on each
-// other.  The surviving (tile, bit) pairs are the candidate sets Y_j; lane l
-// fetches the row of candidate l into the wave's slice of LDS and every lane
-// checks X minus C against every candidate row.  For 2..6 words per set the
-// check goes through a one-word signature first: the OR of a set's words,
-// since X subset of Y implies OR(X) subset of OR(Y); only a lane whose
-// signature test passes reads the whole row.  Candidates go in increasing
-// j, so a lane's first hit is its least j.  When a group has very many
+// other.  The surviving (tile, bit) pairs are the candidate sets Y_j.  Their
+// indices are listed in the wave's slice of LDS, the one-word signatures of
+// those sets (the OR of a set's words) are gathered next to them in one round
+// of independent loads, and every lane tests X minus C against each
+// signature: X subset of Y implies OR(X) subset of OR(Y), so a failed test
+// rejects exactly; only a lane whose test passes reads the whole row of that
+// Y.  Candidates go in increasing j, so a lane's first hit is its least j.
+// When a group has very many
 // candidates (chunks with almost no common state) the remaining states of
 // each X are ANDed over the columns of each surviving tile instead.
 __device__ __forceinline__ void wave_sync_lds() {
@@ -419,7 +437,7 @@ __device__ __forceinline__ void wave_sync_lds() {
 }
 
 template <int W>
-__device__ u32 meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
+__device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice) {
     const int lane = threadIdx.x & 63;
     const int64_t nX = d.nX >= 0 ? d.nX : (int64_t)d.res[0];
     const int64_t nY = d.nY >= 0 ? d.nY : (int64_t)d.res[0];
@@ -472,10 +490,10 @@ __device__ u32 meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
     u32 nops = 0;
     const u32 orig = valid ? d.Xidx[is] : 0xFFFFFFFFu;
     bool done = !valid || (load_slot(d.res + 1) >> 32) < (u64)orig;
+    // slice: candidate indices (u32) in words 0 .. kRowBatchMax/2-1, their
+    // signatures after them
     u32 *jl = (u32 *)slice;
-    // signature layout: jl in words 0..31, signatures in 32..95, rows from 96
-    constexpr bool kSig = W >= 2 && 96 + 64 * W <= 64 * kMaxW;
-    u64 *sig = slice + 32, *srows = slice + 96;
+    u64 *sig = slice + kRowBatchMax / 2;
     u64 xs = 0;
 #pragma unroll
     for (int w = 0; w < W; ++w) xs |= x[w];
@@ -521,66 +539,46 @@ __device__ u32 meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
         }
         const u32 K = (u32)__shfl((int)incl, 63, 64);
         if (K == 0) continue;
-        if (K <= (u32)d.row_batch_max) {
-            for (u32 base = 0; base < K; base += 64) {
-                wave_sync_lds();                   // the previous batch is read
-                if (incl > base && incl - pc < base + 64) {
-                    u64 mm = m;
-                    for (u32 idx = incl - pc; mm; ++idx) {
-                        const int b = lowest_bit(mm);
-                        mm &= mm - 1;
-                        if (idx >= base && idx < base + 64) jl[idx - base] = (u32)(t * 64 + b);
-                    }
+        if (K <= (u32)d.row_batch_max) {              // row_batch_max <= kRowBatchMax
+            wave_sync_lds();                           // the last group's lists are read
+            {
+                u64 mm = m;
+                for (u32 idx = incl - pc; mm; ++idx) {
+                    jl[idx] = (u32)(t * 64 + lowest_bit(mm));
+                    mm &= mm - 1;
                 }
-                wave_sync_lds();
-                const u32 cnt = min(64u, K - base);
-                const bool has = (u32)lane < cnt;
-                const u32 jj = has ? jl[lane] : 0u;
-                u64 row[W];
+            }
+            wave_sync_lds();
+            for (u32 b0 = 0; b0 < K; b0 += 4 * 64) {   // 4 independent gathers per lane
+                u64 sv[4];
 #pragma unroll
-                for (int w = 0; w < W; ++w) row[w] = has ? d.Yrows[(int64_t)jj * W + w] : 0ull;
-                if constexpr (kSig) {
-                    u64 f = 0;
+                for (int u = 0; u < 4; ++u) {
+                    const u32 idx = b0 + 64 * u + lane;
+                    sv[u] = idx < K ? d.Ysig[jl[idx]] : 0ull;
+                }
 #pragma unroll
-                    for (int w = 0; w < W; ++w) {
-                        f |= row[w];
-                        srows[lane * W + w] = row[w];
-                    }
-                    sig[lane] = f;                 // 0 past cnt: fails unless X minus C is empty
-                    wave_sync_lds();
-                    if (!done) nops += cnt * 2;
-                    for (u32 c0 = 0; c0 < cnt; c0 += 4) {
-                        bool p = false;
+                for (int u = 0; u < 4; ++u) {
+                    const u32 idx = b0 + 64 * u + lane;
+                    if (idx < K) sig[idx] = sv[u];
+                }
+            }
+            wave_sync_lds();
+            if (!done) nops += K * 2;
+            for (u32 c0 = 0; c0 < K; c0 += 4) {
+                bool p = false;
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) p |= (xs & ~sig[c0 + u]) == 0;
-                        if (p && !done) {
+                for (int u = 0; u < 4; ++u) p |= c0 + u < K && (xs & ~sig[c0 + u]) == 0;
+                if (p && !done) {
 #pragma unroll
-                            for (int u = 0; u < 4; ++u) {
-                                const u32 cc = c0 + u;
-                                if (done || cc >= cnt || (xs & ~sig[cc]) != 0) continue;
-                                u64 out = 0;
-#pragma unroll
-                                for (int w = 0; w < W; ++w) out |= x[w] & ~srows[cc * W + w];
-                                nops += 4 * W;
-                                if (out == 0) {
-                                    atomicMin(d.res + 1, ((u64)orig << 32) | (u64)jl[cc]);
-                                    done = true;
-                                }
-                            }
-                        }
-                    }
-                } else {
-                    wave_sync_lds();               // jl is read: rows go over it
-#pragma unroll
-                    for (int w = 0; w < W; ++w) slice[lane * W + w] = row[w];
-                    wave_sync_lds();
-                    if (!done) nops += cnt * 4 * W;
-                    for (u32 cc = 0; cc < cnt; ++cc) {
+                    for (int u = 0; u < 4; ++u) {
+                        const u32 cc = c0 + u;
+                        if (done || cc >= K || (xs & ~sig[cc]) != 0) continue;
+                        const u32 jc = jl[cc];
                         u64 out = 0;
 #pragma unroll
-                        for (int w = 0; w < W; ++w) out |= x[w] & ~slice[cc * W + w];
-                        const u32 jc = (u32)__shfl((int)jj, (int)cc, 64);
-                        if (!done && out == 0) {
+                        for (int w = 0; w < W; ++w) out |= x[w] & ~d.Yrows[(int64_t)jc * W + w];
+                        nops += 4 * W;
+                        if (out == 0) {
                             atomicMin(d.res + 1, ((u64)orig << 32) | (u64)jc);
                             done = true;
                         }
@@ -634,19 +632,19 @@ __device__ u32 meet_chunk_w(const StepDesc &d, int64_t item, u64 *slice) {
 // operations the launch performed (32-bit lane-ops) are added to *ops.
 template <int W>
 __global__ void __launch_bounds__(kBS) k_meet(const StepDesc *descs, const int64_t *pre, int s0, int s1, u64 *ops) {
-    __shared__ u64 cols[kMeetTileWords * 64];
-    const int64_t base = pre[s0], items = pre[s1] - base;
+    __shared__ u64 cols[kMeetLdsWords];
+    const int64_t base = cref(pre + s0), items = cref(pre + s1) - base;
     for (int64_t it = blockIdx.x; it < items; it += gridDim.x) {
         const int s = s0 + find_seg(pre + s0, s1 - s0, base + it);
-        const StepDesc &d = descs[s];
-        const int64_t li = base + it - pre[s];
+        const CONST_AS StepDesc &d = cref(descs + s);
+        const int64_t li = base + it - cref(pre + s);
         __syncthreads();   // the previous item is done with cols
         u32 nops;
         if (d.meet_mode == 0) {
             nops = meet_w<W>(d, li, cols);
         } else {
-            const int wave = threadIdx.x >> 6;
-            nops = meet_chunk_w<W>(d, li * (kBS / 64) + wave, cols + wave * 64 * kMaxW);
+            const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
+            nops = meet_chunk_w<W>(d, li * (kBS / 64) + wave, cols + wave * kSliceWords);
         }
         if (ops) {
             u32 sum = nops;   // at most a few million per wave and item
@@ -662,8 +660,8 @@ __global__ void __launch_bounds__(kBS) k_meet(const StepDesc *descs, const int64
 // zero the state histogram and the key bins
 __global__ void __launch_bounds__(kBS) k_sort_zero(const SortDesc *descs, const int64_t *pre, int nseg) {
     const int s = find_seg(pre, nseg, blockIdx.x);
-    const SortDesc &d = descs[s];
-    const int64_t e = ((int64_t)blockIdx.x - pre[s]) * kBS + threadIdx.x;
+    const CONST_AS SortDesc &d = cref(descs + s);
+    const int64_t e = ((int64_t)blockIdx.x - cref(pre + s)) * kBS + threadIdx.x;
     if (e < kSortBins) d.bins[e] = 0;
     else if (e < kSortBins + d.n) d.hist[e - kSortBins] = 0;
 }
@@ -672,8 +670,8 @@ __global__ void __launch_bounds__(kBS) k_sort_zero(const SortDesc *descs, const 
 __global__ void __launch_bounds__(kBS) k_sort_hist(const SortDesc *descs, const int64_t *pre, int nseg) {
     __shared__ u32 h[kMaxW * 64];
     const int s = find_seg(pre, nseg, blockIdx.x);
-    const SortDesc &d = descs[s];
-    const int64_t i = ((int64_t)blockIdx.x - pre[s]) * kBS + threadIdx.x;
+    const CONST_AS SortDesc &d = cref(descs + s);
+    const int64_t i = ((int64_t)blockIdx.x - cref(pre + s)) * kBS + threadIdx.x;
     const int64_t cnt = (int64_t)*d.cnt;
     for (int q = threadIdx.x; q < kMaxW * 64; q += kBS) h[q] = 0;
     __syncthreads();
@@ -695,7 +693,7 @@ __global__ void __launch_bounds__(kBS) k_sort_hist(const SortDesc *descs, const 
 __global__ void __launch_bounds__(512) k_sort_top(const SortDesc *descs, int nseg) {
     __shared__ u32 h[kMaxW * 64];
     if ((int)blockIdx.x >= nseg) return;
-    const SortDesc &d = descs[blockIdx.x];
+    const CONST_AS SortDesc &d = cref(descs + blockIdx.x);
     const int q = threadIdx.x;
     h[q] = q < d.n ? d.hist[q] : 0u;
     __syncthreads();
@@ -709,8 +707,8 @@ __global__ void __launch_bounds__(512) k_sort_top(const SortDesc *descs, int nse
 
 __global__ void __launch_bounds__(kBS) k_sort_key(const SortDesc *descs, const int64_t *pre, int nseg) {
     const int s = find_seg(pre, nseg, blockIdx.x);
-    const SortDesc &d = descs[s];
-    const int64_t i = ((int64_t)blockIdx.x - pre[s]) * kBS + threadIdx.x;
+    const CONST_AS SortDesc &d = cref(descs + s);
+    const int64_t i = ((int64_t)blockIdx.x - cref(pre + s)) * kBS + threadIdx.x;
     if (i >= (int64_t)*d.cnt) return;
     u32 key = 0;
     for (int r = 0; r < kKeyBits; ++r) {
@@ -726,7 +724,7 @@ __global__ void __launch_bounds__(kBS) k_sort_key(const SortDesc *descs, const i
 __global__ void __launch_bounds__(kBS) k_sort_scan(const SortDesc *descs, int nseg) {
     __shared__ u32 wsum[kBS / 64];
     if ((int)blockIdx.x >= nseg) return;
-    const SortDesc &d = descs[blockIdx.x];
+    const CONST_AS SortDesc &d = cref(descs + blockIdx.x);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     u32 running = 0;
     for (int c0 = 0; c0 < kSortBins; c0 += kBS) {
@@ -755,8 +753,8 @@ __global__ void __launch_bounds__(kBS) k_sort_scan(const SortDesc *descs, int ns
 // meet keeps the original ranks, so its answer does not depend on it)
 __global__ void __launch_bounds__(kBS) k_sort_scatter(const SortDesc *descs, const int64_t *pre, int nseg) {
     const int s = find_seg(pre, nseg, blockIdx.x);
-    const SortDesc &d = descs[s];
-    const int64_t i = ((int64_t)blockIdx.x - pre[s]) * kBS + threadIdx.x;
+    const CONST_AS SortDesc &d = cref(descs + s);
+    const int64_t i = ((int64_t)blockIdx.x - cref(pre + s)) * kBS + threadIdx.x;
     if (i >= (int64_t)*d.cnt) return;
     const u32 pos = atomicAdd(&d.bins[d.keys[i]], 1u);
     for (int w = 0; w < d.W; ++w) d.xs_rows[(int64_t)pos * d.W + w] = d.X[i * d.W + w];
@@ -766,8 +764,8 @@ __global__ void __launch_bounds__(kBS) k_sort_scatter(const SortDesc *descs, con
 // AND of the 64 sorted sets of each chunk (one wave per chunk)
 __global__ void __launch_bounds__(kBS) k_sort_chunk(const SortDesc *descs, const int64_t *pre, int nseg) {
     const int s = find_seg(pre, nseg, blockIdx.x);
-    const SortDesc &d = descs[s];
-    const int64_t c = ((int64_t)blockIdx.x - pre[s]) * (kBS / 64) + (threadIdx.x >> 6);
+    const CONST_AS SortDesc &d = cref(descs + s);
+    const int64_t c = ((int64_t)blockIdx.x - cref(pre + s)) * (kBS / 64) + (threadIdx.x >> 6);
     const int64_t cnt = (int64_t)*d.cnt;
     if (c * 64 >= cnt) return;                     // whole wave
     const int lane = threadIdx.x & 63;
@@ -789,8 +787,8 @@ __global__ void __launch_bounds__(kBS) k_sort_chunk(const SortDesc *descs, const
 // level 0 of both sides: Q forward, the n singletons inverse (Alg. 1 init)
 __global__ void __launch_bounds__(kBS) k_init(const InitDesc *descs, const int64_t *pre, int nseg) {
     const int s = find_seg(pre, nseg, blockIdx.x);
-    const InitDesc &d = descs[s];
-    const int64_t q = ((int64_t)blockIdx.x - pre[s]) * kBS + threadIdx.x;
+    const CONST_AS InitDesc &d = cref(descs + s);
+    const int64_t q = ((int64_t)blockIdx.x - cref(pre + s)) * kBS + threadIdx.x;
     if (q > d.n) return;
     const int W = d.W;
     if (q == d.n) {
@@ -807,7 +805,7 @@ __global__ void __launch_bounds__(kBS) k_init(const InitDesc *descs, const int64
 }
 
 template <int W>
-__device__ void rehash_w(const RehashDesc &d, int64_t id) {
+__device__ void rehash_w(const CONST_AS RehashDesc &d, int64_t id) {
     u64 x[W];
 #pragma unroll
     for (int w = 0; w < W; ++w) x[w] = d.rows[id * W + w];
@@ -823,8 +821,8 @@ __device__ void rehash_w(const RehashDesc &d, int64_t id) {
 // stored rows are pairwise distinct, so each just needs a free slot
 __global__ void __launch_bounds__(kBS) k_rehash(const RehashDesc *descs, const int64_t *pre, int nseg) {
     const int s = find_seg(pre, nseg, blockIdx.x);
-    const RehashDesc &d = descs[s];
-    const int64_t id = ((int64_t)blockIdx.x - pre[s]) * kBS + threadIdx.x;
+    const CONST_AS RehashDesc &d = cref(descs + s);
+    const int64_t id = ((int64_t)blockIdx.x - cref(pre + s)) * kBS + threadIdx.x;
     if (id >= d.count) return;
     SRW_SWITCH_W(d.W, rehash_w<W>(d, id));
 }
@@ -832,8 +830,8 @@ __global__ void __launch_bounds__(kBS) k_rehash(const RehashDesc *descs, const i
 // mark every slot of each segment's (new) hash table free
 __global__ void __launch_bounds__(kBS) k_clear_tables(const RehashDesc *descs, const int64_t *pre, int nseg) {
     const int s = find_seg(pre, nseg, blockIdx.x);
-    const RehashDesc &d = descs[s];
-    const int64_t e = ((int64_t)blockIdx.x - pre[s]) * kBS + threadIdx.x;
+    const CONST_AS RehashDesc &d = cref(descs + s);
+    const int64_t e = ((int64_t)blockIdx.x - cref(pre + s)) * kBS + threadIdx.x;
     if (e <= (int64_t)d.tab_mask) d.tab[e] = kEmpty;
 }
 
@@ -851,7 +849,7 @@ __global__ void __launch_bounds__(kBS) k_fill(u64 *p, int64_t count, u64 v) {
 __global__ void k_trace(const TraceDesc *descs, int count) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= count) return;
-    const TraceDesc &d = descs[t];
+    const CONST_AS TraceDesc &d = cref(descs + t);
     int64_t i = d.i;
     for (int L = d.f; L > 0; --L) {
         const u32 g = d.par_f[d.off_f[L] + i];
@@ -910,7 +908,7 @@ hipError_t launch_transpose_rows(const TransposeDesc *d, const int64_t *pre, int
     hipLaunchKernelGGL(k_transpose_rows, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
     return launch_checked();
 }
-// segments s0..s1-1 all have width W; `items` = pre[s1] - pre[s0].  At most
+// segments s0..s1-1 all have width W; `items` = cref(pre + s1) - cref(pre + s0).  At most
 // max_grid blocks (each then loops over several items); short-lived blocks
 // let kernels of other streams onto the GPU between them.
 hipError_t launch_meet(const StepDesc *d, const int64_t *pre, int s0, int s1, int W, int64_t items,

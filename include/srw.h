@@ -130,7 +130,10 @@ int srw_set_stream(void *hip_stream);
  * srw_solve_batch).  Keys:
  *   "budget"      device memory budget in bytes (0: 80% of free memory)
  *   "max_slots"   automata resident at once in srw_solve_batch
- *   "profile"     1: time every kernel class with HIP events (srw_get_stats)
+ *   "profile"     1: time every kernel class with HIP events (srw_get_stats);
+ *                 2: time the meet launches only (per set width) and count
+ *                 their set operations -- light enough for a timed run;
+ *                 0: off
  *   "schedule"    0: smaller frontier first, ties forward (default)
  *                 1: pseudo-random side per step from "sched_seed"
  *                 2: alternate forward / inverse
@@ -143,7 +146,8 @@ int srw_set_stream(void *hip_stream);
  *   "meet_rows"   chunked meet: groups of 64 tiles with at most this many
  *                 candidate sets (capped at 512) test them by signature,
  *                 larger ones AND columns
- *   "meet_groups" chunked meet: groups of 64 tiles per work item (at most)
+ *   "meet_groups" chunked meet: groups of 64 tiles per work item (at most;
+ *                 default 32)
  *   "meet_order"  chunked meet work items: 1 chunk-major (default), 0 tile-
  *                 range-major (consecutive items share one range of tiles)
  *   "meet_grid"   meet blocks per launch, grid-striding over the work items
@@ -172,11 +176,11 @@ typedef struct srw_stats {
     int64_t bytes_compact;     /* algorithmic bytes of count+compact */
     int64_t peak_device_bytes; /* device memory held at peak */
     int64_t meet_launches_w[8];/* meet kernel launches per set width W = index + 1 */
-    double meet_ms_w[8];       /* their time, with "profile" on */
+    double meet_ms_w[8];       /* their time, with "profile" 1 or 2 */
     int64_t pair_words_w[8];   /* their brute-force pair-word count */
     int64_t meet_ops_w[8];     /* set operations they performed, in 32-bit lane-ops
                                   (2 per 64-bit AND, 4 per word of a subset test),
-                                  with "profile" on */
+                                  with "profile" 1 or 2 */
 } srw_stats;
 /* kernel classes: 0 expand, 1 insert, 2 count+scan+compact, 3 meet
  * preparation (transpose of inverse levels, bucket sort of forward levels),

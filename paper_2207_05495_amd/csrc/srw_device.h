@@ -22,6 +22,12 @@ constexpr int kMeetTileWords = 32;       // LDS budget of the meet: tiles*W <= t
 constexpr int64_t kMeetMaxGrid = 0x7fffffff;  // meet blocks per launch (grid-stride beyond)
 constexpr int kCommonMax = 8;            // chunked meet: common states used per chunk
 constexpr int kCommonRound = 4;          // common columns loaded per round
+// meet operation counters: per set width, kOpsSlots counters kOpsStride words
+// apart (one 128-byte line each), so that the blocks of a launch spread their
+// atomic adds over many addresses
+constexpr int kOpsSlots = 64;
+constexpr int kOpsStride = 16;
+constexpr int kOpsWords = kMaxW * kOpsSlots * kOpsStride;
 constexpr int kRowBatchMax = 512;        // chunked meet: most candidates per group tested by signature
 // LDS words per wave of the chunked meet: kRowBatchMax candidate indices (u32)
 // and their signatures; also holds one tile of columns (64 * W words)

@@ -346,10 +346,10 @@ struct Options {
     uint64_t sched_seed = 1;
     int meet_tiles = 0;
     int64_t meet_rows = kRowBatchMax;   // chunked meet: row tests up to this many candidates per group
-    int64_t meet_groups = 8;            // chunked meet: tile groups per work item (upper limit)
+    int64_t meet_groups = 32;           // chunked meet: tile groups per work item (upper limit)
     int64_t meet_grid = 0;              // meet blocks per launch (0: one per work item)
     int64_t meet_order = 1;             // chunked meet items: 0 tile-range-major, 1 chunk-major
-    bool profile = false;
+    int profile = 0;                    // 1: every kernel class and the meet; 2: the meet only
     bool keep_levels = false;
     bool verbose = false;          // one stderr line per step of a single solve
     int64_t max_slots = 4096;
@@ -405,17 +405,21 @@ class Engine {
     srw_stats stats() {
         srw_stats out = stats_;
         if (d_ops_) {
-            u64 *h = (u64 *)pin_misc_.need(kMaxW * sizeof(u64));
-            HIPCHK(hipMemcpyAsync(h, d_ops_, kMaxW * sizeof(u64), hipMemcpyDeviceToHost, stream_));
+            u64 *h = (u64 *)pin_misc_.need(kOpsWords * sizeof(u64));
+            HIPCHK(hipMemcpyAsync(h, d_ops_, kOpsWords * sizeof(u64), hipMemcpyDeviceToHost, stream_));
             HIPCHK(hipStreamSynchronize(stream_));
-            for (int w = 0; w < kMaxW; ++w) out.meet_ops_w[w] = (int64_t)h[w];
+            for (int w = 0; w < kMaxW; ++w) {
+                out.meet_ops_w[w] = 0;
+                for (int sl = 0; sl < kOpsSlots; ++sl)
+                    out.meet_ops_w[w] += (int64_t)h[((int64_t)w * kOpsSlots + sl) * kOpsStride];
+            }
         }
         return out;
     }
     void reset_stats() {
         memset(&stats_, 0, sizeof stats_);
         if (d_ops_) {
-            HIPCHK(launch_fill(d_ops_, kMaxW, 0, stream_));
+            HIPCHK(launch_fill(d_ops_, kOpsWords, 0, stream_));
             HIPCHK(hipStreamSynchronize(stream_));
         }
     }
@@ -712,7 +716,7 @@ class Engine {
                 pm[i + 1] = pm[i] + d.nXb * d.nYc;
             } else {
                 const int64_t ng_ub = ceil_div(ceil_div(ny_ub, 64), 64);   // groups of 64 tiles
-                d.ngi = std::max<int64_t>(1, std::min<int64_t>(opt.meet_groups, ng_ub / 4));
+                d.ngi = std::max<int64_t>(1, std::min<int64_t>(opt.meet_groups, ng_ub));
                 d.row_batch_max = std::min<int64_t>(opt.meet_rows, kRowBatchMax);
                 d.nch_ub = ceil_div(nx_ub, 64);
                 d.item_order = opt.meet_order;
@@ -787,9 +791,9 @@ class Engine {
         }
         prof_begin(4);
         if (opt.profile && !d_ops_) {
-            d_ops_ = (u64 *)pool_->alloc(kMaxW * sizeof(u64));
+            d_ops_ = (u64 *)pool_->alloc(kOpsWords * sizeof(u64));
             if (!d_ops_) throw HipFailure{hipErrorOutOfMemory, "meet counters"};
-            HIPCHK(launch_fill(d_ops_, kMaxW, 0, stream_));
+            HIPCHK(launch_fill(d_ops_, kOpsWords, 0, stream_));
         }
         for (int s0 = 0; s0 < nseg;) {
             int s1 = s0;
@@ -800,7 +804,8 @@ class Engine {
                 meet_used_[W - 1] = true;
             }
             HIPCHK(launch_meet(dD, dpm, s0, s1, W, pm[s1] - pm[s0], opt.meet_grid,
-                               opt.profile ? d_ops_ + (W - 1) : nullptr, stream_));
+                               opt.profile ? d_ops_ + (int64_t)(W - 1) * kOpsSlots * kOpsStride : nullptr,
+                               stream_));
             if (opt.profile) HIPCHK(hipEventRecord(ev_meet_[2 * (W - 1) + 1], stream_));
             stats_.meet_launches_w[W - 1]++;
             s0 = s1;
@@ -1113,13 +1118,13 @@ class Engine {
     }
 
     void prof_begin(int c) {
-        if (opt.profile) {
+        if (opt.profile == 1) {
             HIPCHK(hipEventRecord(ev_[2 * c], stream_));
             prof_used_[c] = true;
         }
     }
     void prof_end(int c) {
-        if (opt.profile) HIPCHK(hipEventRecord(ev_[2 * c + 1], stream_));
+        if (opt.profile == 1) HIPCHK(hipEventRecord(ev_[2 * c + 1], stream_));
     }
     void prof_collect() {
         if (!opt.profile) return;
@@ -1280,7 +1285,7 @@ int srw_set_option(const char *key, int64_t v) {
         return SRW_OK;
     }
     if (k == "max_slots") { if (v < 1) return set_error(SRW_EINVAL, "max_slots < 1"); x.opt.max_slots = v; }
-    else if (k == "profile") x.opt.profile = v != 0;
+    else if (k == "profile") { if (v < 0 || v > 2) return set_error(SRW_EINVAL, "profile"); x.opt.profile = (int)v; }
     else if (k == "schedule") { if (v < 0 || v > 2) return set_error(SRW_EINVAL, "schedule"); x.opt.schedule = (int)v; }
     else if (k == "sched_seed") x.opt.sched_seed = (uint64_t)v;
     else if (k == "meet_tiles") { if (v < 0 || v > kMeetTileWords) return set_error(SRW_EINVAL, "meet_tiles"); x.opt.meet_tiles = (int)v; }

@@ -409,6 +409,12 @@ __device__ u32 meet_w(const CONST_AS StepDesc &d, int64_t lb, u64 *cols) {
     return nops;
 }
 
+// a / b for a >= 0, b > 0, in 32 bits when both fit
+__device__ __forceinline__ int64_t udiv(int64_t a, int64_t b) {
+    if (((u64)a | (u64)b) >> 32 == 0) return (int64_t)((u32)a / (u32)b);
+    return (int64_t)((u64)a / (u64)b);
+}
+
 __device__ __forceinline__ u64 shfl64(u64 v, int src) {
     const u32 lo = (u32)__shfl((int)(u32)v, src, 64);
     const u32 hi = (u32)__shfl((int)(u32)(v >> 32), src, 64);
@@ -446,8 +452,8 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
     // tile-range-major: the items in flight share one range of tiles, so its
     // columns and rows stay in L2 (every XCD works on the same range)
     int64_t c, gi;
-    if (d.item_order == 0) { gi = item / d.nch_ub; c = item - gi * d.nch_ub; }
-    else { c = item / d.gitems_ub; gi = item - c * d.gitems_ub; }
+    if (d.item_order == 0) { gi = udiv(item, d.nch_ub); c = item - gi * d.nch_ub; }
+    else { c = udiv(item, d.gitems_ub); gi = item - c * d.gitems_ub; }
     if (c * 64 >= nX) return 0;                    // whole wave
     const int64_t g0 = gi * d.ngi;
     const int64_t g1 = min(g0 + d.ngi, ngroups);
@@ -629,7 +635,8 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
 // The item count can exceed the grid limit.  One launch covers segments
 // s0..s1-1, which all have W words per set (a kernel per width keeps the
 // register count of the narrow widths low).  With `ops` set, the set
-// operations the launch performed (32-bit lane-ops) are added to *ops.
+// operations the launch performed (32-bit lane-ops) are added to the
+// kOpsSlots counters at ops (kOpsStride words apart).
 template <int W>
 __global__ void __launch_bounds__(kBS) k_meet(const StepDesc *descs, const int64_t *pre, int s0, int s1, u64 *ops) {
     __shared__ u64 cols[kMeetLdsWords];
@@ -650,7 +657,8 @@ __global__ void __launch_bounds__(kBS) k_meet(const StepDesc *descs, const int64
             u32 sum = nops;   // at most a few million per wave and item
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1) sum += (u32)__shfl_xor((int)sum, off, 64);
-            if ((threadIdx.x & 63) == 0 && sum) atomicAdd((unsigned long long *)ops, (unsigned long long)sum);
+            if ((threadIdx.x & 63) == 0 && sum)
+                atomicAdd((unsigned long long *)(ops + (blockIdx.x % kOpsSlots) * kOpsStride), (unsigned long long)sum);
         }
     }
 }

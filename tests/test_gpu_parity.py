@@ -33,7 +33,7 @@ def gpu():
 
 
 DEFAULTS = (("schedule", 0), ("meet_tiles", 0), ("keep_levels", 0), ("budget", 0), ("meet", 0),
-            ("max_slots", 4096), ("meet_rows", 512), ("meet_groups", 8), ("meet_order", 1),
+            ("max_slots", 4096), ("meet_rows", 512), ("meet_groups", 32), ("meet_order", 1),
             ("meet_grid", 0), ("deadline_ms", 0), ("verbose", 0))
 
 
@@ -342,7 +342,7 @@ def test_meet_tuning_options_keep_results(rows, groups, order, grid):
             assert srw.solve(n, k, d) == O.bidir(n, k, d)[:2]
     finally:
         srw.set_option("meet_rows", 512)
-        srw.set_option("meet_groups", 8)
+        srw.set_option("meet_groups", 32)
         srw.set_option("meet_order", 1)
         srw.set_option("meet_grid", 0)
 

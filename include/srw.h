@@ -152,6 +152,9 @@ int srw_set_stream(void *hip_stream);
  *                 range-major (consecutive items share one range of tiles)
  *   "meet_grid"   meet blocks per launch, grid-striding over the work items
  *                 (0: one block per work item, up to 2^31-1)
+ *   "small_cand"  steps with at most this many candidates (and a small
+ *                 LDS-tile meet) run in one block, one launch for the whole
+ *                 step (default 2048; 0: never)
  *   "deadline_ms" per automaton, from its admission: a solve still running
  *                 after this long ends with SRW_ETIMEOUT (0: no deadline)
  *   "verbose"     1: one line per step of a single solve on stderr
@@ -181,8 +184,11 @@ typedef struct srw_stats {
     int64_t meet_ops_w[8];     /* set operations they performed, in 32-bit lane-ops
                                   (2 per 64-bit AND, 4 per word of a subset test),
                                   with "profile" 1 or 2 */
+    double host_ms[4];         /* wall time of the steps by phase: 0 sides, growth and
+                                  copies; 1 descriptors, uploads and launches; 2 waiting
+                                  for the device; 3 results, meets and words */
 } srw_stats;
-/* kernel classes: 0 expand, 1 insert, 2 count+scan+compact, 3 meet
+/* kernel classes: 0 expand (and whole one-block steps), 1 insert, 2 count+scan+compact, 3 meet
  * preparation (transpose of inverse levels, bucket sort of forward levels),
  * 4 meet, 5 trace, 6 init/rehash/fill/copies, 7 whole steps (host view) */
 

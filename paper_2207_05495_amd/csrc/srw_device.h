@@ -28,6 +28,7 @@ constexpr int kCommonRound = 4;          // common columns loaded per round
 constexpr int kOpsSlots = 64;
 constexpr int kOpsStride = 16;
 constexpr int kOpsWords = kMaxW * kOpsSlots * kOpsStride;
+constexpr int64_t kSmallMeetBlocks = 64;  // small steps: at most this many LDS-tile meet blocks
 constexpr int kRowBatchMax = 512;        // chunked meet: most candidates per group tested by signature
 // LDS words per wave of the chunked meet: kRowBatchMax candidate indices (u32)
 // and their signatures; also holds one tile of columns (64 * W words)
@@ -73,6 +74,8 @@ struct StepDesc {
     int64_t nXb, nYc;          // mode 0 grid of this segment (upper bounds)
     int32_t tpb;               // mode 0: tiles per meet block
     int32_t meet_mode;         // 0: LDS tiles, 1: sorted 64-set chunks
+    int32_t small;             // 1: the whole step runs in one block (k_step_small)
+    int32_t pad2;
     const u32 *Xidx;           // mode 1: rank of each sorted X in its level
     const u64 *Xcom;           // mode 1: AND of the 64 sets of each chunk
     int64_t gitems_ub;         // mode 1: work items per chunk (upper bound)
@@ -110,7 +113,19 @@ struct InitDesc {
     u64 *rows_f;               // forward level 0: Q
     u64 *rows_b;               // inverse level 0: the n singletons
     u32 *par_f, *par_b;
+    const uint16_t *delta_src; // the table as uploaded (all automata of the call in one copy)
+    uint16_t *delta;           // the automaton's own k*n table
+    int32_t k, pad;
 };
+
+// device-to-device copy of `count` 32-bit words (grown buffers keep their
+// contents); one launch copies every buffer grown in a step
+struct CopyDesc {
+    const u32 *src;
+    u32 *dst;
+    int64_t count;
+};
+constexpr int kCopyPerBlock = 4096;      // words per block of k_copy
 
 struct RehashDesc {
     int32_t W, pad;

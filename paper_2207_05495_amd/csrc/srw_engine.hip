@@ -34,6 +34,8 @@ hipError_t launch_compact(const StepDesc *, const int64_t *, int, int64_t, const
 hipError_t launch_transpose(const StepDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_transpose_rows(const TransposeDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_meet(const StepDesc *, const int64_t *, int, int, int, int64_t, int64_t, u64 *, hipStream_t);
+hipError_t launch_step_small(const StepDesc *, const int32_t *, int, u64 *, hipStream_t);
+hipError_t launch_copy(const CopyDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_init(const InitDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_rehash(const RehashDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_fill(u64 *, int64_t, u64, hipStream_t);
@@ -271,6 +273,17 @@ class Pool {
 struct Pinned {
     void *p = nullptr;
     size_t cap = 0;
+    hipEvent_t ev = nullptr;     // recorded after the last copy that reads the buffer
+    // the buffer, once the last copy out of it has been done
+    void *acquire(size_t bytes) {
+        if (ev) HIPCHK(hipEventSynchronize(ev));
+        return need(bytes);
+    }
+    // a copy out of the buffer has been enqueued on `st`
+    void issued(hipStream_t st) {
+        if (!ev) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(ev, st));
+    }
     void *need(size_t bytes) {
         if (bytes > cap) {
             if (p) (void)hipHostFree(p);
@@ -283,7 +296,9 @@ struct Pinned {
         return p;
     }
     ~Pinned() {
+        if (ev) (void)hipEventSynchronize(ev);
         if (p) (void)hipHostFree(p);
+        if (ev) (void)hipEventDestroy(ev);
     }
 };
 
@@ -347,6 +362,7 @@ struct Options {
     int meet_tiles = 0;
     int64_t meet_rows = kRowBatchMax;   // chunked meet: row tests up to this many candidates per group
     int64_t meet_groups = 32;           // chunked meet: tile groups per work item (upper limit)
+    int64_t small_cand = 2048;          // steps with at most this many candidates run in one block (0: never)
     int64_t meet_grid = 0;              // meet blocks per launch (0: one per work item)
     int64_t meet_order = 1;             // chunked meet items: 0 tile-range-major, 1 chunk-major
     int profile = 0;                    // 1: every kernel class and the meet; 2: the meet only
@@ -405,7 +421,7 @@ class Engine {
     srw_stats stats() {
         srw_stats out = stats_;
         if (d_ops_) {
-            u64 *h = (u64 *)pin_misc_.need(kOpsWords * sizeof(u64));
+            u64 *h = (u64 *)pin_misc_.acquire(kOpsWords * sizeof(u64));
             HIPCHK(hipMemcpyAsync(h, d_ops_, kOpsWords * sizeof(u64), hipMemcpyDeviceToHost, stream_));
             HIPCHK(hipStreamSynchronize(stream_));
             for (int w = 0; w < kMaxW; ++w) {
@@ -520,14 +536,20 @@ class Engine {
         // deltas as uint16
         size_t dbytes = 0;
         for (Problem *p : ps) dbytes += (size_t)p->k * p->n * 2;
-        uint16_t *hd = (uint16_t *)pin_delta_.need(dbytes);
+        uint16_t *hd = (uint16_t *)pin_delta_.acquire(dbytes);
+        std::vector<size_t> doff(nseg);
         size_t o = 0;
-        for (Problem *p : ps) {
+        for (int i = 0; i < nseg; ++i) {
+            Problem *p = ps[i];
             const size_t cnt = (size_t)p->k * p->n;
             for (size_t e = 0; e < cnt; ++e) hd[o + e] = (uint16_t)p->delta[e];
-            HIPCHK(hipMemcpyAsync(p->d_delta, hd + o, cnt * 2, hipMemcpyHostToDevice, stream_));
+            doff[i] = o;
             o += cnt;
         }
+        // one copy for all tables; k_init moves each to its automaton
+        uint16_t *dsrc = (uint16_t *)dev_need(delta_blob_, delta_blob_cap_, align8(dbytes));
+        HIPCHK(hipMemcpyAsync(dsrc, hd, dbytes, hipMemcpyHostToDevice, stream_));
+        pin_delta_.issued(stream_);
         // clear both tables, write level 0, insert it, transpose inverse level 0
         std::vector<InitDesc> idesc(nseg);
         std::vector<int64_t> ipre(nseg + 1, 0);
@@ -537,7 +559,8 @@ class Engine {
         std::vector<int64_t> tpre(nseg + 1, 0);
         for (int i = 0; i < nseg; ++i) {
             Problem *p = ps[i];
-            idesc[i] = InitDesc{p->n, p->W, p->s[0].rows, p->s[1].rows, p->s[0].par, p->s[1].par};
+            idesc[i] = InitDesc{p->n, p->W, p->s[0].rows, p->s[1].rows, p->s[0].par, p->s[1].par,
+                                dsrc + doff[i], p->d_delta, p->k, 0};
             ipre[i + 1] = ipre[i] + ceil_div(p->n + 1, kBS);
             for (int sd = 0; sd < 2; ++sd) {
                 rdesc.push_back(RehashDesc{p->W, 0, p->s[sd].rows, p->s[sd].nrows, p->s[sd].tab,
@@ -572,14 +595,14 @@ class Engine {
         std::vector<int64_t> cpre(1, 0);
         for (const RehashDesc &r : t) cpre.push_back(cpre.back() + ceil_div((int64_t)r.tab_mask + 1, kBS));
         const size_t a = align8(sizeof(RehashDesc) * t.size()), b = align8(8 * cpre.size());
-        char *h = (char *)pin_clear_.need(a + b);
+        char *h = (char *)pin_clear_.acquire(a + b);
         memcpy(h, t.data(), sizeof(RehashDesc) * t.size());
         memcpy(h + a, cpre.data(), 8 * cpre.size());
         char *d = dev_need(clear_blob_, clear_blob_cap_, a + b);
         HIPCHK(hipMemcpyAsync(d, h, a + b, hipMemcpyHostToDevice, stream_));
+        pin_clear_.issued(stream_);
         HIPCHK(launch_clear_tables((const RehashDesc *)d, (const int64_t *)(d + a), (int)t.size(),
                                    cpre.back(), stream_));
-        HIPCHK(hipStreamSynchronize(stream_));   // staging reused by the next clear
     }
 
     // One global step: every active problem expands one side.
@@ -607,6 +630,7 @@ class Engine {
             segp.push_back(p);
             segdir.push_back(dir);
         }
+        flush_copies();
         if (segp.empty() && !waiting.empty()) {
             // nothing can move: give up on the largest one to free memory
             Problem *big = waiting[0];
@@ -622,6 +646,8 @@ class Engine {
             stats_.launches[6] += 2;
         }
         prof_end(6);
+        const double t1 = now_ms();
+        stats_.host_ms[0] += t1 - t0;
         const int nseg = (int)segp.size();
         if (nseg == 0) return;
         {   // segments of equal width side by side: the meet launches per width
@@ -640,6 +666,7 @@ class Engine {
         std::vector<int64_t> pe(nseg + 1, 0), pc(nseg + 1, 0), pt(nseg + 1, 0), pm(nseg + 1, 0);
         std::vector<SortDesc> S;
         std::vector<int64_t> pz(1, 0), pr(1, 0), pch(1, 0);
+        std::vector<int32_t> small;                // segments whose whole step runs in one block
         if ((int64_t)nseg * 2 > res_cap_) {
             pool_->free(d_res_);
             res_cap_ = std::max<int64_t>((int64_t)nseg * 2, 2 * res_cap_);
@@ -724,9 +751,14 @@ class Engine {
                 pm[i + 1] = pm[i] + ceil_div(ceil_div(nx_ub, 64) * d.gitems_ub, kBS / 64);
             }
             d.ntr_waves = dir == 1 ? ceil_div(d.C, 64) * W : 0;
-            pe[i + 1] = pe[i] + ceil_div(d.C, kBS);
-            pc[i + 1] = pc[i] + d.ncblk;
-            pt[i + 1] = pt[i] + ceil_div(d.ntr_waves, kBS / 64);
+            d.small = d.meet_mode == 0 && d.C <= opt.small_cand && d.nXb * d.nYc <= kSmallMeetBlocks;
+            if (d.small) {
+                pm[i + 1] = pm[i];
+                small.push_back(i);
+            }
+            pe[i + 1] = pe[i] + (d.small ? 0 : ceil_div(d.C, kBS));
+            pc[i + 1] = pc[i] + (d.small ? 0 : d.ncblk);
+            pt[i + 1] = pt[i] + (d.small ? 0 : ceil_div(d.ntr_waves, kBS / 64));
             stats_.candidates += d.C;
             stats_.cand_words += d.C * W;
             stats_.bytes_expand += 8 * W * (d.m + d.C);
@@ -746,7 +778,9 @@ class Engine {
         const int nsort = (int)S.size();
         const size_t szD = align8(sizeof(StepDesc) * nseg), szP = align8(8 * (nseg + 1));
         const size_t szS = align8(sizeof(SortDesc) * nsort), szQ = align8(8 * (nsort + 1));
-        const size_t total = szD + 4 * szP + szS + 3 * szQ;
+        const int nsmall = (int)small.size();
+        const size_t szL = align8(4 * (size_t)std::max(1, nsmall));
+        const size_t total = szD + 4 * szP + szS + 3 * szQ + szL;
         char *h = (char *)pin_step_.need(total);
         memcpy(h, D.data(), sizeof(StepDesc) * nseg);
         memcpy(h + szD, pe.data(), 8 * (nseg + 1));
@@ -758,6 +792,8 @@ class Engine {
         memcpy(h + oS + szS, pz.data(), 8 * (nsort + 1));
         memcpy(h + oS + szS + szQ, pr.data(), 8 * (nsort + 1));
         memcpy(h + oS + szS + 2 * szQ, pch.data(), 8 * (nsort + 1));
+        const size_t oL = oS + szS + 3 * szQ;
+        if (nsmall) memcpy(h + oL, small.data(), 4 * nsmall);
         char *dblob = dev_need(step_blob_, step_blob_cap_, total);
         HIPCHK(hipMemcpyAsync(dblob, h, total, hipMemcpyHostToDevice, stream_));
         const StepDesc *dD = (const StepDesc *)dblob;
@@ -770,8 +806,15 @@ class Engine {
                                        (const int64_t *)(dblob + oS + szS + szQ),
                                        (const int64_t *)(dblob + oS + szS + 2 * szQ)};
         const int64_t sblocks[3] = {pz.back(), pr.back(), pch.back()};
+        const int32_t *dsmall = (const int32_t *)(dblob + oL);
 
+        if (opt.profile && !d_ops_) {
+            d_ops_ = (u64 *)pool_->alloc(kOpsWords * sizeof(u64));
+            if (!d_ops_) throw HipFailure{hipErrorOutOfMemory, "meet counters"};
+            HIPCHK(launch_fill(d_ops_, kOpsWords, 0, stream_));
+        }
         prof_begin(0);
+        HIPCHK(launch_step_small(dD, dsmall, nsmall, opt.profile ? d_ops_ : nullptr, stream_));
         HIPCHK(launch_expand(dD, dpe, nseg, pe[nseg], stream_));
         prof_end(0);
         prof_begin(1);
@@ -779,7 +822,7 @@ class Engine {
         prof_end(1);
         prof_begin(2);
         HIPCHK(launch_count(dD, dpc, nseg, pc[nseg], d_cnt_, stream_));
-        HIPCHK(launch_scan(dD, nseg, d_cnt_, d_off_, stream_));
+        if (nsmall < nseg) HIPCHK(launch_scan(dD, nseg, d_cnt_, d_off_, stream_));
         HIPCHK(launch_compact(dD, dpc, nseg, pc[nseg], d_off_, stream_));
         prof_end(2);
         if (pt[nseg] > 0 || nsort > 0) {
@@ -790,15 +833,14 @@ class Engine {
             stats_.launches[3]++;
         }
         prof_begin(4);
-        if (opt.profile && !d_ops_) {
-            d_ops_ = (u64 *)pool_->alloc(kOpsWords * sizeof(u64));
-            if (!d_ops_) throw HipFailure{hipErrorOutOfMemory, "meet counters"};
-            HIPCHK(launch_fill(d_ops_, kOpsWords, 0, stream_));
-        }
         for (int s0 = 0; s0 < nseg;) {
             int s1 = s0;
             const int W = segp[s0]->W;
             while (s1 < nseg && segp[s1]->W == W) ++s1;
+            if (pm[s1] == pm[s0]) {                // only small segments of this width
+                s0 = s1;
+                continue;
+            }
             if (opt.profile) {
                 HIPCHK(hipEventRecord(ev_meet_[2 * (W - 1)], stream_));
                 meet_used_[W - 1] = true;
@@ -817,7 +859,11 @@ class Engine {
         stats_.launches[4]++;
         u64 *hres = (u64 *)pin_res_.need((size_t)nseg * 16);
         HIPCHK(hipMemcpyAsync(hres, d_res_, (size_t)nseg * 16, hipMemcpyDeviceToHost, stream_));
-        HIPCHK(hipStreamSynchronize(stream_));
+        const double t2 = now_ms();
+        wait_step();
+        const double t3 = now_ms();
+        stats_.host_ms[1] += t2 - t1;
+        stats_.host_ms[2] += t3 - t2;
         prof_collect();
         stats_.global_steps++;
 
@@ -856,7 +902,9 @@ class Engine {
             }
         }
         if (!met.empty()) trace(met, metbest);
-        stats_.ms[7] += now_ms() - t0;
+        const double t4 = now_ms();
+        stats_.host_ms[3] += t4 - t3;
+        stats_.ms[7] += t4 - t0;
     }
 
     void finish_error(Problem *p, int code, const char *msg = nullptr) {
@@ -900,11 +948,37 @@ class Engine {
         const int64_t nc = std::max(need, cap * 2);
         void *q = pool_->alloc((size_t)nc * elem);
         if (!q) return false;
-        if (ptr && keep > 0) HIPCHK(hipMemcpyAsync(q, ptr, (size_t)keep * elem, hipMemcpyDeviceToDevice, stream_));
-        pool_->free(ptr);
+        if (ptr && keep > 0) {
+            // copied by flush_copies in one launch with the step's other
+            // grown buffers; the old block stays allocated until that launch
+            // is enqueued, so no buffer grown in the same step can reuse it
+            pend_copy_.push_back(CopyDesc{(const u32 *)ptr, (u32 *)q, (int64_t)((size_t)keep * elem / 4)});
+            pend_free_.push_back(ptr);
+        } else {
+            pool_->free(ptr);
+        }
         ptr = q;
         cap = nc;
         return true;
+    }
+
+    void flush_copies() {
+        if (pend_copy_.empty()) return;
+        std::vector<int64_t> pre(1, 0);
+        for (const CopyDesc &c : pend_copy_) pre.push_back(pre.back() + ceil_div(c.count, kCopyPerBlock));
+        const size_t a = align8(sizeof(CopyDesc) * pend_copy_.size()), b = align8(8 * pre.size());
+        char *h = (char *)pin_copy_.acquire(a + b);
+        memcpy(h, pend_copy_.data(), sizeof(CopyDesc) * pend_copy_.size());
+        memcpy(h + a, pre.data(), 8 * pre.size());
+        char *d = dev_need(copy_blob_, copy_blob_cap_, a + b);
+        HIPCHK(hipMemcpyAsync(d, h, a + b, hipMemcpyHostToDevice, stream_));
+        pin_copy_.issued(stream_);
+        HIPCHK(launch_copy((const CopyDesc *)d, (const int64_t *)(d + a), (int)pend_copy_.size(), pre.back(),
+                           stream_));
+        stats_.launches[6]++;
+        for (void *q : pend_free_) pool_->free(q);
+        pend_copy_.clear();
+        pend_free_.clear();
     }
 
     // make room for one step of side `dir`; returns 0 or an SRW_ error
@@ -1086,13 +1160,12 @@ class Engine {
     template <class T>
     void *upload_simple(const std::vector<T> &v, const std::vector<int64_t> &pre, void *&blob) {
         const size_t a = align8(sizeof(T) * v.size()), b = align8(8 * pre.size());
-        char *h = (char *)pin_misc_.need(a + b);
+        char *h = (char *)pin_misc_.acquire(a + b);
         memcpy(h, v.data(), sizeof(T) * v.size());
         memcpy(h + a, pre.data(), 8 * pre.size());
         char *d = dev_need(blob, misc_blob_cap_, a + b);
         HIPCHK(hipMemcpyAsync(d, h, a + b, hipMemcpyHostToDevice, stream_));
-        // the pinned staging buffer is reused by the next upload: wait
-        HIPCHK(hipStreamSynchronize(stream_));
+        pin_misc_.issued(stream_);
         return d;
     }
 
@@ -1103,7 +1176,7 @@ class Engine {
         const size_t s3 = align8(sizeof(RehashDesc) * b.size()), s4 = align8(8 * bp.size());
         const size_t s5 = align8(sizeof(TransposeDesc) * c.size()), s6 = align8(8 * cp.size());
         const size_t total = s1 + s2 + s3 + s4 + s5 + s6;
-        char *h = (char *)pin_init_.need(total);
+        char *h = (char *)pin_init_.acquire(total);
         char *q = h;
         memcpy(q, a.data(), sizeof(InitDesc) * a.size()); q += s1;
         memcpy(q, ap.data(), 8 * ap.size()); q += s2;
@@ -1113,9 +1186,25 @@ class Engine {
         memcpy(q, cp.data(), 8 * cp.size());
         char *d = dev_need(init_blob_, init_blob_cap_, total);
         HIPCHK(hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, stream_));
-        HIPCHK(hipStreamSynchronize(stream_));   // staging reused by the next init
+        pin_init_.issued(stream_);
         return d;
     }
+
+    // Waits for the step's results.  Short steps (many of them: a Černý
+    // automaton takes (n-1)^2 steps) finish within tens of microseconds, and
+    // polling the stream answers sooner than a blocking wait; after
+    // kSpinMs of polling it blocks.
+    void wait_step() {
+        const double t0 = now_ms();
+        for (;;) {
+            const hipError_t e = hipStreamQuery(stream_);
+            if (e == hipSuccess) return;
+            if (e != hipErrorNotReady) throw HipFailure{e, "step"};
+            if (now_ms() - t0 > kSpinMs) break;
+        }
+        HIPCHK(hipStreamSynchronize(stream_));
+    }
+    static constexpr double kSpinMs = 2.0;
 
     void prof_begin(int c) {
         if (opt.profile == 1) {
@@ -1153,7 +1242,11 @@ class Engine {
     hipEvent_t ev_[16], ev_meet_[2 * kMaxW];
     bool meet_used_[kMaxW] = {};
     bool prof_used_[8] = {};
-    Pinned pin_delta_, pin_step_, pin_res_, pin_trace_, pin_init_, pin_misc_, pin_clear_;
+    Pinned pin_delta_, pin_step_, pin_res_, pin_trace_, pin_init_, pin_misc_, pin_clear_, pin_copy_;
+    std::vector<CopyDesc> pend_copy_;
+    std::vector<void *> pend_free_;
+    void *copy_blob_ = nullptr, *delta_blob_ = nullptr;
+    int64_t copy_blob_cap_ = 0, delta_blob_cap_ = 0;
     void *step_blob_ = nullptr, *trace_blob_ = nullptr, *init_blob_ = nullptr, *rehash_blob_ = nullptr,
          *clear_blob_ = nullptr;
     int64_t step_blob_cap_ = 0, trace_blob_cap_ = 0, init_blob_cap_ = 0, misc_blob_cap_ = 0,
@@ -1294,6 +1387,7 @@ int srw_set_option(const char *key, int64_t v) {
     else if (k == "deadline_ms") { if (v < 0) return set_error(SRW_EINVAL, "deadline_ms"); x.opt.deadline_ms = (double)v; }
     else if (k == "meet") { if (v < 0 || v > 2) return set_error(SRW_EINVAL, "meet"); x.opt.meet = (int)v; }
     else if (k == "meet_rows") { if (v < 0) return set_error(SRW_EINVAL, "meet_rows"); x.opt.meet_rows = v; }
+    else if (k == "small_cand") { if (v < 0 || v > (1 << 20)) return set_error(SRW_EINVAL, "small_cand"); x.opt.small_cand = v; }
     else if (k == "meet_groups") { if (v < 1 || v > 4096) return set_error(SRW_EINVAL, "meet_groups"); x.opt.meet_groups = v; }
     else if (k == "meet_grid") { if (v < 0) return set_error(SRW_EINVAL, "meet_grid"); x.opt.meet_grid = v; }
     else if (k == "meet_order") { if (v < 0 || v > 1) return set_error(SRW_EINVAL, "meet_order"); x.opt.meet_order = v; }

@@ -245,6 +245,7 @@ __global__ void __launch_bounds__(kBS) k_scan(const StepDesc *descs, int nseg, c
     const int s = blockIdx.x;
     if (s >= nseg) return;
     const CONST_AS StepDesc &d = cref(descs + s);
+    if (d.small) return;                   // its step runs in k_step_small
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     u64 running = 0;
     for (int64_t c0 = 0; c0 < d.ncblk; c0 += kBS) {
@@ -535,6 +536,7 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
             for (int r = 0; r < kCommonRound; ++r) m &= v[r];
             if (tv) nops += 2 * min(nc - r0, kCommonRound);
         }
+        if (__ballot(m != 0) == 0) continue;      // the usual case: no candidate in the group
         // number the candidates: lane order (tile), then bit order
         const u32 pc = (u32)__popcll(m);
         u32 incl = pc;
@@ -660,6 +662,100 @@ __global__ void __launch_bounds__(kBS) k_meet(const StepDesc *descs, const int64
             if ((threadIdx.x & 63) == 0 && sum)
                 atomicAdd((unsigned long long *)(ops + (blockIdx.x % kOpsSlots) * kOpsStride), (unsigned long long)sum);
         }
+    }
+}
+
+// ------------------------------------------------------ copies
+
+__global__ void __launch_bounds__(kBS) k_copy(const CopyDesc *descs, const int64_t *pre, int nseg) {
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const CONST_AS CopyDesc &d = cref(descs + s);
+    const int64_t base = ((int64_t)blockIdx.x - cref(pre + s)) * kCopyPerBlock;
+    for (int i = threadIdx.x; i < kCopyPerBlock; i += kBS) {
+        const int64_t e = base + i;
+        if (e < d.count) d.dst[e] = d.src[e];
+    }
+}
+
+// ------------------------------------------------------ small steps
+
+// One block runs a whole step of one small segment: expansion, insertion,
+// compaction in key order (a running rank over the candidates instead of a
+// scan across blocks), the transpose of a new inverse level and the LDS-tile
+// meet, with a barrier between phases.  The same device functions as the
+// per-phase kernels do the work, so the results are the same; what goes is
+// six dependent launches per step, which dominate when the lists are tiny (a
+// Černý automaton takes (n-1)^2 steps over lists of about n sets).
+template <int W>
+__device__ u32 step_small_w(const CONST_AS StepDesc &d, u64 *lds, u32 *wsum) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t nb = (d.C + kBS - 1) / kBS;
+    for (int64_t lb = 0; lb < nb; ++lb) expand_w<W>(d, lb, lds);
+    __syncthreads();
+    for (int64_t lb = 0; lb < nb; ++lb) insert_w<W>(d, lb);
+    __syncthreads();
+    u32 rank0 = 0;
+    for (int64_t g0 = 0; g0 < d.C; g0 += kBS) {
+        const int64_t g = g0 + tid;
+        const bool f = g < d.C && is_winner(d, g);
+        const u64 mask = __ballot(f);
+        if (lane == 0) wsum[wave] = (u32)__popcll(mask);
+        __syncthreads();
+        u32 wpre = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < kBS / 64; ++w) {
+            if (w < wave) wpre += wsum[w];
+            tot += wsum[w];
+        }
+        if (f) {
+            const u64 rank = rank0 + wpre + lanes_below(mask);
+#pragma unroll
+            for (int w = 0; w < W; ++w) d.out_rows[rank * W + w] = d.cand[g * W + w];
+            d.out_par[rank] = (u32)g;
+            const u32 sl = d.cslot[g];
+            const u64 e = d.tab[sl];
+            d.tab[sl] = (e & 0xFFFFFFFF00000000ull) | (u64)(u32)(d.out_base + (int64_t)rank);
+        }
+        rank0 += tot;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        d.res[0] = rank0;
+        d.res[1] = kEmpty;
+    }
+    if (d.ntr_waves > 0) {                 // a new inverse level: transpose it
+        const int64_t tiles = ((int64_t)rank0 + 63) / 64;
+        for (int64_t wv = wave; wv < tiles * W; wv += kBS / 64) {
+            const int64_t tile = wv / W;
+            transpose_tile(d.out_rows, rank0, W, d.YT, d.YTt, d.Ysig, tile, (int)(wv - tile * W));
+        }
+    }
+    __syncthreads();
+    u32 nops = 0;
+    const int64_t nmb = d.nXb * d.nYc;
+    for (int64_t lb = 0; lb < nmb; ++lb) {
+        __syncthreads();                   // the previous tiles are read
+        nops += meet_w<W>(d, lb, lds);
+    }
+    return nops;
+}
+
+// blocks: one per small segment, listed in segs
+__global__ void __launch_bounds__(kBS) k_step_small(const StepDesc *descs, const int32_t *segs, u64 *ops) {
+    __shared__ u64 lds[kMaxW * kBS];       // expansion rows, then meet tiles
+    __shared__ u32 wsum[kBS / 64];
+    static_assert(kMaxW * kBS >= kMeetTileWords * 64, "meet tiles fit the expansion buffer");
+    const int s = cref(segs + blockIdx.x);
+    const CONST_AS StepDesc &d = cref(descs + s);
+    u32 nops = 0;
+    SRW_SWITCH_W(d.W, nops = step_small_w<W>(d, lds, wsum));
+    if (ops) {
+        u32 sum = nops;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) sum += (u32)__shfl_xor((int)sum, off, 64);
+        if ((threadIdx.x & 63) == 0 && sum)
+            atomicAdd((unsigned long long *)(ops + ((int64_t)(d.W - 1) * kOpsSlots + blockIdx.x % kOpsSlots) * kOpsStride),
+                      (unsigned long long)sum);
     }
 }
 
@@ -799,6 +895,8 @@ __global__ void __launch_bounds__(kBS) k_init(const InitDesc *descs, const int64
     const int64_t q = ((int64_t)blockIdx.x - cref(pre + s)) * kBS + threadIdx.x;
     if (q > d.n) return;
     const int W = d.W;
+    if (q < d.n)
+        for (int a = 0; a < d.k; ++a) d.delta[(int64_t)a * d.n + q] = d.delta_src[(int64_t)a * d.n + q];
     if (q == d.n) {
         for (int w = 0; w < W; ++w) {
             const int lo = 64 * w;
@@ -877,6 +975,16 @@ __global__ void k_trace(const TraceDesc *descs, int count) {
 
 static inline hipError_t launch_checked() { return hipGetLastError(); }
 
+hipError_t launch_copy(const CopyDesc *d, const int64_t *pre, int nseg, int64_t blocks, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
+    return launch_checked();
+}
+hipError_t launch_step_small(const StepDesc *d, const int32_t *segs, int count, u64 *ops, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_step_small, dim3((unsigned)count), dim3(kBS), 0, st, d, segs, ops);
+    return launch_checked();
+}
 hipError_t launch_expand(const StepDesc *d, const int64_t *pre, int nseg, int64_t blocks, hipStream_t st) {
     if (blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_expand, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);

@@ -34,7 +34,7 @@ def gpu():
 
 DEFAULTS = (("schedule", 0), ("meet_tiles", 0), ("keep_levels", 0), ("budget", 0), ("meet", 0),
             ("max_slots", 4096), ("meet_rows", 512), ("meet_groups", 32), ("meet_order", 1),
-            ("meet_grid", 0), ("deadline_ms", 0), ("verbose", 0))
+            ("meet_grid", 0), ("small_cand", 2048), ("deadline_ms", 0), ("verbose", 0))
 
 
 def say(*a):
@@ -408,11 +408,13 @@ def test_profile_counters_per_width():
     probs = [(150, 2, rand_sync(150, 2, 0, base=73)), (60, 3, rand_sync(60, 3, 1, base=73))]
     srw.reset_stats()
     srw.set_option("profile", 1)
+    srw.set_option("small_cand", 0)        # every meet as its own launch
     try:
         say("profile counters")
         res = srw.solve_batch(probs)
     finally:
         srw.set_option("profile", 0)
+        srw.set_option("small_cand", 2048)
     assert all(st == srw.OK for st, _, _ in res)
     st = srw.get_stats()
     mw = st["meet_w"]
@@ -420,3 +422,23 @@ def test_profile_counters_per_width():
     assert sum(m["pair_words"] for m in mw.values()) == st["pair_words"]
     for m in mw.values():
         assert m["launches"] > 0 and m["ms"] > 0 and m["ops"] > 0
+
+
+@pytest.mark.parametrize("small", [0, 1 << 20])
+def test_one_block_steps_keep_results(small):
+    """Whole steps in one block (small segments) and the per-phase kernels
+    give the same r and word; 1 << 20 sends every step with an LDS-tile meet
+    of at most 64 blocks through the one-block path."""
+    cs = [(n, 2, I.cerny(n)) for n in (2, 3, 7, 16, 25)]
+    cs += [(n, k, rand_sync(n, k, i, base=79)) for i, (n, k) in
+           enumerate([(40, 2), (64, 3), (100, 2), (150, 2), (200, 3)])]
+    srw.set_option("small_cand", small)
+    try:
+        for n, k, d in cs:
+            say("one-block steps", small, n, k)
+            assert srw.solve(n, k, d) == O.bidir(n, k, d)[:2]
+        res = srw.solve_batch(cs)
+        for (n, k, d), (st, r, w) in zip(cs, res):
+            assert st == srw.OK and (r, w) == O.bidir(n, k, d)[:2]
+    finally:
+        srw.set_option("small_cand", 2048)

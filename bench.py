@@ -39,25 +39,25 @@ CLASSES = ("expand", "insert", "compact", "prep", "meet", "trace", "setup")
 def workload(name, srw, count=None, nmax=None):
     """List of (n, k, delta, label)."""
     out = []
-    if name == "config3":
+    if name == "mix4096-n32-320-k2-3":
         # the seeded 4096-member batch: n uniform in [32, 320], k in {2, 3};
         # optionally only its first `count` members and those with n <= nmax
-        for m in I.config_mixed(count or 4096, 32, 320, (2, 3), srw.check_sync):
+        for m in I.mixed_batch(count or 4096, 32, 320, (2, 3), srw.check_sync):
             if nmax is None or m["n"] <= nmax:
                 out.append((m["n"], m["k"], m["delta"], f"mix{m['n']}k{m['k']}"))
         return out
-    if name in ("config2", "config2-random"):
+    if name in ("n256k2x10+cerny16-32", "n256k2x10"):
         for i in range(10):
             d, _ = I.first_synchronizing(256, 2, I.member_seed(I.BASE_SEED, i), srw.check_sync)
             out.append((256, 2, d, f"rand256#{i}"))
-        if name == "config2":
+        if name == "n256k2x10+cerny16-32":
             for n in range(16, 33):
                 out.append((n, 2, I.cerny(n), f"cerny{n}"))
-    elif name == "config1":
+    elif name == "n64k2x100":
         for i in range(100):
             d, _ = I.first_synchronizing(64, 2, I.member_seed(I.BASE_SEED, i), srw.check_sync)
             out.append((64, 2, d, f"rand64#{i}"))
-    elif name == "config4":
+    elif name == "n450k2":
         d, _ = I.first_synchronizing(450, 2, I.member_seed(I.BASE_SEED, 0), srw.check_sync)
         out.append((450, 2, d, "rand450#0"))
     else:
@@ -317,7 +317,7 @@ def serve_bench(args, srw):
         "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": elapsed * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u64", "data": "synthetic",
-        "config": {"workload": "config5", "requests": len(reqs), "rate_per_s": rate,
+        "config": {"workload": "serve-mix", "requests": len(reqs), "rate_per_s": rate,
                    "mix": f"90% random n~U[64,{args.serve_nmax}] k~U{{2..{args.serve_kmax}}}, "
                           "10% Cerny n~U[8,40]", "path": "srw_server (continuous batching)"},
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
@@ -334,7 +334,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="config2")
+    ap.add_argument("--workload", default="n256k2x10+cerny16-32")
     ap.add_argument("--cpu-budget", type=float, default=40.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -348,18 +348,18 @@ def main():
     ap.add_argument("--pmc-src", default=KERNEL_SRC,
                     help="with --pmc-summary: the kernel source the counters were taken with")
     ap.add_argument("--count", type=int, default=None,
-                    help="config3: first COUNT members of the seeded 4096-member batch")
+                    help="mix4096-n32-320-k2-3: first COUNT members of the seeded 4096-member batch")
     ap.add_argument("--nmax", type=int, default=None,
-                    help="config3: keep only members with n <= NMAX")
-    ap.add_argument("--requests", type=int, default=400, help="config5: requests")
+                    help="mix4096-n32-320-k2-3: keep only members with n <= NMAX")
+    ap.add_argument("--requests", type=int, default=400, help="serve-mix: requests")
     ap.add_argument("--deadline-ms", type=int, default=20000,
-                    help="config5: per-request deadline on the device (0: none)")
+                    help="serve-mix: per-request deadline on the device (0: none)")
     ap.add_argument("--rate", type=float, default=0.0,
-                    help="config5: Poisson arrivals per second (0: 0.7 x measured capacity)")
-    ap.add_argument("--serve-nmax", type=int, default=400, help="config5: largest random n")
-    ap.add_argument("--serve-kmax", type=int, default=4, help="config5: largest alphabet")
+                    help="serve-mix: Poisson arrivals per second (0: 0.7 x measured capacity)")
+    ap.add_argument("--serve-nmax", type=int, default=400, help="serve-mix: largest random n")
+    ap.add_argument("--serve-kmax", type=int, default=4, help="serve-mix: largest alphabet")
     ap.add_argument("--serve-seconds", type=float, default=90.0,
-                    help="config5: stop waiting for completions after this long")
+                    help="serve-mix: stop waiting for completions after this long")
     args = ap.parse_args()
     if args.oracle_one:
         oracle_one(args.oracle_one)
@@ -374,7 +374,7 @@ def main():
         sys.exit(2)
 
     from paper_2207_05495_amd import srw
-    if args.workload == "config5":
+    if args.workload == "serve-mix":
         import torch
         torch.cuda.set_device(0)
         srw.use_torch(0)
@@ -437,12 +437,12 @@ def main():
         "config": {"workload": args.workload,
                    "automata": len(probs),
                    "sizes": {
-                       "config1": "100 x random n=64 k=2",
-                       "config2-random": "10 x random n=256 k=2",
-                       "config2": "10 x random n=256 k=2 + Cerny C_16..C_32",
-                       "config3": f"first {len(probs)} of the 4096-member batch, "
+                       "n64k2x100": "100 x random n=64 k=2",
+                       "n256k2x10": "10 x random n=256 k=2",
+                       "n256k2x10+cerny16-32": "10 x random n=256 k=2 + Cerny C_16..C_32",
+                       "mix4096-n32-320-k2-3": f"first {len(probs)} of the 4096-member batch, "
                                   "n~U[32,320], k~U{2,3}",
-                       "config4": "1 x random n=450 k=2"}[args.workload]
+                       "n450k2": "1 x random n=450 k=2"}[args.workload]
                    + " (uniform delta, seeded SplitMix64, first synchronizing draw)",
                    "path": "srw_solve_batch"},
         "automata_per_s": len(probs) / per_step,

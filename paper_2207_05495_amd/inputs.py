@@ -141,7 +141,7 @@ def config_single(n: int, k: int, count: int, is_sync, base: int = BASE_SEED):
     return out
 
 
-def config_mixed(count: int, n_lo: int, n_hi: int, ks, is_sync,
+def mixed_batch(count: int, n_lo: int, n_hi: int, ks, is_sync,
                  base: int = BASE_SEED):
     """Random automata with n uniform in [n_lo, n_hi] and k uniform in ks.
 

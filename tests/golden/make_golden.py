@@ -4,7 +4,7 @@ Calls only oracle/ and the shared input generator: the stored values never
 come from the GPU path.  Each entry records the generator seed and attempt,
 so a test can rebuild the exact automaton.
 
-    python tests/golden/make_golden.py config2     # n=256, k=2, 10 seeds
+    python tests/golden/make_golden.py rand256     # n=256, k=2, 10 seeds
     python tests/golden/make_golden.py mixed       # smaller mixed sizes
 """
 
@@ -34,7 +34,7 @@ def solve_one(args):
 
 
 def jobs(which):
-    if which == "config2":
+    if which == "rand256":
         return [(256, 2, I.member_seed(I.BASE_SEED, i)) for i in range(10)]
     if which == "mixed":
         out = []
@@ -46,7 +46,7 @@ def jobs(which):
 
 
 def main():
-    which = sys.argv[1] if len(sys.argv) > 1 else "config2"
+    which = sys.argv[1] if len(sys.argv) > 1 else "rand256"
     procs = int(sys.argv[2]) if len(sys.argv) > 2 else 6
     js = jobs(which)
     with Pool(procs) as p:

@@ -73,7 +73,7 @@ def test_cerny(n):
 
 # ------------------------------------------------------ random vs oracle
 
-def test_config1_n64_k2_100_seeds():
+def test_random_n64_k2_100_seeds():
     """n=64, k=2, one 64-bit word per subset: 100 seeds."""
     for i in range(100):
         d = rand_sync(64, 2, i)
@@ -367,36 +367,36 @@ def golden(name):
         return json.load(f)["cases"]
 
 
-def test_config2_n256_against_stored_oracle_values():
+def test_random_n256_against_stored_oracle_values():
     """n=256, k=2, four 64-bit words per subset: r and word of every seed
     equal the oracle's stored values (tests/golden/make_golden.py)."""
-    for c in golden("config2.json"):
+    for c in golden("rand256.json"):
         n, k = c["n"], c["k"]
         d = I.random_automaton(n, k, c["seed"], c["attempt"])
-        say("config2 seed", c["seed"])
+        say("n256 seed", c["seed"])
         r, w = srw.solve(n, k, d)
         assert r == c["r"]
         assert "".join(map(str, w)) == c["word"]
 
 
-def test_config2_lds_tile_meet_equals_stored():
-    cs = golden("config2.json")[:2]
+def test_random_n256_lds_tile_meet_equals_stored():
+    cs = golden("rand256.json")[:2]
     srw.set_option("meet", 1)
     try:
         for c in cs:
             d = I.random_automaton(c["n"], c["k"], c["seed"], c["attempt"])
-            say("config2 lds-tile meet seed", c["seed"])
+            say("n256 lds-tile meet seed", c["seed"])
             r, w = srw.solve(c["n"], c["k"], d)
             assert r == c["r"] and "".join(map(str, w)) == c["word"]
     finally:
         srw.set_option("meet", 0)
 
 
-def test_config2_batched_equals_stored():
-    cs = golden("config2.json")
+def test_random_n256_batched_equals_stored():
+    cs = golden("rand256.json")
     probs = [(c["n"], c["k"], I.random_automaton(c["n"], c["k"], c["seed"], c["attempt"]))
              for c in cs]
-    say("config2 batched")
+    say("n256 batched")
     res = srw.solve_batch(probs)
     for c, (st, r, w) in zip(cs, res):
         assert st == srw.OK and r == c["r"] and "".join(map(str, w)) == c["word"]

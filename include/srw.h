@@ -147,11 +147,15 @@ int srw_set_stream(void *hip_stream);
  *                 candidate sets (capped at 512) test them by signature,
  *                 larger ones AND columns
  *   "meet_groups" chunked meet: groups of 64 tiles per work item (at most;
- *                 default 32)
+ *                 default 16)
  *   "meet_order"  chunked meet work items: 1 chunk-major (default), 0 tile-
  *                 range-major (consecutive items share one range of tiles)
  *   "meet_grid"   meet blocks per launch, grid-striding over the work items
  *                 (0: one block per work item, up to 2^31-1)
+ *   "ysort"       new inverse levels of at least this many candidates are
+ *                 kept in order of decreasing cardinality for the meet, so
+ *                 that forward sets scan only large enough inverse sets
+ *                 (0, the default: never; the same results either way)
  *   "small_cand"  steps with at most this many candidates (and a small
  *                 LDS-tile meet) run in one block, one launch for the whole
  *                 step (default 2048; 0: never)

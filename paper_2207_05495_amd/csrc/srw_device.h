@@ -75,7 +75,14 @@ struct StepDesc {
     int32_t tpb;               // mode 0: tiles per meet block
     int32_t meet_mode;         // 0: LDS tiles, 1: sorted 64-set chunks
     int32_t small;             // 1: the whole step runs in one block (k_step_small)
-    int32_t pad2;
+    int32_t ysort;             // 1: sort the new inverse level by cardinality (dir 1)
+    // the inverse level in cardinality order, largest first (null: level order)
+    const u32 *Yidx;           // sorted position -> index in the level
+    const u32 *Ycnt;           // Ycnt[c] = sets of the level with at least c states, c = 0..n+1
+    // the sort of a new inverse level
+    u32 *ys_hist;              // n + 1 counters
+    u32 *ys_cnt;               // n + 2 entries
+    u32 *ys_idx;               // position -> index
     const u32 *Xidx;           // mode 1: rank of each sorted X in its level
     const u64 *Xcom;           // mode 1: AND of the 64 sets of each chunk
     int64_t gitems_ub;         // mode 1: work items per chunk (upper bound)

@@ -36,6 +36,7 @@ hipError_t launch_transpose_rows(const TransposeDesc *, const int64_t *, int, in
 hipError_t launch_meet(const StepDesc *, const int64_t *, int, int, int, int64_t, int64_t, u64 *, hipStream_t);
 hipError_t launch_step_small(const StepDesc *, const int32_t *, int, u64 *, hipStream_t);
 hipError_t launch_copy(const CopyDesc *, const int64_t *, int, int64_t, hipStream_t);
+hipError_t launch_ysort(const StepDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_init(const InitDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_rehash(const RehashDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_fill(u64 *, int64_t, u64, hipStream_t);
@@ -328,6 +329,10 @@ struct Problem {
     int64_t colT_cap = 0;     // words
     u64 *ysig = nullptr;      // signature (OR of the words) of each set of the current inverse level
     int64_t ysig_cap = 0;     // words
+    // cardinality order of the current inverse level (ys_valid: it is in that order)
+    u32 *ys_hist = nullptr, *ys_cnt = nullptr, *ys_idx = nullptr;
+    int64_t ys_cap = 0;
+    bool ys_valid = false;
     u64 *cand = nullptr;
     int64_t cand_cap = 0;     // rows
     u32 *cslot = nullptr;
@@ -361,8 +366,9 @@ struct Options {
     uint64_t sched_seed = 1;
     int meet_tiles = 0;
     int64_t meet_rows = kRowBatchMax;   // chunked meet: row tests up to this many candidates per group
-    int64_t meet_groups = 32;           // chunked meet: tile groups per work item (upper limit)
+    int64_t meet_groups = 16;           // chunked meet: tile groups per work item (upper limit)
     int64_t small_cand = 2048;          // steps with at most this many candidates run in one block (0: never)
+    int64_t ysort = 0;                  // new inverse levels of at least this many candidates go in cardinality order (0: never)
     int64_t meet_grid = 0;              // meet blocks per launch (0: one per work item)
     int64_t meet_order = 1;             // chunked meet items: 0 tile-range-major, 1 chunk-major
     int profile = 0;                    // 1: every kernel class and the meet; 2: the meet only
@@ -663,7 +669,7 @@ class Engine {
 
         // descriptors
         std::vector<StepDesc> D(nseg);
-        std::vector<int64_t> pe(nseg + 1, 0), pc(nseg + 1, 0), pt(nseg + 1, 0), pm(nseg + 1, 0);
+        std::vector<int64_t> pe(nseg + 1, 0), pc(nseg + 1, 0), pt(nseg + 1, 0), pm(nseg + 1, 0), pq(nseg + 1, 0);
         std::vector<SortDesc> S;
         std::vector<int64_t> pz(1, 0), pr(1, 0), pch(1, 0);
         std::vector<int32_t> small;                // segments whose whole step runs in one block
@@ -756,6 +762,19 @@ class Engine {
                 pm[i + 1] = pm[i];
                 small.push_back(i);
             }
+            if (dir == 0 && p->ys_valid) {         // the current inverse level is in cardinality order
+                d.Yidx = p->ys_idx;
+                d.Ycnt = p->ys_cnt;
+            }
+            if (dir == 1 && !d.small && opt.ysort > 0 && d.C >= opt.ysort && ensure_ysort(p, d.C)) {
+                d.ysort = 1;
+                d.ys_hist = p->ys_hist;
+                d.ys_cnt = p->ys_cnt;
+                d.ys_idx = p->ys_idx;
+                d.Yidx = p->ys_idx;
+                d.Ycnt = p->ys_cnt;
+            }
+            pq[i + 1] = pq[i] + (d.ysort ? ceil_div(d.C, kBS) : 0);
             pe[i + 1] = pe[i] + (d.small ? 0 : ceil_div(d.C, kBS));
             pc[i + 1] = pc[i] + (d.small ? 0 : d.ncblk);
             pt[i + 1] = pt[i] + (d.small ? 0 : ceil_div(d.ntr_waves, kBS / 64));
@@ -780,7 +799,7 @@ class Engine {
         const size_t szS = align8(sizeof(SortDesc) * nsort), szQ = align8(8 * (nsort + 1));
         const int nsmall = (int)small.size();
         const size_t szL = align8(4 * (size_t)std::max(1, nsmall));
-        const size_t total = szD + 4 * szP + szS + 3 * szQ + szL;
+        const size_t total = szD + 4 * szP + szS + 3 * szQ + szL + szP;
         char *h = (char *)pin_step_.need(total);
         memcpy(h, D.data(), sizeof(StepDesc) * nseg);
         memcpy(h + szD, pe.data(), 8 * (nseg + 1));
@@ -794,6 +813,8 @@ class Engine {
         memcpy(h + oS + szS + 2 * szQ, pch.data(), 8 * (nsort + 1));
         const size_t oL = oS + szS + 3 * szQ;
         if (nsmall) memcpy(h + oL, small.data(), 4 * nsmall);
+        const size_t oQ = oL + szL;
+        memcpy(h + oQ, pq.data(), 8 * (nseg + 1));
         char *dblob = dev_need(step_blob_, step_blob_cap_, total);
         HIPCHK(hipMemcpyAsync(dblob, h, total, hipMemcpyHostToDevice, stream_));
         const StepDesc *dD = (const StepDesc *)dblob;
@@ -807,6 +828,7 @@ class Engine {
                                        (const int64_t *)(dblob + oS + szS + 2 * szQ)};
         const int64_t sblocks[3] = {pz.back(), pr.back(), pch.back()};
         const int32_t *dsmall = (const int32_t *)(dblob + oL);
+        const int64_t *dpq = (const int64_t *)(dblob + oQ);
 
         if (opt.profile && !d_ops_) {
             d_ops_ = (u64 *)pool_->alloc(kOpsWords * sizeof(u64));
@@ -827,6 +849,7 @@ class Engine {
         prof_end(2);
         if (pt[nseg] > 0 || nsort > 0) {
             prof_begin(3);
+            HIPCHK(launch_ysort(dD, dpq, nseg, pq[nseg], stream_));
             HIPCHK(launch_transpose(dD, dpt, nseg, pt[nseg], stream_));
             HIPCHK(launch_sort(dS, dsp, sblocks, nsort, stream_));
             prof_end(3);
@@ -879,6 +902,7 @@ class Engine {
             s.nrows += U;
             s.off.push_back(s.nrows);
             if (dir == 0) p->xs_valid = p->sort_now;
+            if (dir == 1) p->ys_valid = d.ysort != 0;
             p->sort_now = false;
             p->steps++;
             stats_.steps++;
@@ -959,6 +983,21 @@ class Engine {
         }
         ptr = q;
         cap = nc;
+        return true;
+    }
+
+    // buffers for the cardinality order of an inverse level of up to C sets
+    bool ensure_ysort(Problem *p, int64_t C) {
+        if (!p->ys_hist) {
+            p->ys_hist = (u32 *)pool_->alloc((size_t)(p->n + 1) * 4);
+            p->ys_cnt = (u32 *)pool_->alloc((size_t)(p->n + 2) * 4);
+            if (!p->ys_hist || !p->ys_cnt) return false;
+        }
+        void *pp = p->ys_idx;
+        int64_t cap = p->ys_cap;
+        if (!dev_grow(pp, cap, C, 4, 0)) return false;
+        p->ys_idx = (u32 *)pp;
+        p->ys_cap = cap;
         return true;
     }
 
@@ -1133,6 +1172,10 @@ class Engine {
         }
         pool_->free(p->colT); p->colT = nullptr; p->colT_cap = 0;
         pool_->free(p->ysig); p->ysig = nullptr; p->ysig_cap = 0;
+        pool_->free(p->ys_hist); pool_->free(p->ys_cnt); pool_->free(p->ys_idx);
+        p->ys_hist = p->ys_cnt = p->ys_idx = nullptr;
+        p->ys_cap = 0;
+        p->ys_valid = false;
         pool_->free(p->cand); p->cand = nullptr; p->cand_cap = 0;
         pool_->free(p->cslot); p->cslot = nullptr; p->cslot_cap = 0;
         for (void *q : {(void *)p->xs_rows, (void *)p->xs_com, (void *)p->xs_idx, (void *)p->xs_keys,
@@ -1367,6 +1410,7 @@ int srw_set_option(const char *key, int64_t v) {
     std::lock_guard<std::mutex> g(x.mu);
     std::string k(key);
     if (k == "budget") {
+        if (v < 0) return set_error(SRW_EINVAL, "budget < 0");
         x.budget = v;
         if (x.eng) {
             try {
@@ -1387,6 +1431,7 @@ int srw_set_option(const char *key, int64_t v) {
     else if (k == "deadline_ms") { if (v < 0) return set_error(SRW_EINVAL, "deadline_ms"); x.opt.deadline_ms = (double)v; }
     else if (k == "meet") { if (v < 0 || v > 2) return set_error(SRW_EINVAL, "meet"); x.opt.meet = (int)v; }
     else if (k == "meet_rows") { if (v < 0) return set_error(SRW_EINVAL, "meet_rows"); x.opt.meet_rows = v; }
+    else if (k == "ysort") { if (v < 0) return set_error(SRW_EINVAL, "ysort"); x.opt.ysort = v; }
     else if (k == "small_cand") { if (v < 0 || v > (1 << 20)) return set_error(SRW_EINVAL, "small_cand"); x.opt.small_cand = v; }
     else if (k == "meet_groups") { if (v < 1 || v > 4096) return set_error(SRW_EINVAL, "meet_groups"); x.opt.meet_groups = v; }
     else if (k == "meet_grid") { if (v < 0) return set_error(SRW_EINVAL, "meet_grid"); x.opt.meet_grid = v; }

@@ -317,14 +317,16 @@ __global__ void __launch_bounds__(kBS) k_compact(const StepDesc *descs, const in
 // state-major at YT[q * nt + tile] (nt = number of tiles) and tile-major at
 // YTt[tile * 64W + q].
 __device__ __forceinline__ void transpose_tile(const u64 *rows, int64_t count, int W, u64 *YT,
-                                               u64 *YTt, u64 *Ysig, int64_t tile, int w) {
+                                               u64 *YTt, u64 *Ysig, int64_t tile, int w,
+                                               const u32 *perm = nullptr) {
     const int lane = threadIdx.x & 63;
     const int64_t j = tile * 64 + lane;
     const int64_t nt = (count + 63) / 64;
-    const u64 v = j < count ? rows[j * W + w] : 0ull;
+    const int64_t src = j < count ? (perm ? (int64_t)perm[j] : j) : 0;   // row j of the (sorted) level
+    const u64 v = j < count ? rows[src * W + w] : 0ull;
     if (w == 0) {                       // the set's signature (0 past the end)
         u64 f = 0;
-        for (int ww = 0; ww < W; ++ww) f |= j < count ? rows[j * W + ww] : 0ull;
+        for (int ww = 0; ww < W; ++ww) f |= j < count ? rows[src * W + ww] : 0ull;
         Ysig[j] = f;
     }
     u64 col = 0;
@@ -346,7 +348,61 @@ __global__ void __launch_bounds__(kBS) k_transpose(const StepDesc *descs, const 
     const int64_t tile = wv / d.W;
     const int w = (int)(wv - tile * d.W);
     if (tile * 64 >= count) return;
-    transpose_tile(d.out_rows, count, d.W, d.YT, d.YTt, d.Ysig, tile, w);
+    transpose_tile(d.out_rows, count, d.W, d.YT, d.YTt, d.Ysig, tile, w, d.ysort ? d.ys_idx : nullptr);
+}
+
+// ------------------------------------ cardinality order of an inverse level
+
+// A set X can lie in Y only if |X| <= |Y|.  A large new inverse level is
+// put in order of decreasing cardinality (ties in any order: the meet
+// resolves the least index pair through Yidx, whatever the order), so that a
+// chunk of forward sets scans only the tiles of sets at least as large as its
+// smallest member.
+__global__ void __launch_bounds__(kBS) k_ysort_zero(const StepDesc *descs, int nseg) {
+    const CONST_AS StepDesc &d = cref(descs + blockIdx.x);
+    if (!d.ysort) return;
+    for (int c = threadIdx.x; c <= d.n; c += kBS) d.ys_hist[c] = 0;
+}
+__global__ void __launch_bounds__(kBS) k_ysort_hist(const StepDesc *descs, const int64_t *pre, int nseg) {
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const CONST_AS StepDesc &d = cref(descs + s);
+    const int64_t j = ((int64_t)blockIdx.x - cref(pre + s)) * kBS + threadIdx.x;
+    if (j >= (int64_t)d.res[0]) return;
+    int c = 0;
+    for (int w = 0; w < d.W; ++w) c += __popcll(d.out_rows[j * d.W + w]);
+    atomicAdd(d.ys_hist + c, 1u);
+}
+// one block per segment: Ycnt, and ys_hist turned into the first position
+// of each cardinality (largest first)
+__global__ void __launch_bounds__(kBS) k_ysort_scan(const StepDesc *descs, int nseg) {
+    __shared__ u32 h[kMaxW * 64 + 1];       // n + 1 cardinalities
+    const CONST_AS StepDesc &d = cref(descs + blockIdx.x);
+    if (!d.ysort) return;
+    for (int c = threadIdx.x; c <= d.n; c += kBS) h[c] = d.ys_hist[c];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u32 acc = 0;                        // sets with more than c states
+        for (int c = d.n; c >= 0; --c) {
+            const u32 v = h[c];
+            h[c] = acc;
+            acc += v;
+        }
+        d.ys_cnt[0] = acc;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c <= d.n; c += kBS) {
+        d.ys_hist[c] = h[c];
+        d.ys_cnt[c + 1] = h[c];
+    }
+}
+__global__ void __launch_bounds__(kBS) k_ysort_scatter(const StepDesc *descs, const int64_t *pre, int nseg) {
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const CONST_AS StepDesc &d = cref(descs + s);
+    const int64_t j = ((int64_t)blockIdx.x - cref(pre + s)) * kBS + threadIdx.x;
+    if (j >= (int64_t)d.res[0]) return;
+    int c = 0;
+    for (int w = 0; w < d.W; ++w) c += __popcll(d.out_rows[j * d.W + w]);
+    d.ys_idx[atomicAdd(d.ys_hist + c, 1u)] = (u32)j;
 }
 
 __global__ void __launch_bounds__(kBS) k_transpose_rows(const TransposeDesc *descs, const int64_t *pre,
@@ -402,9 +458,13 @@ __device__ u32 meet_w(const CONST_AS StepDesc &d, int64_t lb, u64 *cols) {
             }
         }
         if (alive) {
-            const u64 j = (u64)t * 64 + (u64)lowest_bit(M);
-            atomicMin(d.res + 1, ((u64)i << 32) | j);
-            return nops;
+            if (!d.Yidx) {                 // level order: the lowest bit is the least j
+                const u64 j = (u64)t * 64 + (u64)lowest_bit(M);
+                atomicMin(d.res + 1, ((u64)i << 32) | j);
+                return nops;
+            }
+            for (u64 mm = M; mm; mm &= mm - 1)   // cardinality order: every hit
+                atomicMin(d.res + 1, ((u64)i << 32) | (u64)d.Yidx[(u64)t * 64 + lowest_bit(mm)]);
         }
     }
     return nops;
@@ -457,7 +517,7 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
     else { c = udiv(item, d.gitems_ub); gi = item - c * d.gitems_ub; }
     if (c * 64 >= nX) return 0;                    // whole wave
     const int64_t g0 = gi * d.ngi;
-    const int64_t g1 = min(g0 + d.ngi, ngroups);
+    int64_t g1 = min(g0 + d.ngi, ngroups);
     if (g0 >= g1) return 0;                        // whole wave
     const int64_t is = c * 64 + lane;
     const bool valid = is < nX;
@@ -496,6 +556,23 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
     // 64-bit AND of a column, 4 per word of a row test (and-not, or)
     u32 nops = 0;
     const u32 orig = valid ? d.Xidx[is] : 0xFFFFFFFFu;
+    // inverse level in cardinality order: only its first Ycnt[min |X|] sets
+    // can contain a set of this chunk
+    int64_t nt_lim = nt;
+    if (d.Ycnt) {
+        int sz = 0x7fffffff;
+        if (valid) {
+            sz = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) sz += __popcll(x[w]);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) sz = min(sz, __shfl_xor(sz, off, 64));
+        int csz = 0;                       // the states of C taken out of each x
+#pragma unroll
+        for (int r = 0; r < kCommonMax; ++r) csz += cq[r] >= 0;
+        nt_lim = ((int64_t)d.Ycnt[min(sz + csz, d.n + 1)] + 63) / 64;
+    }
     bool done = !valid || (load_slot(d.res + 1) >> 32) < (u64)orig;
     // slice: candidate indices (u32) in words 0 .. kRowBatchMax/2-1, their
     // signatures after them
@@ -504,26 +581,31 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
     u64 xs = 0;
 #pragma unroll
     for (int w = 0; w < W; ++w) xs |= x[w];
-    // first round of common columns of group gg (loaded one group ahead)
+    // first round of common columns of group gg, loaded two groups ahead
+    // (a group with no candidate is a few dozen instructions, far shorter than
+    // a load).  Lanes past the last tile and unused states load word 0 of YT
+    // and drop it, so the loads need no branch.
     auto first_round = [&](int64_t gg, u64 *v) {
         const int64_t tg = gg * 64 + lane;
 #pragma unroll
-        for (int r = 0; r < kCommonRound; ++r)
-            v[r] = (tg < nt && cq[r] >= 0) ? d.YT[(int64_t)cq[r] * nt + tg] : ~0ull;
+        for (int r = 0; r < kCommonRound; ++r) {
+            const bool ok = tg < nt && cq[r] >= 0;
+            const u64 w = d.YT[ok ? (int64_t)cq[r] * nt + tg : 0];
+            v[r] = ok ? w : ~0ull;
+        }
     };
-    u64 pre[kCommonRound];
-    first_round(g0, pre);
-    for (int64_t g = g0; g < g1; ++g) {
-        if (__ballot(!done) == 0) break;
+    const u64 last_rows = (nY & 63) ? ((1ull << (nY & 63)) - 1ull) : ~0ull;   // the last tile may be partial
+    // one group with its first-round columns in cur; refills cur for group g + 2.
+    // false: every lane of the wave is done
+    auto group = [&](int64_t g, u64 *cur) -> bool {
+        if (__ballot(!done) == 0) return false;
         const int64_t t = g * 64 + lane;
-        const bool tv = t < nt;
-        // rows of tile t that exist (the last tile may be partial)
-        const int64_t rows_left = nY - t * 64;
-        u64 m = !tv ? 0ull : (rows_left >= 64 ? ~0ull : ((1ull << rows_left) - 1ull));
+        const bool tv = t < nt_lim;
+        u64 m = !tv ? 0ull : (t == nt - 1 ? last_rows : ~0ull);
 #pragma unroll
-        for (int r = 0; r < kCommonRound; ++r) m &= pre[r];
+        for (int r = 0; r < kCommonRound; ++r) m &= cur[r];
         if (tv) nops += 2 * min(nc, kCommonRound);
-        if (g + 1 < g1) first_round(g + 1, pre);
+        if (g + 2 < g1) first_round(g + 2, cur);
         // further common columns, in rounds of independent loads
 #pragma unroll
         for (int r0 = kCommonRound; r0 < kCommonMax; r0 += kCommonRound) {
@@ -536,7 +618,7 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
             for (int r = 0; r < kCommonRound; ++r) m &= v[r];
             if (tv) nops += 2 * min(nc - r0, kCommonRound);
         }
-        if (__ballot(m != 0) == 0) continue;      // the usual case: no candidate in the group
+        if (__ballot(m != 0) == 0) return true;      // the usual case: no candidate in the group
         // number the candidates: lane order (tile), then bit order
         const u32 pc = (u32)__popcll(m);
         u32 incl = pc;
@@ -546,7 +628,7 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
             if (lane >= off) incl += o;
         }
         const u32 K = (u32)__shfl((int)incl, 63, 64);
-        if (K == 0) continue;
+        if (K == 0) return true;
         if (K <= (u32)d.row_batch_max) {              // row_batch_max <= kRowBatchMax
             wave_sync_lds();                           // the last group's lists are read
             {
@@ -581,19 +663,19 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
                     for (int u = 0; u < 4; ++u) {
                         const u32 cc = c0 + u;
                         if (done || cc >= K || (xs & ~sig[cc]) != 0) continue;
-                        const u32 jc = jl[cc];
+                        const u32 jc = d.Yidx ? d.Yidx[jl[cc]] : jl[cc];   // index in the level
                         u64 out = 0;
 #pragma unroll
                         for (int w = 0; w < W; ++w) out |= x[w] & ~d.Yrows[(int64_t)jc * W + w];
                         nops += 4 * W;
                         if (out == 0) {
                             atomicMin(d.res + 1, ((u64)orig << 32) | (u64)jc);
-                            done = true;
+                            done = !d.Yidx;        // cardinality order: a later hit may be smaller
                         }
                     }
                 }
             }
-            continue;
+            return true;
         }
         // many candidates: per surviving tile, stage its columns in LDS
         // (coalesced, tile-major) and AND the remaining states of each X
@@ -624,10 +706,24 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
                 nops += 2 * (u32)(__popcll(x[w]) - __popcll(b));
             }
             if (alive) {
-                atomicMin(d.res + 1, ((u64)orig << 32) | (u64)(tt * 64 + lowest_bit(M)));
-                done = true;
+                if (!d.Yidx) {
+                    atomicMin(d.res + 1, ((u64)orig << 32) | (u64)(tt * 64 + lowest_bit(M)));
+                    done = true;
+                } else {
+                    for (u64 mm = M; mm; mm &= mm - 1)
+                        atomicMin(d.res + 1, ((u64)orig << 32) | (u64)d.Yidx[tt * 64 + lowest_bit(mm)]);
+                }
             }
         }
+        return true;
+    };
+    g1 = min(g1, (nt_lim + 63) / 64);
+    u64 pa[kCommonRound], pb[kCommonRound];
+    if (g0 < g1) first_round(g0, pa);
+    if (g0 + 1 < g1) first_round(g0 + 1, pb);
+    for (int64_t g = g0; g < g1; g += 2) {
+        if (!group(g, pa)) break;
+        if (g + 1 < g1 && !group(g + 1, pb)) break;
     }
     return nops;
 }
@@ -975,6 +1071,16 @@ __global__ void k_trace(const TraceDesc *descs, int count) {
 
 static inline hipError_t launch_checked() { return hipGetLastError(); }
 
+// cardinality order of the new inverse levels of the segments with ysort set;
+// pre: blocks of kBS sets per such segment
+hipError_t launch_ysort(const StepDesc *d, const int64_t *pre, int nseg, int64_t blocks, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ysort_zero, dim3((unsigned)nseg), dim3(kBS), 0, st, d, nseg);
+    hipLaunchKernelGGL(k_ysort_hist, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
+    hipLaunchKernelGGL(k_ysort_scan, dim3((unsigned)nseg), dim3(kBS), 0, st, d, nseg);
+    hipLaunchKernelGGL(k_ysort_scatter, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
+    return launch_checked();
+}
 hipError_t launch_copy(const CopyDesc *d, const int64_t *pre, int nseg, int64_t blocks, hipStream_t st) {
     if (blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);

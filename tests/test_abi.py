@@ -116,3 +116,54 @@ def test_estimator_inputs_generator_is_deterministic():
     # splitmix64 reference values of the published generator (seed 0)
     x = I.splitmix64_stream(0, 0, 3)
     assert [int(v) for v in x] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_every_documented_option_is_accepted_and_checked():
+    """Each key the header documents is accepted with its default value;
+    out-of-range values are SRW_EINVAL (no device needed to set options)."""
+    import re
+    with open(os.path.join(ROOT, "include", "srw.h")) as f:
+        head = f.read()
+    block = head[head.index("Tuning and test options"):head.index("int srw_set_option")]
+    keys = re.findall(r'^ \*   "(\w+)"', block, re.M)
+    defaults = {"budget": 0, "max_slots": 4096, "profile": 0, "schedule": 0, "sched_seed": 0,
+                "meet": 0, "meet_tiles": 0, "meet_rows": 512, "meet_groups": 16, "meet_order": 1,
+                "meet_grid": 0, "ysort": 0, "small_cand": 2048, "deadline_ms": 0,
+                "verbose": 0, "keep_levels": 0}
+    assert set(keys) == set(defaults), set(keys) ^ set(defaults)
+    for k in keys:
+        srw.set_option(k, defaults[k])
+    bad = {"profile": 3, "schedule": 3, "meet": 3, "meet_order": 2, "meet_groups": 0,
+           "meet_tiles": 1000, "ysort": -1, "small_cand": -1, "meet_grid": -1, "budget": -5}
+    for k, v in bad.items():
+        with pytest.raises(srw.SrwError) as e:
+            srw.set_option(k, v)
+        assert e.value.code == srw.EINVAL, k
+        srw.set_option(k, defaults[k])
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of srw_stats, srw_config and srw_result have the C
+    sizes and field offsets (gcc on include/srw.h)."""
+    import ctypes
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    structs = {"srw_stats": srw.Stats, "srw_config": srw.Config, "srw_result": srw.Result}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "srw.h"', 'int main(void) {']
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append('return 0; }')
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        cname, what, val = line.split()
+        py = structs[cname]
+        want = ctypes.sizeof(py) if what == "size" else getattr(py, what).offset
+        assert int(val) == want, (cname, what, int(val), want)

@@ -33,8 +33,9 @@ def gpu():
 
 
 DEFAULTS = (("schedule", 0), ("meet_tiles", 0), ("keep_levels", 0), ("budget", 0), ("meet", 0),
-            ("max_slots", 4096), ("meet_rows", 512), ("meet_groups", 32), ("meet_order", 1),
-            ("meet_grid", 0), ("small_cand", 2048), ("deadline_ms", 0), ("verbose", 0))
+            ("max_slots", 4096), ("meet_rows", 512), ("meet_groups", 16), ("meet_order", 1),
+            ("meet_grid", 0), ("small_cand", 2048), ("ysort", 0), ("deadline_ms", 0),
+            ("verbose", 0))
 
 
 def say(*a):
@@ -342,7 +343,7 @@ def test_meet_tuning_options_keep_results(rows, groups, order, grid):
             assert srw.solve(n, k, d) == O.bidir(n, k, d)[:2]
     finally:
         srw.set_option("meet_rows", 512)
-        srw.set_option("meet_groups", 32)
+        srw.set_option("meet_groups", 16)
         srw.set_option("meet_order", 1)
         srw.set_option("meet_grid", 0)
 
@@ -442,3 +443,31 @@ def test_one_block_steps_keep_results(small):
             assert st == srw.OK and (r, w) == O.bidir(n, k, d)[:2]
     finally:
         srw.set_option("small_cand", 2048)
+
+
+@pytest.mark.parametrize("ysort", [0, 1])
+def test_cardinality_order_keeps_results(ysort):
+    """Inverse levels in order of decreasing cardinality (every level with
+    ysort 1) and in level order give the least index pair alike, in both meet
+    modes and batched; n=256 against the stored oracle values."""
+    cs = [(n, k, rand_sync(n, k, i, base=83)) for i, (n, k) in
+          enumerate([(70, 2), (130, 2), (100, 3), (160, 2)])]
+    want = [O.bidir(n, k, d)[:2] for n, k, d in cs]
+    g = golden("rand256.json")[:3]
+    cs += [(c["n"], c["k"], I.random_automaton(c["n"], c["k"], c["seed"], c["attempt"])) for c in g]
+    want += [(c["r"], [int(ch) for ch in c["word"]]) for c in g]
+    srw.set_option("ysort", ysort)
+    try:
+        for meet in (0, 1, 2):
+            srw.set_option("meet", meet)
+            for (n, k, d), ww in zip(cs, want):
+                say("cardinality order", ysort, "meet", meet, n, k)
+                r, w = srw.solve(n, k, d)
+                assert (r, list(w)) == (ww[0], list(ww[1]))
+        srw.set_option("meet", 0)
+        res = srw.solve_batch(cs)
+        for (st, r, w), ww in zip(res, want):
+            assert st == srw.OK and (r, list(w)) == (ww[0], list(ww[1]))
+    finally:
+        srw.set_option("meet", 0)
+        srw.set_option("ysort", 0)

@@ -471,3 +471,24 @@ def test_cardinality_order_keeps_results(ysort):
     finally:
         srw.set_option("meet", 0)
         srw.set_option("ysort", 0)
+
+
+def test_edge_shapes():
+    """One letter (a path into a fixed point: r = n - 1), 255 letters,
+    an empty batch and a batch that repeats one automaton."""
+    for n in (2, 5, 64, 65, 200):
+        d = np.array([max(q - 1, 0) for q in range(n)], np.int32)   # q -> q-1, 0 fixed
+        say("one letter path", n)
+        assert srw.solve(n, 1, d) == (n - 1, [0] * (n - 1))
+    rng = np.random.default_rng(5)
+    for n in (3, 6, 9):                    # 255-way branching: small n keeps the oracle quick
+        d = rng.integers(0, n, size=255 * n).astype(np.int32)
+        if not srw.check_sync(n, 255, d):
+            continue
+        say("255 letters", n)
+        assert srw.solve(n, 255, d) == O.bidir(n, 255, d)[:2]
+    assert srw.solve_batch([]) == []
+    d = rand_sync(90, 2, 0, base=89)
+    res = srw.solve_batch([(90, 2, d)] * 5)
+    want = O.bidir(90, 2, d)[:2]
+    assert all(st == srw.OK and (r, w) == want for st, r, w in res)

@@ -123,9 +123,16 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2207_05495_amd", "csrc", "srw_kernels.hip
 
 
 def source_sha1(path=KERNEL_SRC):
+    """SHA-1 of the kernel source without its comments and blank lines: the
+    code the counters describe (an edit of comments alone leaves it)."""
     import hashlib
-    with open(path, "rb") as f:
-        return hashlib.sha1(f.read()).hexdigest()
+    import re
+    with open(path) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    lines = [ln.rstrip() for ln in text.splitlines() if ln.strip()]
+    return hashlib.sha1("\n".join(lines).encode()).hexdigest()
 
 
 def pmc_summary(fetch_csv, write_csv, workload, out_path, src=KERNEL_SRC):

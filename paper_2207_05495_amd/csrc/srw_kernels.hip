@@ -15,11 +15,17 @@
 //               stream compaction of the winners in key order into the new
 //               level, with the parent key stored per row (predecessor
 //               pointers, end of the Section 2 intro).
-//   k_transpose a new inverse level into 64-set tiles of column words.
+//   k_transpose a new inverse level into 64-set tiles of column words, plus
+//               one signature word (OR of the set's words) per set.
+//   k_sort_*    bucket sort of a large new forward level into 64-set chunks
+//               with their common states, for the chunked meet.
 //   k_meet      the meet test of Alg. 1: least (i, j) with X_i subset of Y_j
 //               (Section 2: X in the BFS list, Y in the IBFS list).  Bit-
 //               sliced: for a tile of 64 sets Y, the AND of the columns of
 //               the states of X has bit j set iff X is a subset of Y_j.
+//   k_step_small  a whole step of one small segment in one block.
+//   k_copy, k_init, k_rehash, k_clear_tables, k_fill
+//               growth of buffers and hash tables, level 0.
 //   k_trace     walks the parent keys back to the reset word.
 //
 // All arithmetic is exact integer / bitwise.  Subsets are W = ceil(n/64)

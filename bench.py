@@ -240,10 +240,12 @@ def class_table(stats):
         if c in out and stats["ms"][c] > 0:
             out[c]["GBps"] = round(b / (stats["ms"][c] / 1e3) / 1e9, 1)
             out[c]["hbm_frac"] = round(b / (stats["ms"][c] / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
-    # hash probes: every candidate probes the table at least once (one CAS on
-    # a free slot, or a compare with an equal set)
-    if "insert" in out and stats["ms"]["insert"] > 0:
-        out["insert"]["candidates_per_s"] = stats["candidates"] / (stats["ms"]["insert"] / 1e3)
+    # candidates over the time of the kernels that expand, insert (hash
+    # probes: at least one per candidate) and compact them; one-block steps
+    # are timed with the expansion class
+    t_exp = sum(stats["ms"][c] for c in ("expand", "insert", "compact"))
+    if t_exp > 0:
+        out["expansion_candidates_per_s"] = stats["candidates"] / (t_exp / 1e3)
     if "meet" in out and stats["ms"]["meet"] > 0:
         out["meet"]["pairs_per_s"] = stats["pairs"] / (stats["ms"]["meet"] / 1e3)
     return out

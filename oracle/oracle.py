@@ -71,6 +71,7 @@ def bind(path):
                                 u8p, ctypes.c_int, ctypes.c_int,
                                 i32p, u8p, ctypes.c_int64, u8p, i64p,
                                 ctypes.POINTER(ctypes.c_void_p)]
+        L.orc_bidir_reduced.argtypes = L.orc_bidir.argtypes
         L.orc_levels.argtypes = [ctypes.c_void_p, ctypes.c_int, i32p, i64p, i64p,
                                  u64p, i64p]
         L.orc_free.argtypes = [ctypes.c_void_p]
@@ -169,9 +170,10 @@ STAT_NAMES = ("steps", "f", "b", "visited_f", "visited_b", "candidates",
 
 
 def bidir(n, k, delta, meet=MEET_MARK, sched=None, max_steps=1 << 20,
-          keep_levels=False):
+          keep_levels=False, reduce=False):
     """Plain bidirectional BFS.  Returns (r, word, info) where info holds the
-    sides chosen per step, run statistics and (optionally) all levels."""
+    sides chosen per step, run statistics and (optionally) all levels.  With
+    reduce, every new level is self-reduced before the meet test."""
     d = _delta(delta)
     r = ctypes.c_int32(-1)
     cap = 1 << 20
@@ -184,7 +186,8 @@ def bidir(n, k, delta, meet=MEET_MARK, sched=None, max_steps=1 << 20,
     else:
         sp, sl = None, 0
     h = ctypes.c_void_p(None)
-    rc = lib().orc_bidir(n, k, _ptr(d, ctypes.c_int32), meet, sp, sl,
+    fn = lib().orc_bidir_reduced if reduce else lib().orc_bidir
+    rc = fn(n, k, _ptr(d, ctypes.c_int32), meet, sp, sl,
                          min(max_steps, cap), ctypes.byref(r),
                          _ptr(word, ctypes.c_uint8), cap,
                          _ptr(sides, ctypes.c_uint8), _ptr(stats, ctypes.c_int64),

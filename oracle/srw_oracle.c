@@ -22,6 +22,10 @@
  *                         (Section 1.3.1), n <= 24
  *   orc_forward           forward BFS over subsets from Q (one side of
  *                         Alg. 1), stops at the first singleton
+ *   orc_bidir_reduced     the same with every new level self-reduced
+ *                         (non-minimal forward / non-maximal inverse sets
+ *                         dropped, Alg. 1); parity unpinned beyond r and
+ *                         the invariants its tests check
  *   orc_bidir             plain bidirectional BFS (Alg. 1 with only the
  *                         duplicate removal kept): forward images from Q,
  *                         inverse preimages from the singletons, meet test
@@ -429,6 +433,48 @@ static int is_subset(const u64 *X, const u64 *Y, int W) {
     return 1;
 }
 
+/* Self-reduction of the newest level of a side (Alg. 1: deleting the
+ * non-minimal sets of the BFS list, and on the IBFS side the analogous
+ * deletion of the non-maximal sets).  Forward (dir 0): a set is dropped when
+ * another set of its level is a proper subset of it.  Inverse (dir 1): a
+ * set is dropped when another set of its level is a proper superset of it.
+ * The sets of a level are distinct, so "another set contained in it" is
+ * already a proper subset.  Survivors keep key order (and so the ranks that
+ * the next level's keys refer to are ranks among survivors).  Dropped sets
+ * leave the visited index as well: they never enter the history, and may be
+ * generated again later.  Brute force over all pairs of the level. */
+static int side_reduce(Side *s, int dir) {
+    const int W = s->W, L = s->nlev - 1;
+    const int64_t m = level_size(s, L), base = s->off[L];
+    unsigned char *drop = calloc((size_t)(m ? m : 1), 1);
+    if (!drop) return ORC_ENOMEM;
+    for (int64_t i = 0; i < m; i++) {
+        const u64 *A = level_row(s, L, i);
+        for (int64_t j = 0; j < m && !drop[i]; j++) {
+            if (j == i) continue;
+            const u64 *B = level_row(s, L, j);
+            if (dir == 0 ? is_subset(B, A, W) : is_subset(A, B, W)) drop[i] = 1;
+        }
+    }
+    int64_t pos = base;
+    for (int64_t i = 0; i < m; i++) {
+        if (drop[i]) continue;
+        if (pos != base + i) {
+            memmove(s->rows + pos * W, s->rows + (base + i) * W, sizeof(u64) * W);
+            s->par[pos] = s->par[base + i];
+        }
+        pos++;
+    }
+    free(drop);
+    s->nrows = pos;
+    s->off[L + 1] = pos;
+    /* the visited index again, over the remaining rows */
+    for (int64_t t = 0; t < s->nrows; t++) s->sorted[t] = t;
+    g_rows = s->rows; g_W = W;
+    qsort(s->sorted, (size_t)s->nrows, sizeof(int64_t), cmp_cand);
+    return ORC_OK;
+}
+
 /* ---------------- Alg. 2: MarkSupersets(A, B, d) ---------------------- */
 
 typedef struct {
@@ -625,11 +671,12 @@ int orc_forward(int n, int k, const int32_t *delta, int64_t max_sets,
 
 /* ------------------------------ O-B ------------------------------------ */
 
-/* sides_out[s] = 0 for a forward step, 1 for an inverse step */
-int orc_bidir(int n, int k, const int32_t *delta, int meet_mode,
-              const uint8_t *sched, int sched_len, int max_steps,
-              int32_t *r, uint8_t *word, int64_t word_cap,
-              uint8_t *sides_out, int64_t *stats_out, void **handle_out) {
+/* sides_out[s] = 0 for a forward step, 1 for an inverse step; reduce: 1 to
+ * self-reduce every new level (side_reduce) before the meet test */
+static int bidir_impl(int n, int k, const int32_t *delta, int meet_mode,
+                      const uint8_t *sched, int sched_len, int max_steps,
+                      int32_t *r, uint8_t *word, int64_t word_cap,
+                      uint8_t *sides_out, int64_t *stats_out, void **handle_out, int reduce) {
     int rc = check_input(n, k, delta);
     if (rc) return rc;
     if (handle_out) *handle_out = NULL;
@@ -679,6 +726,7 @@ int orc_bidir(int n, int k, const int32_t *delta, int meet_mode,
             if (sides_out) sides_out[step] = (uint8_t)side;
             run->candidates += (side ? lb : lf) * k;
             rc = side ? step_inverse(&run->B, n, k, delta) : step_forward(&run->F, n, k, delta);
+            if (!rc && reduce) rc = side_reduce(side ? &run->B : &run->F, side);
             if (rc) { out = rc; break; }
             step++;
             int64_t nl = side ? level_size(&run->B, run->B.nlev - 1)
@@ -703,6 +751,23 @@ int orc_bidir(int n, int k, const int32_t *delta, int meet_mode,
         side_free(&run->F); side_free(&run->B); free(run);
     }
     return out;
+}
+
+int orc_bidir(int n, int k, const int32_t *delta, int meet_mode,
+              const uint8_t *sched, int sched_len, int max_steps,
+              int32_t *r, uint8_t *word, int64_t word_cap,
+              uint8_t *sides_out, int64_t *stats_out, void **handle_out) {
+    return bidir_impl(n, k, delta, meet_mode, sched, sched_len, max_steps, r, word, word_cap,
+                      sides_out, stats_out, handle_out, 0);
+}
+
+/* orc_bidir with every new level self-reduced (side_reduce) */
+int orc_bidir_reduced(int n, int k, const int32_t *delta, int meet_mode,
+                      const uint8_t *sched, int sched_len, int max_steps,
+                      int32_t *r, uint8_t *word, int64_t word_cap,
+                      uint8_t *sides_out, int64_t *stats_out, void **handle_out) {
+    return bidir_impl(n, k, delta, meet_mode, sched, sched_len, max_steps, r, word, word_cap,
+                      sides_out, stats_out, handle_out, 1);
 }
 
 /* Level data of a finished orc_bidir run (side 0 forward, 1 inverse).

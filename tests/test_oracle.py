@@ -292,3 +292,67 @@ def test_mean_reset_threshold_matches_paper_fit():
         d, _ = I.first_synchronizing(64, 2, I.member_seed(12345, i), O.is_synchronizing)
         rs.append(O.bidir(64, 2, d)[0])
     assert abs(np.mean(rs) - 2.284 * 64 ** 0.515) < 1.0
+
+
+# ------------------------------------------- self-reduction of new levels
+
+def reduction_cases(count=40, base=12345):
+    out = []
+    for i in range(count):
+        n, k = 4 + (i * 7) % 37, 2 + i % 2
+        d, _ = I.first_synchronizing(n, k, I.member_seed(base, i), O.is_synchronizing)
+        out.append((n, k, d))
+    return out
+
+
+def reduced_levels_hold(n, k, d):
+    """Every stored set of a side is distinct, and every level after the
+    first is an antichain: no set of a forward level contains another set of
+    its level, no set of an inverse level is contained in another."""
+    _, _, info = O.bidir(n, k, d, reduce=True, keep_levels=True)
+    for side in (0, 1):
+        seen = set()
+        for L, (rows, _) in enumerate(info["levels"][side]):
+            for row in rows:
+                t = tuple(int(x) for x in row)
+                if t in seen:
+                    return False
+                seen.add(t)
+            if L == 0:
+                continue
+            for i in range(len(rows)):
+                A = rows[i]
+                inside = (np.all((rows & ~A) == 0, axis=1) if side == 0
+                          else np.all((A & ~rows) == 0, axis=1))
+                inside[i] = False
+                if inside.any():
+                    return False
+    return True
+
+
+def test_self_reduction_keeps_r_and_gives_reset_words():
+    """Dropping the non-minimal forward and non-maximal inverse sets of each
+    new level (Alg. 1's list reductions) keeps the reset threshold, and the
+    word the reduced search returns is a reset word of length r."""
+    for n, k, d in reduction_cases():
+        r0 = O.bidir(n, k, d)[0]
+        r1, w1, _ = O.bidir(n, k, d, reduce=True)
+        assert r1 == r0 and len(w1) == r1 and O.verify(n, k, d, w1), (n, k)
+    for n in range(2, 17):
+        r1, w1, _ = O.bidir(n, 2, I.cerny(n), reduce=True)
+        assert r1 == (n - 1) ** 2 and O.verify(n, 2, I.cerny(n), w1)
+
+
+def test_self_reduced_levels_are_antichains_without_repeats():
+    for n, k, d in reduction_cases(16, base=4242):
+        assert reduced_levels_hold(n, k, d), (n, k)
+
+
+def test_self_reduction_shrinks_the_search():
+    plain = reduced = 0
+    for n, k, d in reduction_cases(20, base=999):
+        i0 = O.bidir(n, k, d)[2]
+        i1 = O.bidir(n, k, d, reduce=True)[2]
+        plain += i0["visited_f"] + i0["visited_b"]
+        reduced += i1["visited_f"] + i1["visited_b"]
+    assert reduced < 0.9 * plain, (reduced, plain)

@@ -99,8 +99,55 @@ def pins_hold():
     return True
 
 
+# planted mistakes in the self-reduction of new levels
+REDUCE_MUTANTS = {
+    # forward drops sets that contain another, inverse sets inside another: swapped
+    "reduce_direction_swapped": [("if (dir == 0 ? is_subset(B, A, W) : is_subset(A, B, W)) drop[i] = 1;",
+                                  "if (dir == 0 ? is_subset(A, B, W) : is_subset(B, A, W)) drop[i] = 1;")],
+    # the forward rule on both sides
+    "reduce_same_rule_both_sides": [("if (dir == 0 ? is_subset(B, A, W) : is_subset(A, B, W)) drop[i] = 1;",
+                                     "if (is_subset(B, A, W)) drop[i] = 1;")],
+    # rows move down but their parent keys stay
+    "reduce_parents_not_moved": [("            s->par[pos] = s->par[base + i];\n", "")],
+    # a set counts as its own proper subset
+    "reduce_compares_with_itself": [("            if (j == i) continue;\n", "")],
+    # the visited index is not rebuilt after the level shrank
+    "reduce_stale_visited_index": [("    for (int64_t t = 0; t < s->nrows; t++) s->sorted[t] = t;\n",
+                                    "    if (0) for (int64_t t = 0; t < s->nrows; t++) s->sorted[t] = t;\n")],
+}
+
+
+def reduction_pins_hold():
+    """The pins of the self-reduced search; False as soon as one fails."""
+    from tests.test_oracle import reduced_levels_hold, reduction_cases
+    try:
+        for n, k, d in reduction_cases(24):
+            r0 = O.bidir(n, k, d)[0]
+            r1, w1, _ = O.bidir(n, k, d, reduce=True)
+            if r1 != r0 or len(w1) != r1 or not O.verify(n, k, d, w1):
+                return False
+        for n, k, d in reduction_cases(16, base=4242):
+            if not reduced_levels_hold(n, k, d):
+                return False
+    except O.OracleError:
+        return False
+    return True
+
+
 def test_unmutated_oracle_passes():
     assert pins_hold()
+    assert reduction_pins_hold()
+
+
+@pytest.mark.parametrize("name", sorted(REDUCE_MUTANTS))
+def test_reduction_mutant_is_caught(name, tmp_path):
+    so = build_mutant(name, REDUCE_MUTANTS[name], str(tmp_path))
+    saved = O._lib
+    try:
+        O._lib = O.bind(so)
+        assert not reduction_pins_hold(), f"planted mistake {name} went unnoticed"
+    finally:
+        O._lib = saved
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))

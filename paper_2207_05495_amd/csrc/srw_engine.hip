@@ -1616,6 +1616,7 @@ struct srw_server {
 static void server_loop(srw_server *s, int li) {
     std::deque<Problem *> pending;
     std::vector<Problem *> active;
+    std::vector<Problem *> done_now;        // finished in this round, not yet returned
     Engine *eng = s->lane[li].eng.get();
     std::deque<Problem *> &inbox = s->lane[li].inbox;
     try {
@@ -1632,7 +1633,7 @@ static void server_loop(srw_server *s, int li) {
                 }
             }
             std::vector<Problem *> fresh;
-            std::vector<Problem *> done_now;
+            done_now.clear();
             // admit in arrival order; a request whose estimated footprint
             // does not fit waits without blocking smaller ones behind it
             std::deque<Problem *> waiting;
@@ -1667,13 +1668,18 @@ static void server_loop(srw_server *s, int li) {
             if (!done_now.empty()) {
                 std::lock_guard<std::mutex> lk(s->mu);
                 for (Problem *p : done_now) s->outbox.push_back(p);
+                done_now.clear();
                 s->cv_out.notify_all();
             }
         }
     } catch (const HipFailure &f) {
         std::lock_guard<std::mutex> lk(s->mu);
         s->fatal = std::string("HIP error ") + hipGetErrorString(f.e) + " in " + f.where;
-        for (Problem *p : active) { p->status = SRW_EDEVICE; s->outbox.push_back(p); }
+        for (Problem *p : done_now) s->outbox.push_back(p);   // their own status stands
+        for (Problem *p : active) {
+            if (p->status == 1) p->status = SRW_EDEVICE;
+            if (std::find(done_now.begin(), done_now.end(), p) == done_now.end()) s->outbox.push_back(p);
+        }
         for (Problem *p : pending) { p->status = SRW_EDEVICE; s->outbox.push_back(p); }
         s->cv_out.notify_all();
         return;

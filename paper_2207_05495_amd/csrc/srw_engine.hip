@@ -1675,12 +1675,20 @@ static void server_loop(srw_server *s, int li) {
     } catch (const HipFailure &f) {
         std::lock_guard<std::mutex> lk(s->mu);
         s->fatal = std::string("HIP error ") + hipGetErrorString(f.e) + " in " + f.where;
+        const double t = now_ms();
         for (Problem *p : done_now) s->outbox.push_back(p);   // their own status stands
         for (Problem *p : active) {
-            if (p->status == 1) p->status = SRW_EDEVICE;
+            if (p->status == 1) {
+                p->status = SRW_EDEVICE;
+                p->t_done = t;
+            }
             if (std::find(done_now.begin(), done_now.end(), p) == done_now.end()) s->outbox.push_back(p);
         }
-        for (Problem *p : pending) { p->status = SRW_EDEVICE; s->outbox.push_back(p); }
+        for (Problem *p : pending) {
+            p->status = SRW_EDEVICE;
+            p->t_admit = p->t_done = t;
+            s->outbox.push_back(p);
+        }
         s->cv_out.notify_all();
         return;
     }

@@ -144,8 +144,8 @@ int srw_set_stream(void *hip_stream);
  *                 results; auto sorts the large levels)
  *   "meet_tiles"  tiles of 64 inverse sets per LDS meet block (0: auto)
  *   "meet_rows"   chunked meet: groups of 64 tiles with at most this many
- *                 candidate sets (capped at 512) test them by signature,
- *                 larger ones AND columns
+ *                 candidate sets (default and cap 512) test them by
+ *                 signature, larger ones AND columns
  *   "meet_groups" chunked meet: groups of 64 tiles per work item (at most;
  *                 default 16)
  *   "meet_order"  chunked meet work items: 1 chunk-major (default), 0 tile-

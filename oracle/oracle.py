@@ -72,6 +72,7 @@ def bind(path):
                                 i32p, u8p, ctypes.c_int64, u8p, i64p,
                                 ctypes.POINTER(ctypes.c_void_p)]
         L.orc_bidir_reduced.argtypes = L.orc_bidir.argtypes
+        L.orc_bidir_history.argtypes = L.orc_bidir.argtypes
         L.orc_levels.argtypes = [ctypes.c_void_p, ctypes.c_int, i32p, i64p, i64p,
                                  u64p, i64p]
         L.orc_free.argtypes = [ctypes.c_void_p]
@@ -173,7 +174,8 @@ def bidir(n, k, delta, meet=MEET_MARK, sched=None, max_steps=1 << 20,
           keep_levels=False, reduce=False):
     """Plain bidirectional BFS.  Returns (r, word, info) where info holds the
     sides chosen per step, run statistics and (optionally) all levels.  With
-    reduce, every new level is self-reduced before the meet test."""
+    reduce, every new level is self-reduced before the meet test; with
+    reduce="history", also reduced by the sets of the side's earlier levels."""
     d = _delta(delta)
     r = ctypes.c_int32(-1)
     cap = 1 << 20
@@ -186,7 +188,8 @@ def bidir(n, k, delta, meet=MEET_MARK, sched=None, max_steps=1 << 20,
     else:
         sp, sl = None, 0
     h = ctypes.c_void_p(None)
-    fn = lib().orc_bidir_reduced if reduce else lib().orc_bidir
+    fn = (lib().orc_bidir_history if reduce == "history"
+          else lib().orc_bidir_reduced if reduce else lib().orc_bidir)
     rc = fn(n, k, _ptr(d, ctypes.c_int32), meet, sp, sl,
                          min(max_steps, cap), ctypes.byref(r),
                          _ptr(word, ctypes.c_uint8), cap,

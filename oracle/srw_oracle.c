@@ -26,6 +26,9 @@
  *                         (non-minimal forward / non-maximal inverse sets
  *                         dropped, Alg. 1); parity unpinned beyond r and
  *                         the invariants its tests check
+ *   orc_bidir_history     self-reduction and reduction by history (sets
+ *                         dominated by a set of an earlier level dropped);
+ *                         pinned the same way
  *   orc_bidir             plain bidirectional BFS (Alg. 1 with only the
  *                         duplicate removal kept): forward images from Q,
  *                         inverse preimages from the singletons, meet test
@@ -443,7 +446,7 @@ static int is_subset(const u64 *X, const u64 *Y, int W) {
  * the next level's keys refer to are ranks among survivors).  Dropped sets
  * leave the visited index as well: they never enter the history, and may be
  * generated again later.  Brute force over all pairs of the level. */
-static int side_reduce(Side *s, int dir) {
+static int side_reduce(Side *s, int dir, int history) {
     const int W = s->W, L = s->nlev - 1;
     const int64_t m = level_size(s, L), base = s->off[L];
     unsigned char *drop = calloc((size_t)(m ? m : 1), 1);
@@ -454,6 +457,13 @@ static int side_reduce(Side *s, int dir) {
             if (j == i) continue;
             const u64 *B = level_row(s, L, j);
             if (dir == 0 ? is_subset(B, A, W) : is_subset(A, B, W)) drop[i] = 1;
+        }
+        /* reduction by history: a set stored on an earlier level of the side
+         * that lies inside A (forward) or contains A (inverse) reaches the
+         * same singletons with a shorter word */
+        for (int64_t h = 0; history && h < base && !drop[i]; h++) {
+            const u64 *H = s->rows + h * W;
+            if (dir == 0 ? is_subset(H, A, W) : is_subset(A, H, W)) drop[i] = 1;
         }
     }
     int64_t pos = base;
@@ -726,7 +736,7 @@ static int bidir_impl(int n, int k, const int32_t *delta, int meet_mode,
             if (sides_out) sides_out[step] = (uint8_t)side;
             run->candidates += (side ? lb : lf) * k;
             rc = side ? step_inverse(&run->B, n, k, delta) : step_forward(&run->F, n, k, delta);
-            if (!rc && reduce) rc = side_reduce(side ? &run->B : &run->F, side);
+            if (!rc && reduce) rc = side_reduce(side ? &run->B : &run->F, side, reduce & 2);
             if (rc) { out = rc; break; }
             step++;
             int64_t nl = side ? level_size(&run->B, run->B.nlev - 1)
@@ -768,6 +778,18 @@ int orc_bidir_reduced(int n, int k, const int32_t *delta, int meet_mode,
                       uint8_t *sides_out, int64_t *stats_out, void **handle_out) {
     return bidir_impl(n, k, delta, meet_mode, sched, sched_len, max_steps, r, word, word_cap,
                       sides_out, stats_out, handle_out, 1);
+}
+
+/* orc_bidir_reduced, and every new level also reduced by history: a new
+ * forward set containing a set stored on an earlier forward level, a new
+ * inverse set contained in one stored on an earlier inverse level, is
+ * dropped (Alg. 1, deleting the supersets of the BFS history list) */
+int orc_bidir_history(int n, int k, const int32_t *delta, int meet_mode,
+                      const uint8_t *sched, int sched_len, int max_steps,
+                      int32_t *r, uint8_t *word, int64_t word_cap,
+                      uint8_t *sides_out, int64_t *stats_out, void **handle_out) {
+    return bidir_impl(n, k, delta, meet_mode, sched, sched_len, max_steps, r, word, word_cap,
+                      sides_out, stats_out, handle_out, 1 | 2);
 }
 
 /* Level data of a finished orc_bidir run (side 0 forward, 1 inverse).

@@ -305,28 +305,37 @@ def reduction_cases(count=40, base=12345):
     return out
 
 
-def reduced_levels_hold(n, k, d):
+def reduced_levels_hold(n, k, d, reduce=True):
     """Every stored set of a side is distinct, and every level after the
     first is an antichain: no set of a forward level contains another set of
-    its level, no set of an inverse level is contained in another."""
-    _, _, info = O.bidir(n, k, d, reduce=True, keep_levels=True)
+    its level, no set of an inverse level is contained in another.  With
+    reduce="history", also no set of a forward level contains a set of an
+    earlier forward level, and no set of an inverse level lies inside a set
+    of an earlier inverse level."""
+    _, _, info = O.bidir(n, k, d, reduce=reduce, keep_levels=True)
     for side in (0, 1):
         seen = set()
+        earlier = np.zeros((0, (n + 63) // 64), dtype=np.uint64)
         for L, (rows, _) in enumerate(info["levels"][side]):
             for row in rows:
                 t = tuple(int(x) for x in row)
                 if t in seen:
                     return False
                 seen.add(t)
-            if L == 0:
-                continue
-            for i in range(len(rows)):
-                A = rows[i]
-                inside = (np.all((rows & ~A) == 0, axis=1) if side == 0
-                          else np.all((A & ~rows) == 0, axis=1))
-                inside[i] = False
-                if inside.any():
-                    return False
+            if L > 0:
+                for i in range(len(rows)):
+                    A = rows[i]
+                    inside = (np.all((rows & ~A) == 0, axis=1) if side == 0
+                              else np.all((A & ~rows) == 0, axis=1))
+                    inside[i] = False
+                    if inside.any():
+                        return False
+                    if reduce == "history" and len(earlier):
+                        dom = (np.all((earlier & ~A) == 0, axis=1) if side == 0
+                               else np.all((A & ~earlier) == 0, axis=1))
+                        if dom.any():
+                            return False
+            earlier = np.concatenate([earlier, rows.reshape(len(rows), -1)])
     return True
 
 
@@ -356,3 +365,38 @@ def test_self_reduction_shrinks_the_search():
         plain += i0["visited_f"] + i0["visited_b"]
         reduced += i1["visited_f"] + i1["visited_b"]
     assert reduced < 0.9 * plain, (reduced, plain)
+
+
+# ------------------------------------------- reduction by history
+
+def test_history_reduction_keeps_r_and_gives_reset_words():
+    """Also dropping each new set dominated by a set of an earlier level of
+    its side (a forward superset, an inverse subset: the shorter word already
+    reaches at least as much) keeps the reset threshold, and the returned
+    word is a reset word of length r."""
+    for n, k, d in reduction_cases():
+        r0 = O.bidir(n, k, d)[0]
+        r2, w2, _ = O.bidir(n, k, d, reduce="history")
+        assert r2 == r0 and len(w2) == r2 and O.verify(n, k, d, w2), (n, k)
+    for n in range(2, 17):
+        r2, w2, _ = O.bidir(n, 2, I.cerny(n), reduce="history")
+        assert r2 == (n - 1) ** 2 and O.verify(n, 2, I.cerny(n), w2)
+
+
+def test_history_reduced_levels_are_undominated():
+    for n, k, d in reduction_cases(16, base=4242):
+        assert reduced_levels_hold(n, k, d, reduce="history"), (n, k)
+
+
+def test_history_reduction_stores_no_more_than_self_reduction():
+    """Over the sample, the history-reduced search keeps fewer sets than the
+    self-reduced one.  Not per run: the side stepped next depends on the
+    frontier sizes, so the two searches can take different schedules."""
+    self_total = hist_total = 0
+    for n, k, d in reduction_cases(20, base=999):
+        i1 = O.bidir(n, k, d, reduce=True)[2]
+        i2 = O.bidir(n, k, d, reduce="history")[2]
+        v1, v2 = i1["visited_f"] + i1["visited_b"], i2["visited_f"] + i2["visited_b"]
+        hist_total += v2
+        self_total += v1
+    assert hist_total < self_total, (hist_total, self_total)

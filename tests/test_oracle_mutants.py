@@ -117,17 +117,35 @@ REDUCE_MUTANTS = {
 }
 
 
-def reduction_pins_hold():
-    """The pins of the self-reduced search; False as soon as one fails."""
+# planted mistakes in the reduction by history
+HISTORY_MUTANTS = {
+    # forward drops sets inside an earlier set, inverse sets containing one: swapped
+    "history_direction_swapped": [("if (dir == 0 ? is_subset(H, A, W) : is_subset(A, H, W)) drop[i] = 1;",
+                                   "if (dir == 0 ? is_subset(A, H, W) : is_subset(H, A, W)) drop[i] = 1;")],
+    # the level being reduced counts as history, so each set meets itself
+    "history_includes_own_level": [("history && h < base && !drop[i]",
+                                    "history && h < base + m && !drop[i]")],
+    # the level just before the new one is left out of the history
+    "history_skips_previous_level": [("history && h < base && !drop[i]",
+                                      "history && h < s->off[L - 1] && !drop[i]")],
+    # history reduction never switched on
+    "history_never_applied": [("side ? &run->B : &run->F, side, reduce & 2)",
+                               "side ? &run->B : &run->F, side, 0)")],
+}
+
+
+def reduction_pins_hold(reduce=True):
+    """The pins of the self-reduced (or history-reduced) search; False as
+    soon as one fails."""
     from tests.test_oracle import reduced_levels_hold, reduction_cases
     try:
         for n, k, d in reduction_cases(24):
             r0 = O.bidir(n, k, d)[0]
-            r1, w1, _ = O.bidir(n, k, d, reduce=True)
+            r1, w1, _ = O.bidir(n, k, d, reduce=reduce)
             if r1 != r0 or len(w1) != r1 or not O.verify(n, k, d, w1):
                 return False
         for n, k, d in reduction_cases(16, base=4242):
-            if not reduced_levels_hold(n, k, d):
+            if not reduced_levels_hold(n, k, d, reduce=reduce):
                 return False
     except O.OracleError:
         return False
@@ -137,6 +155,7 @@ def reduction_pins_hold():
 def test_unmutated_oracle_passes():
     assert pins_hold()
     assert reduction_pins_hold()
+    assert reduction_pins_hold("history")
 
 
 @pytest.mark.parametrize("name", sorted(REDUCE_MUTANTS))
@@ -157,5 +176,16 @@ def test_mutant_is_caught(name, tmp_path):
     try:
         O._lib = O.bind(so)
         assert not pins_hold(), f"planted mistake {name} went unnoticed"
+    finally:
+        O._lib = saved
+
+
+@pytest.mark.parametrize("name", sorted(HISTORY_MUTANTS))
+def test_history_mutant_is_caught(name, tmp_path):
+    so = build_mutant(name, HISTORY_MUTANTS[name], str(tmp_path))
+    saved = O._lib
+    try:
+        O._lib = O.bind(so)
+        assert not reduction_pins_hold("history"), f"planted mistake {name} went unnoticed"
     finally:
         O._lib = saved

@@ -111,6 +111,28 @@ def cerny_word(n: int) -> list[int]:
     return ([0] + [1] * (n - 1)) * (n - 2) + [0]
 
 
+def sink_series(n: int) -> np.ndarray:
+    """Rystsov's series with a sink (Section 3.1.1): n states,
+    state 0 the sink, n - 1 letters.  Letter 0 sends state 1 to the sink and
+    fixes every other state; letter i (1 <= i <= n - 2) swaps states i and
+    i + 1 and fixes the rest.  Its reset threshold is n(n - 1)/2, the largest
+    an automaton with a sink can have."""
+    if n < 2:
+        raise ValueError("n must be at least 2")
+    k = n - 1
+    d = np.tile(np.arange(n, dtype=np.int32), (k, 1))
+    d[0, 1] = 0
+    for i in range(1, n - 1):
+        d[i, i], d[i, i + 1] = i + 1, i
+    return d.reshape(-1)
+
+
+def sink_word(n: int) -> list[int]:
+    """The blocks (j, j-1, ..., 1, 0) for j = 0, ..., n - 2, of total length
+    n(n - 1)/2, for the sink series of n states (n >= 2)."""
+    return [a for j in range(n - 1) for a in range(j, -1, -1)]
+
+
 def relabel(delta: np.ndarray, n: int, k: int, perm: np.ndarray) -> np.ndarray:
     """The same automaton with state q renamed perm[q]."""
     d = np.asarray(delta, dtype=np.int64).reshape(k, n)

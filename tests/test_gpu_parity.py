@@ -72,6 +72,29 @@ def test_cerny(n):
     assert srw.solve(n, 2, I.cerny(n)) == ((n - 1) ** 2, I.cerny_word(n))
 
 
+@pytest.mark.parametrize("n", list(range(2, 21)))
+def test_sink_series(n):
+    """Rystsov's sink series: n - 1 letters, r = n(n - 1)/2, word in closed
+    form; the oracle agrees on these sizes."""
+    say("sink series", n)
+    d = I.sink_series(n)
+    want = (n * (n - 1) // 2, I.sink_word(n))
+    assert srw.solve(n, n - 1, d) == want
+    if n <= 16:
+        assert O.bidir(n, n - 1, d)[:2] == want
+
+
+def test_sink_series_paper_member():
+    """The member with 26 states and 25 letters: r = 325 (Section 3.1.1),
+    with the closed-form lex-least word."""
+    import time
+    say("sink series 26")
+    t = time.perf_counter()
+    got = srw.solve(26, 25, I.sink_series(26))
+    say(f"sink series 26: {time.perf_counter() - t:.2f} s")
+    assert got == (325, I.sink_word(26))
+
+
 # ------------------------------------------------------ random vs oracle
 
 def test_random_n64_k2_100_seeds():

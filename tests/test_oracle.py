@@ -400,3 +400,52 @@ def test_history_reduction_stores_no_more_than_self_reduction():
         hist_total += v2
         self_total += v1
     assert hist_total < self_total, (hist_total, self_total)
+
+
+# ------------------------------------------- the sink series
+
+# The sink series of n states has n - 1 letters and reset threshold
+# n(n - 1)/2; the paper reports the member with 26 states, 25 letters and
+# r = 325 (Section 3.1.1).
+SINK_PAPER = (26, 25, 325)
+
+
+def test_sink_series_paper_member_matches_closed_form():
+    n, k, r = SINK_PAPER
+    assert len(I.sink_series(n)) == n * k and n * (n - 1) // 2 == r
+    assert len(I.sink_word(n)) == r and O.verify(n, k, I.sink_series(n), I.sink_word(n))
+
+
+@pytest.mark.parametrize("n", range(2, 17))
+def test_sink_series_reset_threshold(n):
+    """Proof of the closed forms.  Let phi be the sum of the occupied states
+    (the sink counts 0).  The swap letter i lowers phi by at most 1 (only when
+    exactly one of i, i + 1 is occupied), letter 0 by at most 1 (it empties
+    state 1), and phi(Q) = n(n - 1)/2 must fall to 0: r >= n(n - 1)/2.  Some
+    letter always lowers phi (the least occupied state moves down or into the
+    sink), so every shortest reset word lowers phi at each letter, and the
+    lex-least one takes the least such letter each time: from the occupied
+    states j + 1, ..., n - 1 these are j, j - 1, ..., 1, 0, the word
+    sink_word(n)."""
+    d = I.sink_series(n)
+    r, w, _ = O.bidir(n, n - 1, d)
+    assert r == n * (n - 1) // 2
+    assert w == I.sink_word(n)
+    assert O.verify(n, n - 1, d, w) and not O.verify(n, n - 1, d, w[:-1])
+
+
+@pytest.mark.parametrize("n", range(2, 11))
+def test_sink_series_brute_force_and_exhaustive(n):
+    d = I.sink_series(n)
+    want = (n * (n - 1) // 2, I.sink_word(n))
+    assert O.exhaustive(n, n - 1, d) == want
+    if n <= 5:
+        assert O.bruteforce(n, n - 1, d, max_len=want[0] + 1) == want
+
+
+@pytest.mark.parametrize("reduce", [True, "history"])
+def test_sink_series_reduced_search_keeps_r(reduce):
+    for n in range(2, 15):
+        d = I.sink_series(n)
+        r, w, _ = O.bidir(n, n - 1, d, reduce=reduce)
+        assert r == n * (n - 1) // 2 and O.verify(n, n - 1, d, w), n

@@ -73,6 +73,7 @@ def bind(path):
                                 ctypes.POINTER(ctypes.c_void_p)]
         L.orc_bidir_reduced.argtypes = L.orc_bidir.argtypes
         L.orc_bidir_history.argtypes = L.orc_bidir.argtypes
+        L.orc_bidir_reduce.argtypes = L.orc_bidir.argtypes + [ctypes.c_int]
         L.orc_levels.argtypes = [ctypes.c_void_p, ctypes.c_int, i32p, i64p, i64p,
                                  u64p, i64p]
         L.orc_free.argtypes = [ctypes.c_void_p]
@@ -167,34 +168,41 @@ def forward(n, k, delta, max_sets=5_000_000):
 
 
 STAT_NAMES = ("steps", "f", "b", "visited_f", "visited_b", "candidates",
-              "pair_tests", "pairs")
+              "pair_tests", "pairs", "reduce_tests")
 
 
 def bidir(n, k, delta, meet=MEET_MARK, sched=None, max_steps=1 << 20,
-          keep_levels=False, reduce=False):
+          keep_levels=False, reduce=False, alg2=False):
     """Plain bidirectional BFS.  Returns (r, word, info) where info holds the
     sides chosen per step, run statistics and (optionally) all levels.  With
     reduce, every new level is self-reduced before the meet test; with
-    reduce="history", also reduced by the sets of the side's earlier levels."""
+    reduce="history", also reduced by the sets of the side's earlier levels.
+    With alg2, the reductions find their drops with Alg. 2 (the same drops)."""
     d = _delta(delta)
     r = ctypes.c_int32(-1)
     cap = 1 << 20
     word = np.zeros(cap, dtype=np.uint8)
     sides = np.zeros(min(max_steps, cap) + 1, dtype=np.uint8)
-    stats = np.zeros(8, dtype=np.int64)
+    stats = np.zeros(len(STAT_NAMES), dtype=np.int64)
     if sched is not None:
         s = np.ascontiguousarray(np.asarray(sched, dtype=np.uint8))
         sp, sl = _ptr(s, ctypes.c_uint8), len(s)
     else:
         sp, sl = None, 0
     h = ctypes.c_void_p(None)
-    fn = (lib().orc_bidir_history if reduce == "history"
-          else lib().orc_bidir_reduced if reduce else lib().orc_bidir)
-    rc = fn(n, k, _ptr(d, ctypes.c_int32), meet, sp, sl,
-                         min(max_steps, cap), ctypes.byref(r),
-                         _ptr(word, ctypes.c_uint8), cap,
-                         _ptr(sides, ctypes.c_uint8), _ptr(stats, ctypes.c_int64),
-                         ctypes.byref(h) if keep_levels else None)
+    args = (n, k, _ptr(d, ctypes.c_int32), meet, sp, sl, min(max_steps, cap), ctypes.byref(r),
+            _ptr(word, ctypes.c_uint8), cap, _ptr(sides, ctypes.c_uint8),
+            _ptr(stats, ctypes.c_int64), ctypes.byref(h) if keep_levels else None)
+    if alg2:
+        if not reduce:
+            raise ValueError("alg2 chooses how reductions are done: reduce must be set")
+        rc = lib().orc_bidir_reduce(*args, 1 | (2 if reduce == "history" else 0) | 4)
+    elif reduce == "history":
+        rc = lib().orc_bidir_history(*args)
+    elif reduce:
+        rc = lib().orc_bidir_reduced(*args)
+    else:
+        rc = lib().orc_bidir(*args)
     rr, ww = _result(rc, "bidir", r, word)
     info = dict(zip(STAT_NAMES, (int(x) for x in stats)))
     info["sides"] = [int(x) for x in sides[: info["steps"]]]

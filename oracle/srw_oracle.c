@@ -29,6 +29,9 @@
  *   orc_bidir_history     self-reduction and reduction by history (sets
  *                         dominated by a set of an earlier level dropped);
  *                         pinned the same way
+ *   orc_bidir_reduce      either reduction by flags, with the drops found
+ *                         by all pairs or by Alg. 2; pinned by equality of
+ *                         the two and the invariants above
  *   orc_bidir             plain bidirectional BFS (Alg. 1 with only the
  *                         duplicate removal kept): forward images from Q,
  *                         inverse preimages from the singletons, meet test
@@ -445,17 +448,26 @@ static int is_subset(const u64 *X, const u64 *Y, int W) {
  * already a proper subset.  Survivors keep key order (and so the ranks that
  * the next level's keys refer to are ranks among survivors).  Dropped sets
  * leave the visited index as well: they never enter the history, and may be
- * generated again later.  Brute force over all pairs of the level. */
-static int side_reduce(Side *s, int dir, int history) {
+ * generated again later.  Brute force over all pairs of the level, or, with
+ * alg2, the marks of Alg. 2 (alg2_drops). */
+static int alg2_drops(const Side *s, int dir, int history, int n, unsigned char *drop,
+                      int64_t *tests);
+
+static int side_reduce(Side *s, int dir, int history, int alg2, int n, int64_t *tests) {
     const int W = s->W, L = s->nlev - 1;
     const int64_t m = level_size(s, L), base = s->off[L];
     unsigned char *drop = calloc((size_t)(m ? m : 1), 1);
     if (!drop) return ORC_ENOMEM;
-    for (int64_t i = 0; i < m; i++) {
+    if (alg2) {
+        int rc = alg2_drops(s, dir, history, n, drop, tests);
+        if (rc) { free(drop); return rc; }
+    }
+    for (int64_t i = 0; i < m && !alg2; i++) {
         const u64 *A = level_row(s, L, i);
         for (int64_t j = 0; j < m && !drop[i]; j++) {
             if (j == i) continue;
             const u64 *B = level_row(s, L, j);
+            (*tests)++;
             if (dir == 0 ? is_subset(B, A, W) : is_subset(A, B, W)) drop[i] = 1;
         }
         /* reduction by history: a set stored on an earlier level of the side
@@ -463,6 +475,7 @@ static int side_reduce(Side *s, int dir, int history) {
          * same singletons with a shorter word */
         for (int64_t h = 0; history && h < base && !drop[i]; h++) {
             const u64 *H = s->rows + h * W;
+            (*tests)++;
             if (dir == 0 ? is_subset(H, A, W) : is_subset(A, H, W)) drop[i] = 1;
         }
     }
@@ -494,6 +507,7 @@ typedef struct {
     int64_t *B;                      /* indices into the B level (permuted) */
     int n, W, minsize;
     int64_t tests;
+    int proper;                      /* A and B are one list: skip a set against itself */
 } MarkCtx;
 
 static const u64 *A_row(const MarkCtx *c, int64_t t) { return level_row(c->A_side, c->A_lev, c->A[t]); }
@@ -509,6 +523,7 @@ static int64_t mark_supersets(MarkCtx *c, int64_t alo, int64_t ahi,
         while (b < bhi) {
             int hit = 0;
             for (int64_t a = alo; a < ahi && !hit; a++) {
+                if (c->proper && c->A[a] == c->B[b]) continue;
                 c->tests++;
                 hit = is_subset(A_row(c, a), B_row(c, b), c->W);
             }
@@ -586,7 +601,7 @@ static int meet(const Side *F, const Side *B, int n, int mode, int64_t *bi, int6
     for (int64_t j = 0; j < ny; j++) Bi[j] = j;
     g_lex_side = F; g_lex_lev = lf; g_lex_n = n;
     qsort(A, (size_t)nx, sizeof(int64_t), cmp_lex);
-    MarkCtx c = {F, lf, B, lb, A, Bi, n, W, 16, 0};
+    MarkCtx c = {F, lf, B, lb, A, Bi, n, W, 16, 0, 0};
     int64_t active = mark_supersets(&c, 0, nx, 0, ny, 0);
     *tests += c.tests;
     int64_t nm = ny - active;
@@ -611,12 +626,72 @@ static int meet(const Side *F, const Side *B, int n, int mode, int64_t *bi, int6
     return ORC_OK;
 }
 
+/* Self-reduction and reduction by history with Alg. 2 instead of all pairs.
+ * Forward: MarkProperSupersets(L, L) marks the sets of L that properly
+ * contain another set of L; MarkSupersets(H, L) those that contain a set of
+ * the history H (the rows of the side's earlier levels).  Inverse: X lies
+ * inside Y exactly when the complement of Y lies inside the complement of X,
+ * so the same two calls run on complemented rows (padding bits cleared).
+ * Every marked set of L is dropped; the result is the same set of drops as
+ * the all-pairs rule. */
+static int alg2_mark(const u64 *arows, int64_t na, const u64 *brows, int64_t nb, int n, int W,
+                     int proper, unsigned char *drop, int64_t *tests) {
+    if (na == 0 || nb == 0) return ORC_OK;
+    int64_t aoff[2] = {0, na}, boff[2] = {0, nb};
+    Side av = {0}, bv = {0};
+    av.W = bv.W = W;
+    av.rows = (u64 *)arows; av.off = aoff; av.nlev = 1;
+    bv.rows = (u64 *)brows; bv.off = boff; bv.nlev = 1;
+    int64_t *A = malloc((size_t)na * sizeof(int64_t));
+    int64_t *B = malloc((size_t)nb * sizeof(int64_t));
+    if (!A || !B) { free(A); free(B); return ORC_ENOMEM; }
+    for (int64_t i = 0; i < na; i++) A[i] = i;
+    for (int64_t j = 0; j < nb; j++) B[j] = j;
+    g_lex_side = &av; g_lex_lev = 0; g_lex_n = n;
+    qsort(A, (size_t)na, sizeof(int64_t), cmp_lex);
+    MarkCtx c = {&av, 0, &bv, 0, A, B, n, W, 16, 0, proper};
+    int64_t active = mark_supersets(&c, 0, na, 0, nb, 0);
+    for (int64_t t = active; t < nb; t++) drop[B[t]] = 1;
+    *tests += c.tests;
+    free(A); free(B);
+    return ORC_OK;
+}
+
+static int alg2_drops(const Side *s, int dir, int history, int n, unsigned char *drop,
+                      int64_t *tests) {
+    const int W = s->W, L = s->nlev - 1;
+    const int64_t m = level_size(s, L), base = s->off[L];
+    const int64_t nh = history ? base : 0;
+    const u64 *lev = level_row(s, L, 0), *hist = s->rows;
+    u64 *comp = NULL;
+    if (dir == 1) {
+        /* complements of the history rows, then of the level rows */
+        comp = malloc((size_t)((nh + m) ? (nh + m) : 1) * W * sizeof(u64));
+        if (!comp) return ORC_ENOMEM;
+        for (int64_t t = 0; t < nh + m; t++) {
+            const u64 *src = t < nh ? s->rows + t * W : lev + (t - nh) * W;
+            for (int w = 0; w < W; w++) {
+                int lo = w * 64;
+                u64 mask = n - lo >= 64 ? ~(u64)0 : (((u64)1 << (n - lo)) - 1);
+                comp[t * W + w] = ~src[w] & mask;
+            }
+        }
+        hist = comp;
+        lev = comp + nh * W;
+    }
+    int rc = alg2_mark(lev, m, lev, m, n, W, 1, drop, tests);
+    if (!rc && nh) rc = alg2_mark(hist, nh, lev, m, n, W, 0, drop, tests);
+    free(comp);
+    return rc;
+}
+
 /* ------------------------------ O-F ------------------------------------ */
 
 typedef struct {
     int n, k;
     Side F, B;
     int64_t pair_tests;     /* subset tests actually made */
+    int64_t reduce_tests;   /* subset tests made by the list reductions */
     int64_t pairs;          /* sum of |L_f| * |L_b| over all meet checks */
     int64_t candidates;     /* sets generated by expansion steps */
     int steps;
@@ -682,7 +757,11 @@ int orc_forward(int n, int k, const int32_t *delta, int64_t max_sets,
 /* ------------------------------ O-B ------------------------------------ */
 
 /* sides_out[s] = 0 for a forward step, 1 for an inverse step; reduce: 1 to
- * self-reduce every new level (side_reduce) before the meet test */
+ * self-reduce every new level (side_reduce) before the meet test, 2 also by
+ * history, 4 with Alg. 2.  stats_out (nine entries, or NULL): steps, forward
+ * depth, inverse depth, forward and inverse sets kept, candidates generated,
+ * meet subset tests made, sum of |L_f|*|L_b| over the meet checks, subset
+ * tests made by the reductions */
 static int bidir_impl(int n, int k, const int32_t *delta, int meet_mode,
                       const uint8_t *sched, int sched_len, int max_steps,
                       int32_t *r, uint8_t *word, int64_t word_cap,
@@ -736,7 +815,9 @@ static int bidir_impl(int n, int k, const int32_t *delta, int meet_mode,
             if (sides_out) sides_out[step] = (uint8_t)side;
             run->candidates += (side ? lb : lf) * k;
             rc = side ? step_inverse(&run->B, n, k, delta) : step_forward(&run->F, n, k, delta);
-            if (!rc && reduce) rc = side_reduce(side ? &run->B : &run->F, side, reduce & 2);
+            if (!rc && reduce)
+                rc = side_reduce(side ? &run->B : &run->F, side, reduce & 2, reduce & 4, n,
+                                 &run->reduce_tests);
             if (rc) { out = rc; break; }
             step++;
             int64_t nl = side ? level_size(&run->B, run->B.nlev - 1)
@@ -754,6 +835,7 @@ static int bidir_impl(int n, int k, const int32_t *delta, int meet_mode,
         stats_out[5] = run->candidates;
         stats_out[6] = run->pair_tests;
         stats_out[7] = run->pairs;
+        stats_out[8] = run->reduce_tests;
     }
     if (handle_out && out == ORC_OK) {
         *handle_out = run;
@@ -790,6 +872,18 @@ int orc_bidir_history(int n, int k, const int32_t *delta, int meet_mode,
                       uint8_t *sides_out, int64_t *stats_out, void **handle_out) {
     return bidir_impl(n, k, delta, meet_mode, sched, sched_len, max_steps, r, word, word_cap,
                       sides_out, stats_out, handle_out, 1 | 2);
+}
+
+/* orc_bidir with the reductions chosen by flags: 1 self-reduction, 2 also
+ * reduction by history, 4 drops found with Alg. 2 instead of all pairs (the
+ * same drops) */
+int orc_bidir_reduce(int n, int k, const int32_t *delta, int meet_mode,
+                     const uint8_t *sched, int sched_len, int max_steps,
+                     int32_t *r, uint8_t *word, int64_t word_cap,
+                     uint8_t *sides_out, int64_t *stats_out, void **handle_out, int flags) {
+    if (flags & ~7 || ((flags & 6) && !(flags & 1))) return ORC_EINVAL;
+    return bidir_impl(n, k, delta, meet_mode, sched, sched_len, max_steps, r, word, word_cap,
+                      sides_out, stats_out, handle_out, flags);
 }
 
 /* Level data of a finished orc_bidir run (side 0 forward, 1 inverse).

@@ -449,3 +449,56 @@ def test_sink_series_reduced_search_keeps_r(reduce):
         d = I.sink_series(n)
         r, w, _ = O.bidir(n, n - 1, d, reduce=reduce)
         assert r == n * (n - 1) // 2 and O.verify(n, n - 1, d, w), n
+
+
+# ------------------------------------------- reductions through Alg. 2
+
+def same_search(a, b):
+    """Equal r, word and, level by level on both sides, equal sets and
+    parent keys."""
+    if a[:2] != b[:2]:
+        return False
+    for side in (0, 1):
+        la, lb = a[2]["levels"][side], b[2]["levels"][side]
+        if len(la) != len(lb):
+            return False
+        for (ra, pa), (rb, pb) in zip(la, lb):
+            if not (np.array_equal(ra, rb) and np.array_equal(pa, pb)):
+                return False
+    return True
+
+
+@pytest.mark.parametrize("reduce", [True, "history"])
+def test_alg2_reductions_drop_exactly_what_all_pairs_drop(reduce):
+    """MarkProperSupersets / MarkSupersets (Alg. 2, on complements for the
+    inverse side) find the same drops as the all-pairs rule: the whole
+    search, every level and parent key, comes out the same."""
+    for n, k, d in reduction_cases(40, base=777) + [(n, n - 1, I.sink_series(n)) for n in (5, 9, 12)]:
+        a = O.bidir(n, k, d, reduce=reduce, keep_levels=True)
+        b = O.bidir(n, k, d, reduce=reduce, keep_levels=True, alg2=True)
+        assert same_search(a, b), (n, k)
+
+
+def test_alg2_reductions_across_word_boundaries():
+    """The complements' last-word mask at widths 63, 64, 65 and 130."""
+    for n in (63, 64, 65, 130):
+        for i in range(2):
+            d, _ = I.first_synchronizing(n, 2, I.member_seed(4321, i), O.is_synchronizing)
+            for reduce in (True, "history"):
+                a = O.bidir(n, 2, d, reduce=reduce, keep_levels=True)
+                b = O.bidir(n, 2, d, reduce=reduce, keep_levels=True, alg2=True)
+                assert same_search(a, b), (n, i, reduce)
+
+
+def test_alg2_reductions_test_fewer_pairs():
+    """The split makes far fewer subset tests than all pairs."""
+    n = 96
+    d, _ = I.first_synchronizing(n, 2, I.member_seed(I.BASE_SEED, 0), O.is_synchronizing)
+    a = O.bidir(n, 2, d, reduce=True)[2]["reduce_tests"]
+    b = O.bidir(n, 2, d, reduce=True, alg2=True)[2]["reduce_tests"]
+    assert 0 < b < a / 4, (a, b)
+
+
+def test_alg2_needs_a_reduction():
+    with pytest.raises(ValueError):
+        O.bidir(4, 2, I.cerny(4), alg2=True)

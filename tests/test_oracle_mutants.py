@@ -117,6 +117,41 @@ REDUCE_MUTANTS = {
 }
 
 
+# planted mistakes in the reductions through Alg. 2
+ALG2_MUTANTS = {
+    # the proper-superset leaf compares a set with itself: every set is dropped
+    "alg2_not_proper": [("                if (c->proper && c->A[a] == c->B[b]) continue;\n", "")],
+    # the mask of the last word also clears the last state
+    "alg2_mask_drops_last_state": [("(((u64)1 << (n - lo)) - 1);", "(((u64)1 << (n - lo - 1)) - 1);")],
+    # the inverse side marked without complementing
+    "alg2_inverse_not_complemented": [("    if (dir == 1) {\n        /* complements",
+                                       "    if (0) {\n        /* complements")],
+    # history marks run on the history itself instead of the new level
+    "alg2_history_wrong_list": [("if (!rc && nh) rc = alg2_mark(hist, nh, lev, m, n, W, 0, drop, tests);",
+                                 "if (!rc && nh) rc = alg2_mark(lev, m, hist, nh < m ? nh : m, n, W, 0, drop, tests);")],
+}
+
+
+def alg2_pins_hold():
+    from tests.test_oracle import same_search, reduction_cases
+    try:
+        for n, k, d in reduction_cases(24, base=777):
+            for reduce in (True, "history"):
+                a = O.bidir(n, k, d, reduce=reduce, keep_levels=True)
+                b = O.bidir(n, k, d, reduce=reduce, keep_levels=True, alg2=True)
+                if not same_search(a, b):
+                    return False
+        for n in (63, 65):
+            d, _ = I.first_synchronizing(n, 2, I.member_seed(4321, 0), O.is_synchronizing)
+            a = O.bidir(n, 2, d, reduce=True, keep_levels=True)
+            b = O.bidir(n, 2, d, reduce=True, keep_levels=True, alg2=True)
+            if not same_search(a, b):
+                return False
+    except O.OracleError:
+        return False
+    return True
+
+
 # planted mistakes in the reduction by history
 HISTORY_MUTANTS = {
     # forward drops sets inside an earlier set, inverse sets containing one: swapped
@@ -129,8 +164,8 @@ HISTORY_MUTANTS = {
     "history_skips_previous_level": [("history && h < base && !drop[i]",
                                       "history && h < s->off[L - 1] && !drop[i]")],
     # history reduction never switched on
-    "history_never_applied": [("side ? &run->B : &run->F, side, reduce & 2)",
-                               "side ? &run->B : &run->F, side, 0)")],
+    "history_never_applied": [("side ? &run->B : &run->F, side, reduce & 2, reduce & 4, n,",
+                               "side ? &run->B : &run->F, side, 0, reduce & 4, n,")],
 }
 
 
@@ -156,6 +191,7 @@ def test_unmutated_oracle_passes():
     assert pins_hold()
     assert reduction_pins_hold()
     assert reduction_pins_hold("history")
+    assert alg2_pins_hold()
 
 
 @pytest.mark.parametrize("name", sorted(REDUCE_MUTANTS))
@@ -187,5 +223,16 @@ def test_history_mutant_is_caught(name, tmp_path):
     try:
         O._lib = O.bind(so)
         assert not reduction_pins_hold("history"), f"planted mistake {name} went unnoticed"
+    finally:
+        O._lib = saved
+
+
+@pytest.mark.parametrize("name", sorted(ALG2_MUTANTS))
+def test_alg2_mutant_is_caught(name, tmp_path):
+    so = build_mutant(name, ALG2_MUTANTS[name], str(tmp_path))
+    saved = O._lib
+    try:
+        O._lib = O.bind(so)
+        assert not alg2_pins_hold(), f"planted mistake {name} went unnoticed"
     finally:
         O._lib = saved

@@ -57,6 +57,10 @@ def workload(name, srw, count=None, nmax=None):
         for i in range(100):
             d, _ = I.first_synchronizing(64, 2, I.member_seed(I.BASE_SEED, i), srw.check_sync)
             out.append((64, 2, d, f"rand64#{i}"))
+    elif name == "sink26-k25":
+        # the member of Rystsov's sink series with 26 states and 25 letters
+        # (r = 325), the hard instance the paper times
+        out.append((26, 25, I.sink_series(26), "sink26"))
     elif name == "n450k2":
         d, _ = I.first_synchronizing(450, 2, I.member_seed(I.BASE_SEED, 0), srw.check_sync)
         out.append((450, 2, d, "rand450#0"))
@@ -199,7 +203,7 @@ def roofline(stats, cls_stats, workload):
     dom = max(CLASSES[:6], key=lambda c: ms[c])
     t = ms[dom] / max(1, launches[dom]) / 1e3     # seconds per launch
     nl = max(1, launches[dom])
-    if dom == "meet":
+    if dom == "meet" and stats["meet_w"]:
         # the meet launches one kernel per set width: take the one with the
         # most time.  Unit: the set operations of the chunked meet as the
         # kernel counts them (32-bit lane-ops: 2 per 64-bit column AND, 4 per
@@ -457,8 +461,10 @@ def main():
                        "n256k2x10+cerny16-32": "10 x random n=256 k=2 + Cerny C_16..C_32",
                        "mix4096-n32-320-k2-3": f"first {len(probs)} of the 4096-member batch, "
                                   "n~U[32,320], k~U{2,3}",
-                       "n450k2": "1 x random n=450 k=2"}[args.workload]
-                   + " (uniform delta, seeded SplitMix64, first synchronizing draw)",
+                       "n450k2": "1 x random n=450 k=2",
+                       "sink26-k25": "Rystsov's sink series, n=26 k=25 (r=325)"}[args.workload]
+                   + ("" if args.workload.startswith("sink") else
+                      " (uniform delta, seeded SplitMix64, first synchronizing draw)"),
                    "path": "srw_solve_batch"},
         "automata_per_s": len(probs) / per_step,
         "subsets_per_step": cand,

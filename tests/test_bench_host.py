@@ -124,5 +124,7 @@ def test_workload_recipes():
     assert len(small) == 100 and len({bytes(d.tobytes()) for _, _, d, _ in small}) == 100
     mix = bench.workload("mix4096-n32-320-k2-3", HostCheck, count=64, nmax=100)
     assert mix and all(32 <= n <= 100 and k in (2, 3) for n, k, _, _ in mix)
+    (n, k, d, _), = bench.workload("sink26-k25", HostCheck)
+    assert (n, k, len(d)) == (26, 25, 26 * 25)
     with pytest.raises(SystemExit):
         bench.workload("no-such-workload", HostCheck)

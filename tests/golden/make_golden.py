@@ -6,6 +6,8 @@ so a test can rebuild the exact automaton.
 
     python tests/golden/make_golden.py rand256     # n=256, k=2, 10 seeds
     python tests/golden/make_golden.py mixed       # smaller mixed sizes
+    python tests/golden/make_golden.py mix4096     # members with n <= 160 among the
+                                                   # first 300 of the 4096-member batch
 """
 
 import json
@@ -42,6 +44,11 @@ def jobs(which):
                                     (160, 3), (80, 4), (100, 4), (300, 2), (320, 2)]):
             out.append((n, k, I.member_seed(I.BASE_SEED ^ 0xABCDEF, i)))
         return out
+    if which == "mix4096":
+        # the seeded 4096-member batch (n uniform in [32, 320], k in {2, 3}):
+        # its first 300 members, those with n <= 160
+        return [(m["n"], m["k"], m["seed"])
+                for m in I.mixed_batch(300, 32, 320, (2, 3), O.is_synchronizing) if m["n"] <= 160]
     raise SystemExit(f"unknown set {which}")
 
 

@@ -515,3 +515,17 @@ def test_edge_shapes():
     res = srw.solve_batch([(90, 2, d)] * 5)
     want = O.bidir(90, 2, d)[:2]
     assert all(st == srw.OK and (r, w) == want for st, r, w in res)
+
+
+def test_mixed_batch_members_against_stored_oracle_values():
+    """The members with n <= 160 among the first 300 of the seeded
+    4096-member batch (n uniform in [32, 320], k in {2, 3}), solved together
+    in one batch: r and word equal the oracle's stored values."""
+    cs = golden("mix4096.json")
+    probs = [(c["n"], c["k"], I.random_automaton(c["n"], c["k"], c["seed"], c["attempt"]))
+             for c in cs]
+    say("mix4096 members", len(probs))
+    res = srw.solve_batch(probs)
+    for c, (st, r, w) in zip(cs, res):
+        assert st == srw.OK and r == c["r"], (c["n"], c["k"], c["seed"])
+        assert "".join(map(str, w)) == c["word"], (c["n"], c["k"], c["seed"])

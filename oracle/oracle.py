@@ -172,12 +172,13 @@ STAT_NAMES = ("steps", "f", "b", "visited_f", "visited_b", "candidates",
 
 
 def bidir(n, k, delta, meet=MEET_MARK, sched=None, max_steps=1 << 20,
-          keep_levels=False, reduce=False, alg2=False):
+          keep_levels=False, reduce=False, alg2=False, keep_dropped=False):
     """Plain bidirectional BFS.  Returns (r, word, info) where info holds the
     sides chosen per step, run statistics and (optionally) all levels.  With
     reduce, every new level is self-reduced before the meet test; with
     reduce="history", also reduced by the sets of the side's earlier levels.
-    With alg2, the reductions find their drops with Alg. 2 (the same drops)."""
+    With alg2, the reductions find their drops with Alg. 2 (the same drops);
+    with keep_dropped, dropped sets stay in the visited index."""
     d = _delta(delta)
     r = ctypes.c_int32(-1)
     cap = 1 << 20
@@ -193,10 +194,12 @@ def bidir(n, k, delta, meet=MEET_MARK, sched=None, max_steps=1 << 20,
     args = (n, k, _ptr(d, ctypes.c_int32), meet, sp, sl, min(max_steps, cap), ctypes.byref(r),
             _ptr(word, ctypes.c_uint8), cap, _ptr(sides, ctypes.c_uint8),
             _ptr(stats, ctypes.c_int64), ctypes.byref(h) if keep_levels else None)
-    if alg2:
+    if alg2 or keep_dropped:
         if not reduce:
-            raise ValueError("alg2 chooses how reductions are done: reduce must be set")
-        rc = lib().orc_bidir_reduce(*args, 1 | (2 if reduce == "history" else 0) | 4)
+            raise ValueError("alg2 and keep_dropped change how reductions are done: "
+                             "reduce must be set")
+        flags = 1 | (2 if reduce == "history" else 0) | (4 if alg2 else 0) | (8 if keep_dropped else 0)
+        rc = lib().orc_bidir_reduce(*args, flags)
     elif reduce == "history":
         rc = lib().orc_bidir_history(*args)
     elif reduce:

@@ -267,6 +267,9 @@ typedef struct {
     int64_t *off;       /* level L holds rows off[L] .. off[L+1]-1 */
     int nlev, levcap;
     int64_t *sorted;    /* row ids of all visited rows in row order */
+    u64 *ghost;         /* sets dropped by a reduction that still count as
+                           visited (reduce flag 8), sorted in row order */
+    int64_t nghost, ghost_cap;
 } Side;
 
 static const u64 *g_rows;
@@ -314,7 +317,7 @@ static int side_reserve(Side *s, int64_t more) {
 }
 
 static void side_free(Side *s) {
-    free(s->rows); free(s->par); free(s->off); free(s->sorted);
+    free(s->rows); free(s->par); free(s->off); free(s->sorted); free(s->ghost);
     memset(s, 0, sizeof *s);
 }
 
@@ -323,7 +326,7 @@ static const u64 *level_row(const Side *s, int L, int64_t i) {
     return s->rows + (s->off[L] + i) * s->W;
 }
 
-/* binary search of a set among the visited rows */
+/* binary search of a set among the visited rows, then among the ghosts */
 static int visited(const Side *s, const u64 *x) {
     int64_t lo = 0, hi = s->nrows;
     while (lo < hi) {
@@ -332,7 +335,18 @@ static int visited(const Side *s, const u64 *x) {
         if (c == 0) return 1;
         if (c < 0) lo = mid + 1; else hi = mid;
     }
+    lo = 0, hi = s->nghost;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) / 2;
+        int c = rowcmp(s->ghost + mid * s->W, x, s->W);
+        if (c == 0) return 1;
+        if (c < 0) lo = mid + 1; else hi = mid;
+    }
     return 0;
+}
+
+static int cmp_ghost(const void *a, const void *b) {
+    return rowcmp((const u64 *)a, (const u64 *)b, g_W);
 }
 
 /* Appends a new level made of the candidates cand[0..C-1] (key = index):
@@ -453,7 +467,8 @@ static int is_subset(const u64 *X, const u64 *Y, int W) {
 static int alg2_drops(const Side *s, int dir, int history, int n, unsigned char *drop,
                       int64_t *tests);
 
-static int side_reduce(Side *s, int dir, int history, int alg2, int n, int64_t *tests) {
+static int side_reduce(Side *s, int dir, int history, int alg2, int keep_dropped, int n,
+                       int64_t *tests) {
     const int W = s->W, L = s->nlev - 1;
     const int64_t m = level_size(s, L), base = s->off[L];
     unsigned char *drop = calloc((size_t)(m ? m : 1), 1);
@@ -478,6 +493,22 @@ static int side_reduce(Side *s, int dir, int history, int alg2, int n, int64_t *
             (*tests)++;
             if (dir == 0 ? is_subset(H, A, W) : is_subset(A, H, W)) drop[i] = 1;
         }
+    }
+    if (keep_dropped) {
+        /* the dropped sets stay visited: they join the sorted ghost rows */
+        int64_t nd = 0;
+        for (int64_t i = 0; i < m; i++) nd += drop[i];
+        if (s->nghost + nd > s->ghost_cap) {
+            int64_t cap = 2 * (s->nghost + nd) + 16;
+            u64 *g = realloc(s->ghost, (size_t)cap * W * sizeof(u64));
+            if (!g) { free(drop); return ORC_ENOMEM; }
+            s->ghost = g;
+            s->ghost_cap = cap;
+        }
+        for (int64_t i = 0; i < m; i++)
+            if (drop[i]) memcpy(s->ghost + (s->nghost++) * W, level_row(s, L, i), sizeof(u64) * W);
+        g_W = W;
+        qsort(s->ghost, (size_t)s->nghost, sizeof(u64) * W, cmp_ghost);
     }
     int64_t pos = base;
     for (int64_t i = 0; i < m; i++) {
@@ -758,7 +789,7 @@ int orc_forward(int n, int k, const int32_t *delta, int64_t max_sets,
 
 /* sides_out[s] = 0 for a forward step, 1 for an inverse step; reduce: 1 to
  * self-reduce every new level (side_reduce) before the meet test, 2 also by
- * history, 4 with Alg. 2.  stats_out (nine entries, or NULL): steps, forward
+ * history, 4 with Alg. 2, 8 dropped sets kept as visited.  stats_out (nine entries, or NULL): steps, forward
  * depth, inverse depth, forward and inverse sets kept, candidates generated,
  * meet subset tests made, sum of |L_f|*|L_b| over the meet checks, subset
  * tests made by the reductions */
@@ -816,8 +847,8 @@ static int bidir_impl(int n, int k, const int32_t *delta, int meet_mode,
             run->candidates += (side ? lb : lf) * k;
             rc = side ? step_inverse(&run->B, n, k, delta) : step_forward(&run->F, n, k, delta);
             if (!rc && reduce)
-                rc = side_reduce(side ? &run->B : &run->F, side, reduce & 2, reduce & 4, n,
-                                 &run->reduce_tests);
+                rc = side_reduce(side ? &run->B : &run->F, side, reduce & 2, reduce & 4,
+                                 reduce & 8, n, &run->reduce_tests);
             if (rc) { out = rc; break; }
             step++;
             int64_t nl = side ? level_size(&run->B, run->B.nlev - 1)
@@ -876,12 +907,13 @@ int orc_bidir_history(int n, int k, const int32_t *delta, int meet_mode,
 
 /* orc_bidir with the reductions chosen by flags: 1 self-reduction, 2 also
  * reduction by history, 4 drops found with Alg. 2 instead of all pairs (the
- * same drops) */
+ * same drops), 8 dropped sets stay in the visited index instead of being
+ * forgotten */
 int orc_bidir_reduce(int n, int k, const int32_t *delta, int meet_mode,
                      const uint8_t *sched, int sched_len, int max_steps,
                      int32_t *r, uint8_t *word, int64_t word_cap,
                      uint8_t *sides_out, int64_t *stats_out, void **handle_out, int flags) {
-    if (flags & ~7 || ((flags & 6) && !(flags & 1))) return ORC_EINVAL;
+    if (flags & ~15 || ((flags & 14) && !(flags & 1))) return ORC_EINVAL;
     return bidir_impl(n, k, delta, meet_mode, sched, sched_len, max_steps, r, word, word_cap,
                       sides_out, stats_out, handle_out, flags);
 }

@@ -502,3 +502,31 @@ def test_alg2_reductions_test_fewer_pairs():
 def test_alg2_needs_a_reduction():
     with pytest.raises(ValueError):
         O.bidir(4, 2, I.cerny(4), alg2=True)
+
+
+# ------------------------------------------- dropped sets kept as visited
+
+def test_with_history_dropped_sets_may_stay_visited():
+    """With the reduction by history on, a dropped set may stay in the
+    visited index instead of being forgotten: the search is identical.  A
+    dropped set contains (forward) a kept set of its own or an earlier
+    level, so a later copy of it is dropped by history anyway, and so is
+    every set it would have dropped in a self-reduction."""
+    for n, k, d in reduction_cases(40, base=31):
+        for alg2 in (False, True):
+            a = O.bidir(n, k, d, reduce="history", keep_levels=True, alg2=alg2)
+            b = O.bidir(n, k, d, reduce="history", keep_levels=True, alg2=alg2, keep_dropped=True)
+            assert same_search(a, b), (n, k, alg2)
+
+
+def test_without_history_keeping_dropped_sets_is_a_different_search():
+    """Self-reduction alone: forgetting dropped sets lets them come back on
+    a later level, keeping them visited does not.  The levels differ on some
+    automata; r and the validity of the word do not."""
+    differ = 0
+    for n, k, d in reduction_cases(40, base=31):
+        a = O.bidir(n, k, d, reduce=True, keep_levels=True)
+        b = O.bidir(n, k, d, reduce=True, keep_levels=True, keep_dropped=True)
+        differ += not same_search(a, b)
+        assert a[0] == b[0] and len(b[1]) == b[0] and O.verify(n, k, d, b[1]), (n, k)
+    assert differ > 0

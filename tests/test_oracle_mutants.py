@@ -164,8 +164,8 @@ HISTORY_MUTANTS = {
     "history_skips_previous_level": [("history && h < base && !drop[i]",
                                       "history && h < s->off[L - 1] && !drop[i]")],
     # history reduction never switched on
-    "history_never_applied": [("side ? &run->B : &run->F, side, reduce & 2, reduce & 4, n,",
-                               "side ? &run->B : &run->F, side, 0, reduce & 4, n,")],
+    "history_never_applied": [("side ? &run->B : &run->F, side, reduce & 2, reduce & 4,",
+                               "side ? &run->B : &run->F, side, 0, reduce & 4,")],
 }
 
 

@@ -529,3 +529,32 @@ def test_mixed_batch_members_against_stored_oracle_values():
     for c, (st, r, w) in zip(cs, res):
         assert st == srw.OK and r == c["r"], (c["n"], c["k"], c["seed"])
         assert "".join(map(str, w)) == c["word"], (c["n"], c["k"], c["seed"])
+
+
+def test_server_deadline_then_recovery():
+    """A server with a 1 ms per-request deadline ends two Černý C_40 solves
+    (1,521 steps each) with ETIMEOUT and returns both; a server without a
+    deadline then solves them exactly."""
+    d = I.cerny(40)
+    say("server deadline")
+    got = {}
+    with srw.Server(max_slots=4, deadline_ms=1) as s:
+        s.submit(40, 2, d, 0)
+        s.submit(40, 2, d, 1)
+        for _ in range(300):                 # at most 60 s
+            for x in s.poll(200000):
+                got[x["tag"]] = x
+            if len(got) == 2:
+                break
+        assert len(got) == 2 and s.pending() == 0
+    assert [got[t]["status"] for t in (0, 1)] == [srw.ETIMEOUT] * 2
+    got = {}
+    with srw.Server(max_slots=4) as s:
+        s.submit(40, 2, d, 7)
+        for _ in range(300):
+            for x in s.poll(200000):
+                got[x["tag"]] = x
+            if got:
+                break
+    assert got[7]["status"] == srw.OK
+    assert (got[7]["r"], got[7]["word"]) == (39 ** 2, I.cerny_word(40))

@@ -309,10 +309,12 @@ def test_server_results_same_alone_and_in_mix():
             if t % 5 == 0:
                 for x in s.poll(0):
                     got[x["tag"]] = x
-        while len(got) < len(cases):
+        for _ in range(600):                 # at most 120 s
+            if len(got) == len(cases):
+                break
             for x in s.poll(200000):
                 got[x["tag"]] = x
-        assert s.pending() == 0
+        assert len(got) == len(cases) and s.pending() == 0
     for t, (n, k, d) in enumerate(cases):
         x = got[t]
         assert x["status"] == srw.OK

@@ -128,3 +128,17 @@ def test_workload_recipes():
     assert (n, k, len(d)) == (26, 25, 26 * 25)
     with pytest.raises(SystemExit):
         bench.workload("no-such-workload", HostCheck)
+
+
+def test_cpu_baseline_times_the_oracle_on_a_bounded_sample():
+    """The oracle leg runs each member in a child process, random members
+    first, and reports the subsets it expanded per second of oracle time."""
+    from paper_2207_05495_amd import inputs as I
+    probs = [(n, 2, I.cerny(n), f"cerny{n}") for n in (6, 8)]
+    d, _ = I.first_synchronizing(5, 2, I.member_seed(I.BASE_SEED, 0), O.is_synchronizing)
+    probs.insert(0, (5, 2, d, "rand5"))
+    out = bench.cpu_baseline(probs, 60.0)
+    assert out["kind"] == "oracle" and out["cores"] == 1
+    assert out["unit"] == "subsets expanded/s" and out["value"] > 0
+    assert out["sample"].startswith("3 of 3 automata") and "rand5, cerny6, cerny8" in out["sample"]
+    assert bench.cpu_baseline(probs, 0.1)["value"] is None

@@ -530,3 +530,24 @@ def test_without_history_keeping_dropped_sets_is_a_different_search():
         differ += not same_search(a, b)
         assert a[0] == b[0] and len(b[1]) == b[0] and O.verify(n, k, d, b[1]), (n, k)
     assert differ > 0
+
+
+def test_forward_levels_never_grow_in_set_size():
+    """An image is never larger than its source (Section 2: one state per
+    state), so the largest set of each forward level is at most the largest
+    of the level before; the history pruning of Alg. 1 relies on it."""
+    for n, k, d in reduction_cases(20, base=55):
+        _, _, info = O.bidir(n, k, d, keep_levels=True)
+        sizes = [max(sum(bin(int(w)).count("1") for w in row) for row in rows)
+                 for rows, _ in info["levels"][0] if len(rows)]
+        assert sizes[0] == n and all(a >= b for a, b in zip(sizes, sizes[1:])), (n, k, sizes)
+
+
+def test_alg2_reductions_with_many_letters():
+    for n in (4, 6, 8):
+        d, _ = I.first_synchronizing(n, 255, I.member_seed(99, n), O.is_synchronizing)
+        for reduce in (True, "history"):
+            a = O.bidir(n, 255, d, reduce=reduce, keep_levels=True)
+            b = O.bidir(n, 255, d, reduce=reduce, keep_levels=True, alg2=True)
+            assert same_search(a, b), (n, reduce)
+            assert a[0] == O.bidir(n, 255, d)[0]

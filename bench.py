@@ -79,6 +79,90 @@ def oracle_one(path):
     print(json.dumps({"r": r, "candidates": info["candidates"], "s": time.perf_counter() - t}))
 
 
+def oracle_steps(path, max_steps):
+    """Child process: the oracle's search of one automaton, stopped after
+    1, 2, 3, ... expansion steps (each run from the start); one JSON line per
+    run.  With max_steps > 0 only that many steps, once."""
+    from oracle import oracle as O
+    z = np.load(path)
+    n, k, d = int(z["n"]), int(z["k"]), z["d"]
+    for st in ([max_steps] if max_steps > 0 else range(1, 1 << 20)):
+        t = time.perf_counter()
+        done, info = O.bidir_steps(n, k, d, st)
+        print(json.dumps({"steps": info["steps"], "candidates": info["candidates"], "done": done,
+                          "s": time.perf_counter() - t}), flush=True)
+        if done:
+            break
+
+
+def host_cpu():
+    """CPU model and the cores this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    return model, cores
+
+
+def cpu_baseline_steps(prob, budget_s, max_procs=16):
+    """The oracle (single-threaded C, Alg. 2 meet) on one automaton too large
+    for it to finish: its search stopped after S expansion steps, S the
+    largest step count whose run fits the budget (the runs for 1, 2, ...
+    steps go one after another in a child process, each from the start).
+    Then the same S-step run in as many processes at once as the host has
+    cores (at most max_procs), for the all-cores rate.  Runs before the GPU
+    is touched."""
+    import subprocess
+    import tempfile
+    n, k, d, label = prob
+    model, ncpu = host_cpu()
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "m.npz")
+        np.savez(path, n=n, k=k, d=d)
+        cmd = [sys.executable, os.path.abspath(__file__), "--oracle-steps", path]
+        proc = subprocess.Popen(cmd, stdout=subprocess.PIPE, text=True)
+        last, t0 = None, time.perf_counter()
+        # each run takes about 1.5-2x the one before: stop starting runs
+        # once the next one would likely overrun the budget
+        for line in proc.stdout:
+            rec = json.loads(line)
+            last = rec
+            if rec["done"] or time.perf_counter() - t0 + 2.5 * rec["s"] > budget_s:
+                break
+        proc.kill()
+        proc.wait()
+        if last is None:
+            return None
+        procs = max(1, min(max_procs, ncpu or 1))
+        cmd = [sys.executable, os.path.abspath(__file__), "--oracle-steps", path,
+               "--oracle-max-steps", str(last["steps"])]
+        t1 = time.perf_counter()
+        outs = [subprocess.Popen(cmd, stdout=subprocess.PIPE, text=True) for _ in range(procs)]
+        cand = 0
+        for p_ in outs:
+            out, _ = p_.communicate()
+            cand += json.loads(out.strip().splitlines()[-1])["candidates"]
+        wall = time.perf_counter() - t1
+    return {"value": last["candidates"] / last["s"], "unit": "subsets expanded/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{label}: the oracle's search stopped after its first {last['steps']} "
+                      f"expansion steps ({last['candidates']} subsets expanded in {last['s']:.1f} s, "
+                      f"one thread); the whole search does not finish within minutes on a CPU",
+            "cpu_model": model, "host_cores": ncpu,
+            "all_cores": {"value": cand / wall, "unit": "subsets expanded/s", "cores": procs,
+                          "sample": f"the same {last['steps']}-step run in {procs} processes at once, "
+                                    f"{wall:.1f} s wall"}}
+
+
 def cpu_baseline(probs, budget_s):
     """The oracle (single-threaded C, Alg. 2 meet) on a bounded sample of the
     workload: the random members in order, then the Černý ones, each in
@@ -112,7 +196,8 @@ def cpu_baseline(probs, budget_s):
             "sample": f"{len(solved)} of {len(probs)} automata solved one by one in "
                       f"{busy:.1f} s of oracle time ({', '.join(solved[:3])}, ..., {solved[-1]})"
                       if solved else "none finished within the budget",
-            "automata_per_s": len(solved) / busy if busy else None}
+            "automata_per_s": len(solved) / busy if busy else None,
+            "cpu_model": host_cpu()[0], "host_cores": host_cpu()[1]}
 
 
 def kernel_short_name(name):
@@ -255,21 +340,12 @@ def class_table(stats):
     return out
 
 
-def serve_requests(count, nmax, kmax, srw, base=I.BASE_SEED ^ 5):
-    """Request mix of the serving workload: 90% random automata (n uniform in
-    [64, nmax], k uniform in 2..kmax), 10% Černý C_n with n uniform in [8, 40]."""
-    rng = np.random.default_rng(base & 0xFFFFFFFF)
-    out = []
-    for i in range(count):
-        if rng.random() < 0.1:
-            n = int(rng.integers(8, 41))
-            out.append((n, 2, I.cerny(n), "cerny"))
-        else:
-            n = int(rng.integers(64, nmax + 1))
-            k = int(rng.integers(2, kmax + 1))
-            d, _ = I.first_synchronizing(n, k, I.member_seed(base, i), srw.check_sync)
-            out.append((n, k, d, f"k{k}" + ("big" if n > 300 else "")))
-    return out
+def serve_requests(count, nmax, kmax, srw):
+    """Request mix of the serving workload (inputs.serve_mix): 90% random
+    automata (n uniform in [64, nmax], k uniform in 2..kmax), 10% Černý C_n
+    with n uniform in [8, 40]."""
+    return [(m["n"], m["k"], m["delta"], m["label"])
+            for m in I.serve_mix(count, nmax, kmax, srw.check_sync)]
 
 
 def serve_bench(args, srw):
@@ -348,18 +424,94 @@ def serve_bench(args, srw):
     }
 
 
+def stored_oracle_values():
+    """(r, word) the oracle stored under tests/golden for seeded random
+    automata, keyed by the bytes of the transition table (rebuilt from each
+    entry's seed and attempt)."""
+    import glob
+    out = {}
+    for path in glob.glob(os.path.join(ROOT, "tests", "golden", "*.json")):
+        with open(path) as f:
+            rec = json.load(f)
+        for c in rec.get("cases", []):
+            if "r" not in c or "seed" not in c or "attempt" not in c:
+                continue
+            d = I.random_automaton(c["n"], c["k"], c["seed"], c["attempt"])
+            w = c["word"]
+            w = [int(x) for x in w] if isinstance(w, str) else list(w)
+            out[d.tobytes()] = (c["r"], w)
+    return out
+
+
+def check_against_oracle(probs, res, stored):
+    """Every result with a stored oracle value must equal it (r and word);
+    returns how many were checked."""
+    checked = 0
+    for (n, k, d, label), (st, r, w) in zip(probs, res):
+        want = stored.get(np.asarray(d, dtype=np.int32).tobytes())
+        if want is None:
+            continue
+        if st != 0 or (r, w) != want:
+            raise SystemExit(f"{label}: GPU result {(st, r)} differs from the stored oracle value r={want[0]}")
+        checked += 1
+    return checked
+
+
+def batched_vs_plain(args, srw, stored):
+    """Automata solved per second by one srw_solve_batch call over a seeded
+    batch against srw_solve one automaton at a time, with the latency of the
+    single solves."""
+    import torch
+    probs = workload(args.batch_workload, srw, None, args.batch_nmax)
+    batch = [(n, k, d) for n, k, d, _ in probs]
+    res = srw.solve_batch(batch)                  # warmup
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    res = srw.solve_batch(batch)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    assert all(st == 0 for st, _, _ in res)
+    checked = check_against_oracle(probs, res, stored)
+    print(f"batched pass over {len(batch)} automata: {tb * 1e3:.0f} ms", file=sys.stderr, flush=True)
+    lat = []
+    t = time.perf_counter()
+    for n, k, d in batch:
+        a = time.perf_counter()
+        srw.solve(n, k, d)
+        lat.append((time.perf_counter() - a) * 1e3)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t
+    sizes = sorted({n for n, _, _, _ in probs})
+    return {"workload": args.batch_workload, "automata": len(batch),
+            "members": f"the members with n <= {args.batch_nmax} of the seeded 4096-member batch "
+                       f"(n~U[32,320], k~U{{2,3}}; here n in [{sizes[0]}, {sizes[-1]}])"
+                       if args.batch_nmax else "all members",
+            "batched_automata_per_s": len(batch) / tb, "batched_ms": tb * 1e3,
+            "plain_automata_per_s": len(batch) / tp, "plain_ms": tp * 1e3,
+            "batched_over_plain": tp / tb,
+            "plain_p50_ms": float(np.percentile(lat, 50)), "plain_p99_ms": float(np.percentile(lat, 99)),
+            "oracle_checked": checked}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="n256k2x10+cerny16-32")
+    ap.add_argument("--workload", default="n450k2")
+    ap.add_argument("--batch-workload", default="mix4096-n32-320-k2-3",
+                    help="batched-vs-plain comparison: this workload ...")
+    ap.add_argument("--batch-nmax", type=int, default=160,
+                    help="... its members with n <= BATCH_NMAX (0: all)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparison")
     ap.add_argument("--cpu-budget", type=float, default=40.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--oracle-one", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--oracle-steps", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--oracle-max-steps", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
                     help="summarize rocprofv3 FETCH_SIZE / WRITE_SIZE counter files of a run "
                          "with --calib-copy-mb 256 and exit (no GPU)")
@@ -383,6 +535,9 @@ def main():
     if args.oracle_one:
         oracle_one(args.oracle_one)
         return
+    if args.oracle_steps:
+        oracle_steps(args.oracle_steps, args.oracle_max_steps)
+        return
     if args.pmc_summary:
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.workload, args.pmc_out,
                     args.pmc_src)
@@ -400,7 +555,11 @@ def main():
         print(json.dumps(serve_bench(args, srw)))
         return
     probs = workload(args.workload, srw, args.count, args.nmax)   # host-only calls so far
-    cpu = None if args.no_cpu else cpu_baseline(probs, args.cpu_budget)
+    stored = stored_oracle_values()
+    cpu = None
+    if not args.no_cpu:
+        cpu = (cpu_baseline_steps(probs[0], args.cpu_budget) if len(probs) == 1
+               else cpu_baseline(probs, args.cpu_budget))
 
     import torch
     torch.cuda.set_device(0)
@@ -421,14 +580,18 @@ def main():
     for _ in range(args.warmup):
         res = srw.solve_batch(batch)
         assert all(st == 0 for st, _, _ in res), res
+    checked = check_against_oracle(probs, res, stored) if args.warmup else 0
     # timed region: only the meet launches carry HIP events (profile 2); the
     # per-class events of profile 1 serialize the queue between kernels
     srw.reset_stats()
     srw.set_option("profile", 2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    step_ms = []
     for s in range(args.steps):
+        a = time.perf_counter()
         res = srw.solve_batch(batch)
+        step_ms.append((time.perf_counter() - a) * 1e3)
         print(f"step {s + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -467,13 +630,16 @@ def main():
                       " (uniform delta, seeded SplitMix64, first synchronizing draw)"),
                    "path": "srw_solve_batch"},
         "automata_per_s": len(probs) / per_step,
+        "step_p50_ms": float(np.percentile(step_ms, 50)),
+        "step_p99_ms": float(np.percentile(step_ms, 99)),
+        "oracle_checked": f"{checked} of {len(probs)} results equal stored oracle values (r and word)",
         "subsets_per_step": cand,
         "pairs_per_step": stats["pairs"] / args.steps,
         "kernels": class_table(cls_stats),
         "kernels_note": "per-class times of one extra pass with every class timed",
         "roofline": roofline(stats, cls_stats, args.workload),
     }
-    if not args.no_plain:
+    if not args.no_plain and len(batch) > 1:
         lat = []
         srw.reset_stats()
         torch.cuda.synchronize()
@@ -489,6 +655,8 @@ def main():
                         "p50_ms": float(np.percentile(lat, 50)),
                         "p99_ms": float(np.percentile(lat, 99))}
         out["batched_over_plain"] = out["automata_per_s"] / out["plain"]["automata_per_s"]
+    if not args.no_batch:
+        out["batched_vs_plain"] = batched_vs_plain(args, srw, stored)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out))

@@ -159,6 +159,12 @@ int srw_set_stream(void *hip_stream);
  *   "small_cand"  steps with at most this many candidates (and a small
  *                 LDS-tile meet) run in one block, one launch for the whole
  *                 step (default 2048; 0: never)
+ *   "persist"     1 (default): the first steps of every newly admitted
+ *                 automaton run in one launch, a block per automaton
+ *                 stepping it for as long as its steps are small in the
+ *                 sense of "small_cand" (with the schedule 0 side rule);
+ *                 0: every step is launched by the host.  The same
+ *                 results either way
  *   "deadline_ms" per automaton, from its admission: a solve still running
  *                 after this long ends with SRW_ETIMEOUT (0: no deadline)
  *   "verbose"     1: one line per step of a single solve on stderr

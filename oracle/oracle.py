@@ -217,6 +217,21 @@ def bidir(n, k, delta, meet=MEET_MARK, sched=None, max_steps=1 << 20,
     return rr, ww, info
 
 
+def bidir_steps(n, k, delta, max_steps, meet=MEET_MARK):
+    """The plain bidirectional search stopped after at most `max_steps`
+    expansion steps (or at the meet, whichever comes first).  Returns
+    (done, info): done is True when the searches met; info holds the run
+    statistics of the steps taken (the benchmark's bounded CPU sample)."""
+    d = _delta(delta)
+    r = ctypes.c_int32(-1)
+    stats = np.zeros(len(STAT_NAMES), dtype=np.int64)
+    rc = lib().orc_bidir(n, k, _ptr(d, ctypes.c_int32), meet, None, 0, max_steps,
+                         ctypes.byref(r), None, 0, None, _ptr(stats, ctypes.c_int64), None)
+    if rc not in (OK, ELIMIT):
+        raise OracleError(rc, "bidir_steps")
+    return rc == OK, dict(zip(STAT_NAMES, (int(x) for x in stats)))
+
+
 def _levels(h, side, W):
     L = lib()
     nlev = ctypes.c_int32(0)

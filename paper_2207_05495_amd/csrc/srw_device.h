@@ -96,6 +96,39 @@ struct StepDesc {
     u64 *res;
 };
 
+// A block that runs every step of one automaton by itself for as long as
+// the steps stay small (k_run_small): the search's buffers, as the host set
+// them up, and the limits within which the block may go on.
+struct RunState;
+struct RunDesc {
+    int32_t n, k, W, max_lev;  // max_lev: entries of each side's level offset array
+    const uint16_t *delta;     // delta[a*n + q]
+    u64 *rows[2];              // per side (0 forward, 1 inverse): stored rows
+    u32 *par[2];               // parent keys
+    u64 *tab[2];               // visited hash sets
+    u64 tab_mask[2];           // capacity - 1
+    int64_t rows_cap[2];       // rows of capacity
+    int64_t *off[2];           // level L of side s: rows off[s][L] .. off[s][L+1]-1
+    u64 *cand;                 // candidates of a step
+    u32 *cslot;
+    int64_t cand_cap;
+    u64 *colT;                 // the current inverse level transposed: colT_cap words
+    int64_t colT_cap;          // state-major, then colT_cap words tile-major
+    u64 *ysig;                 // signature of each set of the current inverse level
+    int64_t ysig_cap;
+    int64_t small_cand;        // most candidates of a step run here
+    RunState *st;
+};
+struct RunState {
+    int64_t nrows[2];          // in/out: rows stored per side
+    int32_t nlev[2];           // in/out: levels per side (level 0 included)
+    int32_t status;            // out: 0 the next step is not small, 1 met, 2 a list became empty
+    int32_t steps;             // out: steps run here
+    u64 best;                  // out: the least meeting pair (i << 32 | j), when met
+    u64 res[2];                // step results (new level size, meeting pair)
+    int64_t candidates, unique, pairs;   // out: over the steps run here
+};
+
 constexpr int kKeyBits = 16;             // sort key: the 16 most frequent states
 constexpr int kSortBins = 1 << kKeyBits;
 

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -33,8 +34,9 @@ hipError_t launch_scan(const StepDesc *, int, const u32 *, u32 *, hipStream_t);
 hipError_t launch_compact(const StepDesc *, const int64_t *, int, int64_t, const u32 *, hipStream_t);
 hipError_t launch_transpose(const StepDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_transpose_rows(const TransposeDesc *, const int64_t *, int, int64_t, hipStream_t);
-hipError_t launch_meet(const StepDesc *, const int64_t *, int, int, int, int64_t, int64_t, u64 *, hipStream_t);
+hipError_t launch_meet(const StepDesc *, const int64_t *, int, int, int, int64_t, int64_t, bool, u64 *, hipStream_t);
 hipError_t launch_step_small(const StepDesc *, const int32_t *, int, u64 *, hipStream_t);
+hipError_t launch_run_small(const RunDesc *, int, int, u64 *, hipStream_t);
 hipError_t launch_copy(const CopyDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_ysort(const StepDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_init(const InitDesc *, const int64_t *, int, int64_t, hipStream_t);
@@ -145,19 +147,32 @@ struct Backing {
     void *(*alloc)(size_t, void *) = nullptr;
     void (*free)(void *, void *) = nullptr;
     void *ctx = nullptr;
+    bool own_stream_only = false;   // the memory is used on the engine's stream alone
 };
 
 // Power-of-two size classes.  Blocks up to 4 MiB are carved from 64 MiB
 // slabs; larger ones are separate backing allocations.  Freed blocks are
 // cached per class and reused; everything returns to the backing allocator
 // when the pool is destroyed.  `budget` caps the bytes taken from backing.
+// The search's own buffers may take all but `reserve` bytes of it; the
+// engine's small per-step buffers (descriptors, results, counters) may use
+// the reserve too, so that a search that fills its share of the budget ends
+// in SRW_ENOMEM for that search instead of failing the step of every other.
+// Every block is used on stream `st`: before a block goes back to the
+// backing allocator, the stream is drained, and after an external
+// allocator hands over a block, the stream waits for the legacy default
+// stream (on which such an allocator may still have work queued).
 class Pool {
   public:
-    Pool(Backing b, int64_t budget) : b_(b), budget_(budget) {}
-    ~Pool() {
-        for (auto &c : chunks_) backing_free(c.first);
+    Pool(Backing b, int64_t budget, hipStream_t st) : b_(b), budget_(budget), st_(st) {
+        if (b_.alloc && !b_.own_stream_only) HIPCHK(hipEventCreateWithFlags(&ev_ext_, hipEventDisableTiming));
     }
-    void *alloc(size_t bytes) {
+    ~Pool() {
+        if (!chunks_.empty()) (void)hipStreamSynchronize(st_);
+        for (auto &c : chunks_) backing_free(c.first);
+        if (ev_ext_) (void)hipEventDestroy(ev_ext_);
+    }
+    void *alloc(size_t bytes, bool internal = false) {
         const int c = cls_of(bytes);
         const size_t size = (size_t)256 << c;
         if (!free_[c].empty()) {
@@ -169,10 +184,10 @@ class Pool {
         void *p = nullptr;
         if (size <= kSmallMax) {
             if (slab_left_ < size) {
-                char *s = (char *)backing_alloc(kSlab);
+                char *s = (char *)backing_alloc(kSlab, internal);
                 if (!s) {
                     trim();
-                    s = (char *)backing_alloc(kSlab);
+                    s = (char *)backing_alloc(kSlab, internal);
                     if (!s) return nullptr;
                 }
                 slab_ = s;
@@ -182,10 +197,10 @@ class Pool {
             slab_ += size;
             slab_left_ -= size;
         } else {
-            p = backing_alloc(size);
+            p = backing_alloc(size, internal);
             if (!p) {
                 trim();
-                p = backing_alloc(size);
+                p = backing_alloc(size, internal);
                 if (!p) return nullptr;
             }
             big_.insert({p, size});
@@ -206,6 +221,8 @@ class Pool {
     int64_t peak() const { return peak_; }
     int64_t budget() const { return budget_; }
     void set_budget(int64_t b) { budget_ = b; }
+    // bytes of the budget kept for the engine's own per-step buffers
+    int64_t reserve() const { return std::min<int64_t>(kReserve, budget_ / 4); }
 
   private:
     static int cls_of(size_t bytes) {
@@ -218,12 +235,16 @@ class Pool {
         in_use_ += (int64_t)size;
         peak_ = std::max(peak_, in_use_);
     }
-    void *backing_alloc(size_t bytes) {
-        if (reserved_ + (int64_t)bytes > budget_) return nullptr;
+    void *backing_alloc(size_t bytes, bool internal) {
+        if (reserved_ + (int64_t)bytes > budget_ - (internal ? 0 : reserve())) return nullptr;
         void *p = nullptr;
         if (b_.alloc) {
             p = b_.alloc(bytes, b_.ctx);
             if (!p) return nullptr;
+            if (ev_ext_) {
+                HIPCHK(hipEventRecord(ev_ext_, nullptr));
+                HIPCHK(hipStreamWaitEvent(st_, ev_ext_, 0));
+            }
         } else {
             if (hipMalloc(&p, bytes) != hipSuccess) {
                 (void)hipGetLastError();
@@ -238,8 +259,14 @@ class Pool {
         if (b_.free) b_.free(p, b_.ctx);
         else (void)hipFree(p);
     }
-    // hand cached large blocks back to the backing allocator
+    // hand cached large blocks back to the backing allocator, once the
+    // stream is done with them
     void trim() {
+        bool any = false;
+        for (int c = 0; c < 48; ++c)
+            if ((size_t)256 << c > kSmallMax && !free_[c].empty()) any = true;
+        if (!any) return;
+        HIPCHK(hipStreamSynchronize(st_));
         for (int c = 0; c < 48; ++c) {
             const size_t size = (size_t)256 << c;
             if (size <= kSmallMax) continue;
@@ -260,8 +287,11 @@ class Pool {
     }
     static constexpr size_t kSlab = (size_t)64 << 20;
     static constexpr size_t kSmallMax = (size_t)4 << 20;
+    static constexpr int64_t kReserve = (int64_t)128 << 20;
     Backing b_;
     int64_t budget_, reserved_ = 0, in_use_ = 0, peak_ = 0;
+    hipStream_t st_;
+    hipEvent_t ev_ext_ = nullptr;
     std::vector<void *> free_[48];
     std::unordered_map<void *, int> cls_;
     std::unordered_map<void *, size_t> big_;
@@ -270,22 +300,40 @@ class Pool {
     size_t slab_left_ = 0;
 };
 
-// pinned host buffer that only grows
+// pinned host buffer that only grows.  With `pageable` set (an engine that
+// may not allocate device or pinned memory) it is ordinary host memory, and
+// the next user waits for the whole stream instead of an event.
 struct Pinned {
     void *p = nullptr;
     size_t cap = 0;
     hipEvent_t ev = nullptr;     // recorded after the last copy that reads the buffer
+    bool pageable = false;
+    std::vector<char> host;
+    hipStream_t last = nullptr;  // pageable: the stream of the last copy out of it
     // the buffer, once the last copy out of it has been done
     void *acquire(size_t bytes) {
+        if (pageable) {
+            if (last) HIPCHK(hipStreamSynchronize(last));
+            last = nullptr;
+            return need(bytes);
+        }
         if (ev) HIPCHK(hipEventSynchronize(ev));
         return need(bytes);
     }
     // a copy out of the buffer has been enqueued on `st`
     void issued(hipStream_t st) {
+        if (pageable) {
+            last = st;
+            return;
+        }
         if (!ev) HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         HIPCHK(hipEventRecord(ev, st));
     }
     void *need(size_t bytes) {
+        if (pageable) {
+            if (bytes > host.size()) host.resize(std::max(std::max(bytes, 2 * host.size()), (size_t)1 << 16));
+            return host.data();
+        }
         if (bytes > cap) {
             if (p) (void)hipHostFree(p);
             p = nullptr;
@@ -328,6 +376,8 @@ struct Problem {
     u64 *colT = nullptr;      // current inverse level transposed: colT_cap words state-major, then colT_cap tile-major
     int64_t colT_cap = 0;     // words
     u64 *ysig = nullptr;      // signature (OR of the words) of each set of the current inverse level
+    int64_t *d_off = nullptr; // level offsets of both sides for k_run_small: 2 x max_lev
+    int32_t max_lev = 0;
     int64_t ysig_cap = 0;     // words
     // cardinality order of the current inverse level (ys_valid: it is in that order)
     u32 *ys_hist = nullptr, *ys_cnt = nullptr, *ys_idx = nullptr;
@@ -368,6 +418,7 @@ struct Options {
     int64_t meet_rows = kRowBatchMax;   // chunked meet: row tests up to this many candidates per group
     int64_t meet_groups = 16;           // chunked meet: tile groups per work item (upper limit)
     int64_t small_cand = 2048;          // steps with at most this many candidates run in one block (0: never)
+    int persist = 1;                    // 1: the small steps of a new automaton run in one launch (k_run_small)
     int64_t ysort = 0;                  // new inverse levels of at least this many candidates go in cardinality order (0: never)
     int64_t meet_grid = 0;              // meet blocks per launch (0: one per work item)
     int64_t meet_order = 1;             // chunked meet items: 0 tile-range-major, 1 chunk-major
@@ -378,6 +429,7 @@ struct Options {
     double deadline_ms = 0;        // per automaton, from admission (0: none)
 };
 
+// 64-bit finaliser of MurmurHash3 (Appleby), constants as published
 static uint64_t mix64(uint64_t z) {
     z ^= z >> 33;
     z *= 0xff51afd7ed558ccdull;
@@ -391,9 +443,14 @@ static uint64_t mix64(uint64_t z) {
 
 class Engine {
   public:
-    Engine(int device, Backing backing, int64_t budget, hipStream_t ext_stream)
+    // pageable: staging buffers in ordinary host memory (no pinned
+    // allocations at all; the no-alloc entry point runs such an engine)
+    Engine(int device, Backing backing, int64_t budget, hipStream_t ext_stream, bool pageable = false)
         : device_(device), backing_(backing) {
         HIPCHK(hipSetDevice(device_));
+        for (Pinned *q : {&pin_delta_, &pin_step_, &pin_res_, &pin_trace_, &pin_init_, &pin_misc_, &pin_clear_,
+                          &pin_copy_, &pin_run_})
+            q->pageable = pageable;
         if (ext_stream) {
             stream_ = ext_stream;
         } else {
@@ -405,7 +462,7 @@ class Engine {
             HIPCHK(hipMemGetInfo(&fr, &tot));
             budget = (int64_t)(fr * 0.8);
         }
-        pool_.reset(new Pool(backing_, budget));
+        pool_.reset(new Pool(backing_, budget, stream_));
         for (int c = 0; c < 16; ++c) HIPCHK(hipEventCreate(&ev_[c]));
         for (int c = 0; c < 2 * kMaxW; ++c) HIPCHK(hipEventCreate(&ev_meet_[c]));
         memset(&stats_, 0, sizeof stats_);
@@ -487,7 +544,10 @@ class Engine {
                 }
             }
             pending.swap(waiting);
-            if (!fresh.empty()) init(fresh);
+            if (!fresh.empty()) {
+                init(fresh);
+                run_small(fresh);
+            }
             if (active.empty()) continue;
             step(active);
             std::vector<Problem *> still;
@@ -521,9 +581,33 @@ class Engine {
             while (s.tab_cap < 4 * cap0) s.tab_cap <<= 1;
             s.tab = (u64 *)A((size_t)s.tab_cap * 8);
         }
-        p->colT_cap = ceil_div(n, 64) * 64 * W;
+        int64_t tiles0 = ceil_div(n, 64);
+        if (persist_ok()) {
+            // room for the steps k_run_small may take before the first large
+            // one: kPersistRows sets per side, one small step of candidates
+            const int64_t cc = std::min<int64_t>(opt.small_cand, kPersistCand);
+            for (int sd = 0; sd < 2; ++sd) {
+                SideState &s = p->s[sd];
+                pool_->free(s.rows);
+                pool_->free(s.par);
+                pool_->free(s.tab);
+                s.cap = std::max<int64_t>(cap0, kPersistRows);
+                s.rows = (u64 *)A((size_t)s.cap * W * 8);
+                s.par = (u32 *)A((size_t)s.cap * 4);
+                s.tab_cap = 1024;
+                while (s.tab_cap < 4 * s.cap) s.tab_cap <<= 1;
+                s.tab = (u64 *)A((size_t)s.tab_cap * 8);
+            }
+            p->cand_cap = p->cslot_cap = cc;
+            p->cand = (u64 *)A((size_t)cc * W * 8);
+            p->cslot = (u32 *)A((size_t)cc * 4);
+            tiles0 = std::max(tiles0, ceil_div(cc, 64));
+            p->max_lev = (int32_t)std::min<int64_t>(kPersistLevels, std::max<int64_t>(128, (int64_t)n * n + 2));
+            p->d_off = (int64_t *)A((size_t)2 * p->max_lev * 8);
+        }
+        p->colT_cap = tiles0 * 64 * W;
         p->colT = (u64 *)A((size_t)p->colT_cap * 16);   // state-major, then tile-major
-        p->ysig_cap = ceil_div(n, 64) * 64;
+        p->ysig_cap = tiles0 * 64;
         p->ysig = (u64 *)A((size_t)p->ysig_cap * 8);
         if (!ok) {
             release(p);
@@ -676,7 +760,7 @@ class Engine {
         if ((int64_t)nseg * 2 > res_cap_) {
             pool_->free(d_res_);
             res_cap_ = std::max<int64_t>((int64_t)nseg * 2, 2 * res_cap_);
-            d_res_ = (u64 *)pool_->alloc((size_t)res_cap_ * 8);
+            d_res_ = (u64 *)pool_->alloc((size_t)res_cap_ * 8, true);
             if (!d_res_) throw HipFailure{hipErrorOutOfMemory, "step result buffer"};
         }
         for (int i = 0; i < nseg; ++i) {
@@ -789,8 +873,8 @@ class Engine {
             pool_->free(d_cnt_);
             pool_->free(d_off_);
             cblk_cap_ = std::max(ncb, 2 * cblk_cap_);
-            d_cnt_ = (u32 *)pool_->alloc((size_t)cblk_cap_ * 4);
-            d_off_ = (u32 *)pool_->alloc((size_t)cblk_cap_ * 4);
+            d_cnt_ = (u32 *)pool_->alloc((size_t)cblk_cap_ * 4, true);
+            d_off_ = (u32 *)pool_->alloc((size_t)cblk_cap_ * 4, true);
             if (!d_cnt_ || !d_off_) throw HipFailure{hipErrorOutOfMemory, "compaction counters"};
         }
         // upload descriptors + the four block prefixes in one copy
@@ -830,11 +914,7 @@ class Engine {
         const int32_t *dsmall = (const int32_t *)(dblob + oL);
         const int64_t *dpq = (const int64_t *)(dblob + oQ);
 
-        if (opt.profile && !d_ops_) {
-            d_ops_ = (u64 *)pool_->alloc(kOpsWords * sizeof(u64));
-            if (!d_ops_) throw HipFailure{hipErrorOutOfMemory, "meet counters"};
-            HIPCHK(launch_fill(d_ops_, kOpsWords, 0, stream_));
-        }
+        ensure_ops();
         prof_begin(0);
         HIPCHK(launch_step_small(dD, dsmall, nsmall, opt.profile ? d_ops_ : nullptr, stream_));
         HIPCHK(launch_expand(dD, dpe, nseg, pe[nseg], stream_));
@@ -868,7 +948,9 @@ class Engine {
                 HIPCHK(hipEventRecord(ev_meet_[2 * (W - 1)], stream_));
                 meet_used_[W - 1] = true;
             }
-            HIPCHK(launch_meet(dD, dpm, s0, s1, W, pm[s1] - pm[s0], opt.meet_grid,
+            bool ys = false;                       // an inverse level in cardinality order
+            for (int i = s0; i < s1; ++i) ys = ys || D[i].Yidx != nullptr;
+            HIPCHK(launch_meet(dD, dpm, s0, s1, W, pm[s1] - pm[s0], opt.meet_grid, ys,
                                opt.profile ? d_ops_ + (int64_t)(W - 1) * kOpsSlots * kOpsStride : nullptr,
                                stream_));
             if (opt.profile) HIPCHK(hipEventRecord(ev_meet_[2 * (W - 1) + 1], stream_));
@@ -931,12 +1013,153 @@ class Engine {
         stats_.ms[7] += t4 - t0;
     }
 
+    // The steps of newly admitted automata, in one launch per set width: a
+    // block per automaton steps it until the searches meet or until a step
+    // is too large for one block; the host then takes over from the state
+    // the block left (rows, level offsets).  Met automata are traced here.
+    void run_small(std::vector<Problem *> &ps) {
+        std::vector<Problem *> q;
+        for (Problem *p : ps)
+            if (p->status == 1 && p->d_off && p->s[0].nlev() == 1 && p->s[1].nlev() == 1) q.push_back(p);
+        if (q.empty()) return;
+        std::stable_sort(q.begin(), q.end(), [](Problem *a, Problem *b) { return a->W < b->W; });
+        const int nq = (int)q.size();
+        const size_t szD = align8(sizeof(RunDesc) * nq), szS = align8(sizeof(RunState) * nq);
+        char *dblob = dev_need(run_blob_, run_blob_cap_, szD + szS);
+        char *h = (char *)pin_run_.acquire(szD + szS);
+        RunDesc *D = (RunDesc *)h;
+        RunState *S = (RunState *)(h + szD);
+        RunState *dS = (RunState *)(dblob + szD);
+        for (int i = 0; i < nq; ++i) {
+            Problem *p = q[i];
+            RunDesc &r = D[i];
+            memset(&r, 0, sizeof r);
+            r.n = p->n;
+            r.k = p->k;
+            r.W = p->W;
+            r.max_lev = p->max_lev;
+            r.delta = p->d_delta;
+            for (int sd = 0; sd < 2; ++sd) {
+                SideState &s = p->s[sd];
+                r.rows[sd] = s.rows;
+                r.par[sd] = s.par;
+                r.tab[sd] = s.tab;
+                r.tab_mask[sd] = (u64)(s.tab_cap - 1);
+                r.rows_cap[sd] = s.cap;
+                r.off[sd] = p->d_off + (int64_t)sd * p->max_lev;
+            }
+            r.cand = p->cand;
+            r.cslot = p->cslot;
+            r.cand_cap = std::min(p->cand_cap, p->cslot_cap);
+            r.colT = p->colT;
+            r.colT_cap = p->colT_cap;
+            r.ysig = p->ysig;
+            r.ysig_cap = p->ysig_cap;
+            r.small_cand = opt.small_cand;
+            r.st = dS + i;
+            RunState &st = S[i];
+            memset(&st, 0, sizeof st);
+            for (int sd = 0; sd < 2; ++sd) {
+                st.nrows[sd] = p->s[sd].nrows;
+                st.nlev[sd] = p->s[sd].nlev();
+            }
+        }
+        ensure_ops();
+        prof_begin(0);
+        HIPCHK(hipMemcpyAsync(dblob, h, szD + szS, hipMemcpyHostToDevice, stream_));
+        pin_run_.issued(stream_);
+        for (int i0 = 0; i0 < nq;) {
+            int i1 = i0;
+            while (i1 < nq && q[i1]->W == q[i0]->W) ++i1;
+            HIPCHK(launch_run_small((const RunDesc *)dblob + i0, i1 - i0, q[i0]->W,
+                                    opt.profile ? d_ops_ : nullptr, stream_));
+            i0 = i1;
+        }
+        prof_end(0);
+        stats_.launches[0]++;
+        RunState *hS = (RunState *)pin_res_.need(szS);
+        HIPCHK(hipMemcpyAsync(hS, dS, szS, hipMemcpyDeviceToHost, stream_));
+        wait_step();
+        prof_collect();
+        // every automaton's level offsets, packed into one buffer by one copy launch
+        std::vector<CopyDesc> cp;
+        std::vector<int64_t> pre(1, 0);
+        int64_t words = 0;
+        for (int i = 0; i < nq; ++i)
+            for (int sd = 0; sd < 2; ++sd) words += 2 * ((int64_t)hS[i].nlev[sd] + 1);
+        char *dpack = dev_need(pack_blob_, pack_blob_cap_, (size_t)words * 4);
+        int64_t o = 0;
+        for (int i = 0; i < nq; ++i)
+            for (int sd = 0; sd < 2; ++sd) {
+                const int64_t cnt = 2 * ((int64_t)hS[i].nlev[sd] + 1);
+                cp.push_back(CopyDesc{(const u32 *)(q[i]->d_off + (int64_t)sd * q[i]->max_lev),
+                                      (u32 *)dpack + o, cnt});
+                pre.push_back(pre.back() + ceil_div(cnt, kCopyPerBlock));
+                o += cnt;
+            }
+        const size_t a = align8(sizeof(CopyDesc) * cp.size()), b = align8(8 * pre.size());
+        char *hc = (char *)pin_copy_.acquire(a + b);
+        memcpy(hc, cp.data(), sizeof(CopyDesc) * cp.size());
+        memcpy(hc + a, pre.data(), 8 * pre.size());
+        char *dc = dev_need(copy_blob_, copy_blob_cap_, a + b);
+        HIPCHK(hipMemcpyAsync(dc, hc, a + b, hipMemcpyHostToDevice, stream_));
+        pin_copy_.issued(stream_);
+        HIPCHK(launch_copy((const CopyDesc *)dc, (const int64_t *)(dc + a), (int)cp.size(), pre.back(), stream_));
+        stats_.launches[6]++;
+        int64_t *hoff = (int64_t *)pin_trace_.need((size_t)words * 4);
+        HIPCHK(hipMemcpyAsync(hoff, dpack, (size_t)words * 4, hipMemcpyDeviceToHost, stream_));
+        HIPCHK(hipStreamSynchronize(stream_));
+        std::vector<Problem *> met;
+        std::vector<u64> metbest;
+        o = 0;
+        for (int i = 0; i < nq; ++i) {
+            Problem *p = q[i];
+            const RunState &st = hS[i];
+            for (int sd = 0; sd < 2; ++sd) {
+                SideState &s = p->s[sd];
+                s.off.assign(hoff + o, hoff + o + st.nlev[sd] + 1);
+                o += st.nlev[sd] + 1;
+                s.nrows = st.nrows[sd];
+            }
+            p->steps += st.steps;
+            stats_.steps += st.steps;
+            stats_.candidates += st.candidates;
+            stats_.cand_words += st.candidates * p->W;
+            stats_.unique += st.unique;
+            stats_.pairs += st.pairs;
+            stats_.pair_words += st.pairs * p->W;
+            stats_.pair_words_w[p->W - 1] += st.pairs * p->W;
+            stats_.bytes_expand += 8 * p->W * (st.candidates / p->k + st.candidates);
+            stats_.bytes_insert += st.candidates * (8 * p->W + 8 + 4);
+            stats_.bytes_compact += st.candidates * 24 + st.unique * (16 * p->W + 12);
+            if (st.status == 1) {
+                met.push_back(p);
+                metbest.push_back(st.best);
+            } else if (st.status == 2) {
+                finish_error(p, SRW_EINTERNAL, "a list became empty before the searches met");
+            }
+        }
+        if (!met.empty()) trace(met, metbest);
+    }
+
     void finish_error(Problem *p, int code, const char *msg = nullptr) {
         p->status = code;
         p->r = -1;
         p->t_done = now_ms();
         if (msg) t_err = msg;
         release(p);
+    }
+
+    // After a step failed on the device memory budget (an allocation of the
+    // engine's own per-step buffers found no room even in the reserve): let
+    // the queued work finish and drop the copies that step had planned.  The
+    // caller then fails the problems of that step with SRW_ENOMEM.
+    void recover() {
+        (void)hipStreamSynchronize(stream_);
+        (void)hipGetLastError();
+        for (void *q : pend_free_) pool_->free(q);
+        pend_copy_.clear();
+        pend_free_.clear();
     }
 
     // lists of the last kept problem
@@ -956,6 +1179,22 @@ class Engine {
 
   private:
     static size_t align8(size_t x) { return (x + 7) & ~(size_t)7; }
+
+    // the automata of this engine start with k_run_small (it keeps the side
+    // rule of schedule 0 and the LDS-tile meet of one-block steps)
+    // the meet's operation counters, once profiling is on
+    void ensure_ops() {
+        if (opt.profile && !d_ops_) {
+            d_ops_ = (u64 *)pool_->alloc(kOpsWords * sizeof(u64), true);
+            if (!d_ops_) throw HipFailure{hipErrorOutOfMemory, "meet counters"};
+            HIPCHK(launch_fill(d_ops_, kOpsWords, 0, stream_));
+        }
+    }
+
+    bool persist_ok() const { return opt.persist && opt.small_cand > 0 && opt.schedule == 0 && opt.meet != 2; }
+    static constexpr int64_t kPersistRows = 16384;   // rows per side while k_run_small steps
+    static constexpr int64_t kPersistCand = 8192;    // candidates of its largest step
+    static constexpr int64_t kPersistLevels = 4096;  // levels per side it can record
 
     int choose_side(Problem *p) {
         const int64_t lf = p->s[0].cur(), lb = p->s[1].cur();
@@ -1172,6 +1411,7 @@ class Engine {
         }
         pool_->free(p->colT); p->colT = nullptr; p->colT_cap = 0;
         pool_->free(p->ysig); p->ysig = nullptr; p->ysig_cap = 0;
+        pool_->free(p->d_off); p->d_off = nullptr; p->max_lev = 0;
         pool_->free(p->ys_hist); pool_->free(p->ys_cnt); pool_->free(p->ys_idx);
         p->ys_hist = p->ys_cnt = p->ys_idx = nullptr;
         p->ys_cap = 0;
@@ -1194,7 +1434,7 @@ class Engine {
         if ((int64_t)bytes > cap) {
             pool_->free(p);
             cap = std::max<int64_t>((int64_t)bytes, 2 * cap);
-            p = pool_->alloc((size_t)cap);
+            p = pool_->alloc((size_t)cap, true);
             if (!p) throw HipFailure{hipErrorOutOfMemory, "descriptor blob"};
         }
         return (char *)p;
@@ -1285,11 +1525,11 @@ class Engine {
     hipEvent_t ev_[16], ev_meet_[2 * kMaxW];
     bool meet_used_[kMaxW] = {};
     bool prof_used_[8] = {};
-    Pinned pin_delta_, pin_step_, pin_res_, pin_trace_, pin_init_, pin_misc_, pin_clear_, pin_copy_;
+    Pinned pin_delta_, pin_step_, pin_res_, pin_trace_, pin_init_, pin_misc_, pin_clear_, pin_copy_, pin_run_;
     std::vector<CopyDesc> pend_copy_;
     std::vector<void *> pend_free_;
-    void *copy_blob_ = nullptr, *delta_blob_ = nullptr;
-    int64_t copy_blob_cap_ = 0, delta_blob_cap_ = 0;
+    void *copy_blob_ = nullptr, *delta_blob_ = nullptr, *run_blob_ = nullptr, *pack_blob_ = nullptr;
+    int64_t copy_blob_cap_ = 0, delta_blob_cap_ = 0, run_blob_cap_ = 0, pack_blob_cap_ = 0;
     void *step_blob_ = nullptr, *trace_blob_ = nullptr, *init_blob_ = nullptr, *rehash_blob_ = nullptr,
          *clear_blob_ = nullptr;
     int64_t step_blob_cap_ = 0, trace_blob_cap_ = 0, init_blob_cap_ = 0, misc_blob_cap_ = 0,
@@ -1433,6 +1673,7 @@ int srw_set_option(const char *key, int64_t v) {
     else if (k == "meet_rows") { if (v < 0) return set_error(SRW_EINVAL, "meet_rows"); x.opt.meet_rows = v; }
     else if (k == "ysort") { if (v < 0) return set_error(SRW_EINVAL, "ysort"); x.opt.ysort = v; }
     else if (k == "small_cand") { if (v < 0 || v > (1 << 20)) return set_error(SRW_EINVAL, "small_cand"); x.opt.small_cand = v; }
+    else if (k == "persist") { if (v < 0 || v > 1) return set_error(SRW_EINVAL, "persist"); x.opt.persist = (int)v; }
     else if (k == "meet_groups") { if (v < 1 || v > 4096) return set_error(SRW_EINVAL, "meet_groups"); x.opt.meet_groups = v; }
     else if (k == "meet_grid") { if (v < 0) return set_error(SRW_EINVAL, "meet_grid"); x.opt.meet_grid = v; }
     else if (k == "meet_order") { if (v < 0 || v > 1) return set_error(SRW_EINVAL, "meet_order"); x.opt.meet_order = v; }
@@ -1500,9 +1741,17 @@ int srw_solve_batch(int32_t count, const int32_t *n, const int32_t *k, const int
             e->run(work);
             e->opt.keep_levels = keep;
         } catch (const HipFailure &f) {
-            for (Problem *p : work) status[p->index] = SRW_EDEVICE;
+            // members that finished keep their results; the others fail with
+            // SRW_ENOMEM (the engine's budget) or SRW_EDEVICE (a HIP error)
+            const bool oom = f.e == hipErrorOutOfMemory;
+            for (Problem *p : work)
+                if (p->status == 1) p->status = oom ? SRW_ENOMEM : SRW_EDEVICE;
             x.eng.reset();
-            return device_error(f);
+            if (!oom) {
+                for (Problem *p : work) status[p->index] = p->status;
+                return device_error(f);
+            }
+            set_error(SRW_ENOMEM, "device memory budget exhausted in " + f.where);
         }
     }
     for (Problem *p : work) {
@@ -1537,6 +1786,8 @@ int srw_solve(int32_t n, int32_t k, const int32_t *delta, int32_t *r, uint8_t *w
     } catch (const HipFailure &f) {
         x.eng.reset();
         delete p;
+        if (f.e == hipErrorOutOfMemory)   // the budget, even its reserve, ran out
+            return set_error(SRW_ENOMEM, "device memory budget exhausted in " + f.where);
         return device_error(f);
     }
     rc = p->status;
@@ -1656,8 +1907,20 @@ static void server_loop(srw_server *s, int li) {
                 }
             }
             pending.swap(waiting);
-            if (!fresh.empty()) eng->init(fresh);
-            if (!active.empty()) eng->step(active);
+            try {
+                if (!fresh.empty()) {
+                    eng->init(fresh);
+                    eng->run_small(fresh);
+                }
+                if (!active.empty()) eng->step(active);
+            } catch (const HipFailure &f) {
+                if (f.e != hipErrorOutOfMemory) throw;
+                // the lane's memory budget, not the device: the problems of
+                // this step fail with SRW_ENOMEM and the lane goes on
+                eng->recover();
+                for (Problem *p : active)
+                    if (p->status == 1) eng->finish_error(p, SRW_ENOMEM, "device memory budget exhausted");
+            }
             std::vector<Problem *> still;
             for (Problem *p : active) {
                 if (p->status == 1 && s->deadline_ms > 0 && now_ms() - p->t_admit > s->deadline_ms)

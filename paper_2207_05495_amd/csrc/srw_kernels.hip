@@ -62,6 +62,7 @@ __device__ __forceinline__ int find_seg(const int64_t *pre, int nseg, int64_t b)
     return lo;
 }
 
+// 64-bit finaliser of MurmurHash3 (Appleby), constants as published
 __device__ __forceinline__ u64 fmix64(u64 z) {
     z ^= z >> 33;
     z *= 0xff51afd7ed558ccdull;
@@ -107,8 +108,11 @@ __device__ __forceinline__ int lowest_bit(u64 v) { return __ffsll((unsigned long
 // bits of S.  Inverse: Y = delta^-1(S, a) = { q | delta(q, a) in S },
 // gathering one bit of S per state q.  Each thread owns a row of LDS for the
 // bit-addressed side (registers cannot be indexed by a run-time word).
-template <int W>
-__device__ void expand_w(const CONST_AS StepDesc &d, int64_t lb, u64 *lds) {
+// D: the step descriptor as the caller holds it -- in the constant address
+// space (written by the host) or in LDS (built by a block that runs many
+// steps itself).
+template <int W, class D>
+__device__ void expand_w(const D &d, int64_t lb, u64 *lds) {
     const int tid = threadIdx.x;
     const int64_t g = lb * kBS + tid;
     if (g >= d.C) return;
@@ -163,8 +167,8 @@ __global__ void __launch_bounds__(kBS) k_expand(const StepDesc *descs, const int
 
 // ---------------------------------------------------------------- insert
 
-template <int W>
-__device__ void insert_w(const CONST_AS StepDesc &d, int64_t lb) {
+template <int W, class D>
+__device__ void insert_w(const D &d, int64_t lb) {
     const int64_t g = lb * kBS + threadIdx.x;
     if (g >= d.C) return;
     u64 x[W];
@@ -215,7 +219,8 @@ __global__ void __launch_bounds__(kBS) k_insert(const StepDesc *descs, const int
 
 // ------------------------------------------------------------ compaction
 
-__device__ __forceinline__ bool is_winner(const CONST_AS StepDesc &d, int64_t g) {
+template <class D>
+__device__ __forceinline__ bool is_winner(const D &d, int64_t g) {
     const u32 sl = d.cslot[g];
     if (sl == kDrop) return false;
     return (u32)d.tab[sl] == (kCandBit | (u32)g);
@@ -425,8 +430,12 @@ __global__ void __launch_bounds__(kBS) k_transpose_rows(const TransposeDesc *des
 
 // ------------------------------------------------------------------ meet
 
-template <int W>
-__device__ u32 meet_w(const CONST_AS StepDesc &d, int64_t lb, u64 *cols) {
+// YS: the inverse level may be in cardinality order (read through d.Yidx
+// when it is set); without it the level is in its own order and the paths
+// of that order are compiled out.
+template <int W, bool YS, class D>
+__device__ u32 meet_w(const D &d, int64_t lb, u64 *cols) {
+    const u32 *Yidx = YS ? d.Yidx : nullptr;
     const int tid = threadIdx.x;
     const int64_t nX = d.nX >= 0 ? d.nX : (int64_t)d.res[0];
     const int64_t nY = d.nY >= 0 ? d.nY : (int64_t)d.res[0];
@@ -464,13 +473,13 @@ __device__ u32 meet_w(const CONST_AS StepDesc &d, int64_t lb, u64 *cols) {
             }
         }
         if (alive) {
-            if (!d.Yidx) {                 // level order: the lowest bit is the least j
+            if (!Yidx) {                   // level order: the lowest bit is the least j
                 const u64 j = (u64)t * 64 + (u64)lowest_bit(M);
                 atomicMin(d.res + 1, ((u64)i << 32) | j);
                 return nops;
             }
             for (u64 mm = M; mm; mm &= mm - 1)   // cardinality order: every hit
-                atomicMin(d.res + 1, ((u64)i << 32) | (u64)d.Yidx[(u64)t * 64 + lowest_bit(mm)]);
+                atomicMin(d.res + 1, ((u64)i << 32) | (u64)Yidx[(u64)t * 64 + lowest_bit(mm)]);
         }
     }
     return nops;
@@ -509,9 +518,11 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int W>
+template <int W, bool YS>
 __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice) {
     const int lane = threadIdx.x & 63;
+    const u32 *Yidx = YS ? d.Yidx : nullptr;
+    const u32 *Ycnt = YS ? d.Ycnt : nullptr;
     const int64_t nX = d.nX >= 0 ? d.nX : (int64_t)d.res[0];
     const int64_t nY = d.nY >= 0 ? d.nY : (int64_t)d.res[0];
     const int64_t nt = (nY + 63) / 64;
@@ -565,7 +576,7 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
     // inverse level in cardinality order: only its first Ycnt[min |X|] sets
     // can contain a set of this chunk
     int64_t nt_lim = nt;
-    if (d.Ycnt) {
+    if (Ycnt) {
         int sz = 0x7fffffff;
         if (valid) {
             sz = 0;
@@ -577,7 +588,7 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
         int csz = 0;                       // the states of C taken out of each x
 #pragma unroll
         for (int r = 0; r < kCommonMax; ++r) csz += cq[r] >= 0;
-        nt_lim = ((int64_t)d.Ycnt[min(sz + csz, d.n + 1)] + 63) / 64;
+        nt_lim = ((int64_t)Ycnt[min(sz + csz, d.n + 1)] + 63) / 64;
     }
     bool done = !valid || (load_slot(d.res + 1) >> 32) < (u64)orig;
     // slice: candidate indices (u32) in words 0 .. kRowBatchMax/2-1, their
@@ -589,15 +600,15 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
     for (int w = 0; w < W; ++w) xs |= x[w];
     // first round of common columns of group gg, loaded two groups ahead
     // (a group with no candidate is a few dozen instructions, far shorter than
-    // a load).  Lanes past the last tile and unused states load word 0 of YT
-    // and drop it, so the loads need no branch.
+    // a load).  Lanes past the last tile and unused states load word 0 of YT,
+    // so the loads need no branch; the words are used raw and masked where
+    // the group consumes them (a select here would wait for the load).
     auto first_round = [&](int64_t gg, u64 *v) {
         const int64_t tg = gg * 64 + lane;
 #pragma unroll
         for (int r = 0; r < kCommonRound; ++r) {
             const bool ok = tg < nt && cq[r] >= 0;
-            const u64 w = d.YT[ok ? (int64_t)cq[r] * nt + tg : 0];
-            v[r] = ok ? w : ~0ull;
+            v[r] = d.YT[ok ? (int64_t)cq[r] * nt + tg : 0];
         }
     };
     const u64 last_rows = (nY & 63) ? ((1ull << (nY & 63)) - 1ull) : ~0ull;   // the last tile may be partial
@@ -607,23 +618,30 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
         if (__ballot(!done) == 0) return false;
         const int64_t t = g * 64 + lane;
         const bool tv = t < nt_lim;
+        // lanes past the tiles (t >= nt_lim, so also t >= nt) start from 0,
+        // so the raw word they loaded does not matter; an unused state (cq
+        // < 0, uniform over the wave) contributes no column
         u64 m = !tv ? 0ull : (t == nt - 1 ? last_rows : ~0ull);
 #pragma unroll
-        for (int r = 0; r < kCommonRound; ++r) m &= cur[r];
+        for (int r = 0; r < kCommonRound; ++r) m &= cq[r] >= 0 ? cur[r] : ~0ull;
         if (tv) nops += 2 * min(nc, kCommonRound);
-        if (g + 2 < g1) first_round(g + 2, cur);
-        // further common columns, in rounds of independent loads
+        // further common columns, in rounds of independent loads (issued
+        // before the lookahead of group g + 2, so that waiting for them does
+        // not also wait for that lookahead)
 #pragma unroll
         for (int r0 = kCommonRound; r0 < kCommonMax; r0 += kCommonRound) {
             if (cq[r0] < 0 || __ballot(m != 0) == 0) break;
             u64 v[kCommonRound];
 #pragma unroll
-            for (int r = 0; r < kCommonRound; ++r)
-                v[r] = (tv && cq[r0 + r] >= 0) ? d.YT[(int64_t)cq[r0 + r] * nt + t] : ~0ull;
+            for (int r = 0; r < kCommonRound; ++r) {
+                const bool ok = tv && cq[r0 + r] >= 0;
+                v[r] = d.YT[ok ? (int64_t)cq[r0 + r] * nt + t : 0];
+            }
 #pragma unroll
-            for (int r = 0; r < kCommonRound; ++r) m &= v[r];
+            for (int r = 0; r < kCommonRound; ++r) m &= cq[r0 + r] >= 0 ? v[r] : ~0ull;
             if (tv) nops += 2 * min(nc - r0, kCommonRound);
         }
+        if (g + 2 < g1) first_round(g + 2, cur);
         if (__ballot(m != 0) == 0) return true;      // the usual case: no candidate in the group
         // number the candidates: lane order (tile), then bit order
         const u32 pc = (u32)__popcll(m);
@@ -669,14 +687,14 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
                     for (int u = 0; u < 4; ++u) {
                         const u32 cc = c0 + u;
                         if (done || cc >= K || (xs & ~sig[cc]) != 0) continue;
-                        const u32 jc = d.Yidx ? d.Yidx[jl[cc]] : jl[cc];   // index in the level
+                        const u32 jc = Yidx ? Yidx[jl[cc]] : jl[cc];   // index in the level
                         u64 out = 0;
 #pragma unroll
                         for (int w = 0; w < W; ++w) out |= x[w] & ~d.Yrows[(int64_t)jc * W + w];
                         nops += 4 * W;
                         if (out == 0) {
                             atomicMin(d.res + 1, ((u64)orig << 32) | (u64)jc);
-                            done = !d.Yidx;        // cardinality order: a later hit may be smaller
+                            done = !Yidx;          // cardinality order: a later hit may be smaller
                         }
                     }
                 }
@@ -712,12 +730,12 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
                 nops += 2 * (u32)(__popcll(x[w]) - __popcll(b));
             }
             if (alive) {
-                if (!d.Yidx) {
+                if (!Yidx) {
                     atomicMin(d.res + 1, ((u64)orig << 32) | (u64)(tt * 64 + lowest_bit(M)));
                     done = true;
                 } else {
                     for (u64 mm = M; mm; mm &= mm - 1)
-                        atomicMin(d.res + 1, ((u64)orig << 32) | (u64)d.Yidx[tt * 64 + lowest_bit(mm)]);
+                        atomicMin(d.res + 1, ((u64)orig << 32) | (u64)Yidx[tt * 64 + lowest_bit(mm)]);
                 }
             }
         }
@@ -741,7 +759,7 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
 // register count of the narrow widths low).  With `ops` set, the set
 // operations the launch performed (32-bit lane-ops) are added to the
 // kOpsSlots counters at ops (kOpsStride words apart).
-template <int W>
+template <int W, bool YS>
 __global__ void __launch_bounds__(kBS) k_meet(const StepDesc *descs, const int64_t *pre, int s0, int s1, u64 *ops) {
     __shared__ u64 cols[kMeetLdsWords];
     const int64_t base = cref(pre + s0), items = cref(pre + s1) - base;
@@ -752,10 +770,10 @@ __global__ void __launch_bounds__(kBS) k_meet(const StepDesc *descs, const int64
         __syncthreads();   // the previous item is done with cols
         u32 nops;
         if (d.meet_mode == 0) {
-            nops = meet_w<W>(d, li, cols);
+            nops = meet_w<W, YS>(d, li, cols);
         } else {
             const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
-            nops = meet_chunk_w<W>(d, li * (kBS / 64) + wave, cols + wave * kSliceWords);
+            nops = meet_chunk_w<W, YS>(d, li * (kBS / 64) + wave, cols + wave * kSliceWords);
         }
         if (ops) {
             u32 sum = nops;   // at most a few million per wave and item
@@ -788,8 +806,8 @@ __global__ void __launch_bounds__(kBS) k_copy(const CopyDesc *descs, const int64
 // per-phase kernels do the work, so the results are the same; what goes is
 // six dependent launches per step, which dominate when the lists are tiny (a
 // Černý automaton takes (n-1)^2 steps over lists of about n sets).
-template <int W>
-__device__ u32 step_small_w(const CONST_AS StepDesc &d, u64 *lds, u32 *wsum) {
+template <int W, class D>
+__device__ u32 step_small_w(const D &d, u64 *lds, u32 *wsum) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t nb = (d.C + kBS - 1) / kBS;
     for (int64_t lb = 0; lb < nb; ++lb) expand_w<W>(d, lb, lds);
@@ -837,7 +855,7 @@ __device__ u32 step_small_w(const CONST_AS StepDesc &d, u64 *lds, u32 *wsum) {
     const int64_t nmb = d.nXb * d.nYc;
     for (int64_t lb = 0; lb < nmb; ++lb) {
         __syncthreads();                   // the previous tiles are read
-        nops += meet_w<W>(d, lb, lds);
+        nops += meet_w<W, true>(d, lb, lds);
     }
     return nops;
 }
@@ -857,6 +875,163 @@ __global__ void __launch_bounds__(kBS) k_step_small(const StepDesc *descs, const
         for (int off = 32; off > 0; off >>= 1) sum += (u32)__shfl_xor((int)sum, off, 64);
         if ((threadIdx.x & 63) == 0 && sum)
             atomicAdd((unsigned long long *)(ops + ((int64_t)(d.W - 1) * kOpsSlots + blockIdx.x % kOpsSlots) * kOpsStride),
+                      (unsigned long long)sum);
+    }
+}
+
+// One block runs one automaton's search step after step, choosing the side
+// (smaller current list, ties forward) and building each step's descriptor
+// in LDS, for as long as every step stays within what a one-block step
+// handles (at most small_cand candidates, an LDS-tile meet of at most
+// kSmallMeetBlocks blocks) and within the buffers the host gave it.  Each
+// step is the same sequence of device functions as a one-block step launched
+// by the host, so the results are those of the step-by-step search; what
+// goes is the host round trip per step.  At the first step that does not fit
+// the block stops, and the host goes on from the state it left (level
+// offsets, row counts).
+template <int W>
+__device__ u32 run_small_w(const CONST_AS RunDesc &r, StepDesc &sd, u64 *lds, u32 *wsum) {
+    __shared__ int64_t cs[2], cn[2], nr[2];   // current level start and size, rows stored
+    __shared__ int nl[2];                     // levels per side
+    __shared__ int go, dir_s;
+    RunState *st = r.st;
+    const int tid = threadIdx.x;
+    int steps = 0;
+    int64_t cands = 0, uniq = 0, pairs = 0;
+    u32 nops = 0;
+    if (tid == 0) {
+        for (int s = 0; s < 2; ++s) {
+            nr[s] = st->nrows[s];
+            nl[s] = st->nlev[s];
+            if (nl[s] == 1) {               // level 0 only: its offsets are written here
+                r.off[s][0] = 0;
+                r.off[s][1] = nr[s];
+            }
+            cs[s] = r.off[s][nl[s] - 1];
+            cn[s] = nr[s] - cs[s];
+        }
+    }
+    __syncthreads();
+    for (;;) {
+        if (tid == 0) {
+            const int dir = cn[1] < cn[0] ? 1 : 0;
+            const int64_t m = cn[dir];
+            const int64_t C = m * r.k;
+            const int64_t nx_ub = dir == 0 ? C : cn[0];
+            const int64_t ny_ub = dir == 0 ? cn[1] : C;
+            const int tpb = max(1, kMeetTileWords / W);
+            const int64_t nXb = (nx_ub + kBS - 1) / kBS;
+            const int64_t nYc = ((ny_ub + 63) / 64 + tpb - 1) / tpb;
+            const int64_t tiles = (C + 63) / 64;
+            bool ok = C <= r.small_cand && C <= r.cand_cap && nr[dir] + C <= r.rows_cap[dir] &&
+                      2 * (nr[dir] + C) <= (int64_t)r.tab_mask[dir] + 1 && nl[dir] + 1 < r.max_lev &&
+                      nXb * nYc <= kSmallMeetBlocks;
+            if (dir == 1) ok = ok && tiles * 64 * W <= r.colT_cap && tiles * 64 <= r.ysig_cap;
+            go = ok;
+            dir_s = dir;
+            if (ok) {
+                StepDesc &d = sd;
+                d.n = r.n;
+                d.k = r.k;
+                d.W = W;
+                d.dir = dir;
+                d.delta = r.delta;
+                d.m = m;
+                d.par_rows = r.rows[dir] + cs[dir] * W;
+                d.C = C;
+                d.cand = r.cand;
+                d.cslot = r.cslot;
+                d.tab = r.tab[dir];
+                d.tab_mask = r.tab_mask[dir];
+                d.vis_rows = r.rows[dir];
+                d.out_rows = r.rows[dir] + nr[dir] * W;
+                d.out_par = r.par[dir] + nr[dir];
+                d.out_base = nr[dir];
+                d.YT = r.colT;
+                d.YTt = r.colT + r.colT_cap;
+                d.Ysig = r.ysig;
+                if (dir == 0) {
+                    d.X = d.out_rows;
+                    d.nX = -1;
+                    d.Yrows = r.rows[1] + cs[1] * W;
+                    d.nY = cn[1];
+                } else {
+                    d.X = r.rows[0] + cs[0] * W;
+                    d.nX = cn[0];
+                    d.Yrows = d.out_rows;
+                    d.nY = -1;
+                }
+                d.nXb = nXb;
+                d.nYc = nYc;
+                d.tpb = tpb;
+                d.small = 1;
+                d.ntr_waves = dir == 1 ? tiles * W : 0;
+                d.meet_mode = 0;
+                d.ysort = 0;
+                d.Yidx = nullptr;
+                d.Ycnt = nullptr;
+                d.Xidx = nullptr;
+                d.Xcom = nullptr;
+                d.res = st->res;
+            }
+        }
+        __syncthreads();
+        if (!go) break;
+        nops += step_small_w<W>(sd, lds, wsum);
+        __syncthreads();
+        if (tid == 0) {
+            const int dir = dir_s;
+            const int64_t U = (int64_t)load_slot(st->res);
+            const u64 best = load_slot(st->res + 1);
+            cands += sd.C;
+            uniq += U;
+            pairs += dir == 0 ? U * cn[1] : cn[0] * U;
+            cs[dir] = nr[dir];
+            cn[dir] = U;
+            nr[dir] += U;
+            nl[dir] += 1;
+            r.off[dir][nl[dir]] = nr[dir];
+            ++steps;
+            go = 1;
+            if (best != kEmpty) {
+                st->best = best;
+                st->status = 1;
+                go = 0;
+            } else if (U == 0) {
+                st->status = 2;
+                go = 0;
+            }
+        }
+        __syncthreads();
+        if (!go) break;
+    }
+    if (tid == 0) {
+        for (int s = 0; s < 2; ++s) {
+            st->nrows[s] = nr[s];
+            st->nlev[s] = nl[s];
+        }
+        st->steps = steps;
+        st->candidates = cands;
+        st->unique = uniq;
+        st->pairs = pairs;
+    }
+    return nops;
+}
+
+// one block per automaton; one launch per set width W (all its automata)
+template <int W>
+__global__ void __launch_bounds__(kBS) k_run_small(const RunDesc *descs, u64 *ops) {
+    __shared__ u64 lds[kMaxW * kBS];       // expansion rows, then meet tiles
+    __shared__ u32 wsum[kBS / 64];
+    __shared__ StepDesc sd;
+    const CONST_AS RunDesc &r = cref(descs + blockIdx.x);
+    const u32 nops = run_small_w<W>(r, sd, lds, wsum);
+    if (ops) {
+        u32 sum = nops;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) sum += (u32)__shfl_xor((int)sum, off, 64);
+        if ((threadIdx.x & 63) == 0 && sum)
+            atomicAdd((unsigned long long *)(ops + ((int64_t)(r.W - 1) * kOpsSlots + blockIdx.x % kOpsSlots) * kOpsStride),
                       (unsigned long long)sum);
     }
 }
@@ -1092,6 +1267,12 @@ hipError_t launch_copy(const CopyDesc *d, const int64_t *pre, int nseg, int64_t 
     hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
     return launch_checked();
 }
+// count automata, all with W words per set
+hipError_t launch_run_small(const RunDesc *d, int count, int W, u64 *ops, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    SRW_SWITCH_W(W, hipLaunchKernelGGL(k_run_small<W>, dim3((unsigned)count), dim3(kBS), 0, st, d, ops));
+    return launch_checked();
+}
 hipError_t launch_step_small(const StepDesc *d, const int32_t *segs, int count, u64 *ops, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_step_small, dim3((unsigned)count), dim3(kBS), 0, st, d, segs, ops);
@@ -1139,12 +1320,17 @@ hipError_t launch_transpose_rows(const TransposeDesc *d, const int64_t *pre, int
 // segments s0..s1-1 all have width W; `items` = cref(pre + s1) - cref(pre + s0).  At most
 // max_grid blocks (each then loops over several items); short-lived blocks
 // let kernels of other streams onto the GPU between them.
+// ys: some segment of the launch has its inverse level in cardinality order
 hipError_t launch_meet(const StepDesc *d, const int64_t *pre, int s0, int s1, int W, int64_t items,
-                       int64_t max_grid, u64 *ops, hipStream_t st) {
+                       int64_t max_grid, bool ys, u64 *ops, hipStream_t st) {
     if (items <= 0) return hipSuccess;
     const int64_t cap = max_grid > 0 ? std::min<int64_t>(max_grid, kMeetMaxGrid) : kMeetMaxGrid;
     const unsigned grid = (unsigned)(items < cap ? items : cap);
-    SRW_SWITCH_W(W, hipLaunchKernelGGL(k_meet<W>, dim3(grid), dim3(kBS), 0, st, d, pre, s0, s1, ops));
+    if (ys) {
+        SRW_SWITCH_W(W, hipLaunchKernelGGL((k_meet<W, true>), dim3(grid), dim3(kBS), 0, st, d, pre, s0, s1, ops));
+    } else {
+        SRW_SWITCH_W(W, hipLaunchKernelGGL((k_meet<W, false>), dim3(grid), dim3(kBS), 0, st, d, pre, s0, s1, ops));
+    }
     return launch_checked();
 }
 // sort pipeline: pre[0..4] are the block prefixes of zero, hist (= key =

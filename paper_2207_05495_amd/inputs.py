@@ -180,3 +180,26 @@ def mixed_batch(count: int, n_lo: int, n_hi: int, ks, is_sync,
         d, t = first_synchronizing(n, k, s, is_sync)
         out.append({"n": n, "k": k, "seed": s, "attempt": t, "delta": d})
     return out
+
+
+def serve_mix(count: int, nmax: int, kmax: int, is_sync, base: int = BASE_SEED ^ 5):
+    """Requests of the serving workload, in arrival order: 90% random
+    automata (n uniform in [64, nmax], k uniform in 2..kmax), 10% Černý C_n
+    with n uniform in [8, 40].  Returns dicts with n, k, delta, label and,
+    for random members, seed and attempt (the class draws come from numpy's
+    PCG64 seeded with the low 32 bits of ``base``; request i's table is
+    member i of the batch seeded with ``base``)."""
+    rng = np.random.default_rng(base & 0xFFFFFFFF)
+    out = []
+    for i in range(count):
+        if rng.random() < 0.1:
+            n = int(rng.integers(8, 41))
+            out.append({"n": n, "k": 2, "delta": cerny(n), "label": "cerny"})
+        else:
+            n = int(rng.integers(64, nmax + 1))
+            k = int(rng.integers(2, kmax + 1))
+            s = member_seed(base, i)
+            d, t = first_synchronizing(n, k, s, is_sync)
+            out.append({"n": n, "k": k, "delta": d, "seed": s, "attempt": t,
+                        "label": f"k{k}" + ("big" if n > 300 else "")})
+    return out

@@ -35,7 +35,7 @@ def gpu():
 DEFAULTS = (("schedule", 0), ("meet_tiles", 0), ("keep_levels", 0), ("budget", 0), ("meet", 0),
             ("max_slots", 4096), ("meet_rows", 512), ("meet_groups", 16), ("meet_order", 1),
             ("meet_grid", 0), ("small_cand", 2048), ("ysort", 0), ("deadline_ms", 0),
-            ("verbose", 0))
+            ("verbose", 0), ("persist", 1))
 
 
 def say(*a):
@@ -45,6 +45,38 @@ def say(*a):
 def rand_sync(n, k, i, base=I.BASE_SEED):
     d, _ = I.first_synchronizing(n, k, I.member_seed(base, i), O.is_synchronizing)
     return d
+
+
+def _stored():
+    """(r, word) the oracle stored under tests/golden, keyed by the bytes of
+    the transition table (rebuilt from each entry's seed and attempt)."""
+    out = {}
+    for name in sorted(os.listdir(GOLDEN)):
+        if not name.endswith(".json"):
+            continue
+        with open(os.path.join(GOLDEN, name)) as f:
+            rec = json.load(f)
+        for c in rec.get("cases", []):
+            if "r" not in c or "attempt" not in c:
+                continue
+            d = I.random_automaton(c["n"], c["k"], c["seed"], c["attempt"])
+            w = c["word"]
+            out[(c["n"], c["k"], d.tobytes())] = (c["r"], [int(x) for x in w] if isinstance(w, str) else list(w))
+    return out
+
+
+_MEMO = {}
+
+
+def oracle_rw(n, k, d):
+    """(r, word) of the oracle: a value it stored, or computed now (once per
+    session)."""
+    if not _MEMO:
+        _MEMO.update(_stored())
+    key = (n, k, np.asarray(d, dtype=np.int32).tobytes())
+    if key not in _MEMO:
+        _MEMO[key] = tuple(oracle_rw(n, k, d))
+    return _MEMO[key]
 
 
 # --------------------------------------------------------------- golden
@@ -111,7 +143,7 @@ def test_ragged_widths(n, k):
     for i in range(3):
         d = rand_sync(n, k, i, base=77)
         say("ragged", n, k, i)
-        assert srw.solve(n, k, d) == O.bidir(n, k, d)[:2]
+        assert srw.solve(n, k, d) == oracle_rw(n, k, d)
 
 
 def max_size_automaton(n, seed):
@@ -128,7 +160,7 @@ def test_max_width(n):
     for s in range(3):
         d = max_size_automaton(n, s)
         say("max width", n, s)
-        assert srw.solve(n, 2, d) == O.bidir(n, 2, d)[:2]
+        assert srw.solve(n, 2, d) == oracle_rw(n, 2, d)
 
 
 # ------------------------------------------------------ per-level parity
@@ -196,7 +228,7 @@ def test_meet_modes_agree(mode):
         for j, (n, k) in enumerate(cases):
             d = rand_sync(n, k, j, base=61)
             say("meet mode", mode, n, k)
-            assert srw.solve(n, k, d) == O.bidir(n, k, d)[:2]
+            assert srw.solve(n, k, d) == oracle_rw(n, k, d)
         for n in (5, 17, 33):
             assert srw.solve(n, 2, I.cerny(n)) == ((n - 1) ** 2, I.cerny_word(n))
     finally:
@@ -223,7 +255,7 @@ def test_chunked_meet_with_large_common_sets(n):
             if not O.is_synchronizing(n, 2, d):
                 continue
             say("many common states", n, s)
-            assert srw.solve(n, 2, d) == O.bidir(n, 2, d)[:2]
+            assert srw.solve(n, 2, d) == oracle_rw(n, 2, d)
     finally:
         srw.set_option("meet", 0)
 
@@ -231,7 +263,7 @@ def test_chunked_meet_with_large_common_sets(n):
 def test_meet_mode_levels_and_batch():
     """Forced chunked meet with schedule changes and a batch of mixed sizes."""
     cases = mixed_cases(30, 2024)
-    want = [O.bidir(n, k, d)[:2] for n, k, d in cases]
+    want = [oracle_rw(n, k, d) for n, k, d in cases]
     srw.set_option("meet", 2)
     srw.set_option("schedule", 1)
     srw.set_option("sched_seed", 5)
@@ -281,7 +313,7 @@ def test_batch_matches_oracle_and_single():
             assert st == srw.ENOTSYNC
             continue
         assert st == srw.OK
-        assert (r, w) == O.bidir(n, k, d)[:2]
+        assert (r, w) == oracle_rw(n, k, d)
     # the same automaton alone gives the same answer
     for (n, k, d), (st, r, w) in list(zip(cases, res))[:10]:
         assert srw.solve(n, k, d) == (r, w)
@@ -322,11 +354,96 @@ def test_server_results_same_alone_and_in_mix():
         assert x["latency_ms"] >= x["queue_ms"] >= 0
 
 
+def test_server_serving_mix_against_stored_oracle_values():
+    """Requests of the serving workload's mix (random n in [64, 400], k in
+    2..4, 10% Černý C_8..C_40), submitted in arrival order while earlier
+    ones run: every served result equals the oracle's -- the stored oracle
+    value for the random requests the oracle finished within its time limit
+    (tests/golden/serve5.json), the closed form for the Černý ones.  The
+    requests the oracle did not finish are left out (parity unpinned)."""
+    path = os.path.join(GOLDEN, "serve5.json")
+    if not os.path.exists(path):
+        pytest.skip("no stored oracle values for the serving mix")
+    with open(path) as f:
+        stored = {c["seed"]: c for c in json.load(f)["cases"] if "r" in c}
+    reqs = I.serve_mix(120, 400, 4, srw.check_sync)
+    pick = []
+    for i, m in enumerate(reqs):
+        if m["label"] == "cerny":
+            pick.append((i, m, (m["n"] - 1) ** 2, I.cerny_word(m["n"])))
+        elif m["seed"] in stored:
+            c = stored[m["seed"]]
+            assert (c["n"], c["k"], c["attempt"]) == (m["n"], m["k"], m["attempt"])
+            w = c["word"]
+            pick.append((i, m, c["r"], [int(x) for x in w] if isinstance(w, str) else w))
+    say("serving mix", len(pick), "of", len(reqs), "requests pinned")
+    assert len(pick) >= 40
+    got = {}
+    with srw.Server() as s:
+        for j, (i, m, _, _) in enumerate(pick):
+            s.submit(m["n"], m["k"], m["delta"], i)
+            if j % 4 == 3:                         # arrivals while earlier requests run
+                for x in s.poll(20000):
+                    got[x["tag"]] = x
+        for _ in range(600):                       # at most 120 s
+            if len(got) == len(pick):
+                break
+            for x in s.poll(200000):
+                got[x["tag"]] = x
+        assert len(got) == len(pick) and s.pending() == 0
+    for i, m, r, w in pick:
+        x = got[i]
+        assert x["status"] == srw.OK, (i, m["n"], m["k"], x["status"])
+        assert (x["r"], x["word"]) == (r, w), (i, m["n"], m["k"])
+
+
+def test_server_lane_budget_trim_enomem_then_later_requests():
+    """A server whose lanes have small budgets: blocks freed by finished
+    requests go back to the allocator (the stream is drained first) when a
+    later request needs room, a request too large for its lane ends with
+    ENOMEM, and the requests after it are still served, equal to the
+    oracle."""
+    spec = [(150, 2), (200, 3), (120, 2), (96, 3), (160, 2), (64, 2), (130, 3)]
+    cases = [(n, k, rand_sync(n, k, i, base=313)) for i, (n, k) in enumerate(spec)]
+    want = {}
+    got = {}
+    with srw.Server(hbm_budget=512 << 20, max_slots=2) as s:
+        for t, (n, k, d) in enumerate(cases):
+            say("small-budget server", t, n, k)
+            s.submit(n, k, d, t)
+            for x in s.poll(0):
+                got[x["tag"]] = x
+        for _ in range(600):
+            if len(got) == len(cases):
+                break
+            for x in s.poll(200000):
+                got[x["tag"]] = x
+        assert len(got) == len(cases)
+        # after every request above has finished, one more is served
+        n, k, d = 100, 2, rand_sync(100, 2, 99, base=313)
+        s.submit(n, k, d, 99)
+        for _ in range(600):
+            xs = s.poll(200000)
+            if xs:
+                got[99] = xs[0]
+                break
+    cases.append((n, k, d))
+    tags = list(range(len(spec))) + [99]
+    for t, (n, k, d) in zip(tags, cases):
+        x = got[t]
+        if x["status"] == srw.ENOMEM:
+            assert (n, k) == (200, 3), (n, k)     # only the largest may not fit its lane
+            continue
+        assert x["status"] == srw.OK, (n, k, x["status"])
+        want = oracle_rw(n, k, d)
+        assert (x["r"], x["word"]) == want
+
+
 # ------------------------------------------------------ limits and errors
 
 def test_budget_exhaustion_then_recovery():
     d = rand_sync(200, 3, 1, base=5)
-    want = O.bidir(200, 3, d)[:2]
+    want = oracle_rw(200, 3, d)
     srw.set_option("budget", 96 << 20)
     try:
         say("tiny budget")
@@ -365,7 +482,7 @@ def test_meet_tuning_options_keep_results(rows, groups, order, grid):
         for n, k, i in cs:
             d = rand_sync(n, k, i, base=71)
             say("meet tuning", rows, groups, order, grid, n, k)
-            assert srw.solve(n, k, d) == O.bidir(n, k, d)[:2]
+            assert srw.solve(n, k, d) == oracle_rw(n, k, d)
     finally:
         srw.set_option("meet_rows", 512)
         srw.set_option("meet_groups", 16)
@@ -462,11 +579,49 @@ def test_one_block_steps_keep_results(small):
     try:
         for n, k, d in cs:
             say("one-block steps", small, n, k)
-            assert srw.solve(n, k, d) == O.bidir(n, k, d)[:2]
+            assert srw.solve(n, k, d) == oracle_rw(n, k, d)
         res = srw.solve_batch(cs)
         for (n, k, d), (st, r, w) in zip(cs, res):
-            assert st == srw.OK and (r, w) == O.bidir(n, k, d)[:2]
+            assert st == srw.OK and (r, w) == oracle_rw(n, k, d)
     finally:
+        srw.set_option("small_cand", 2048)
+
+
+@pytest.mark.parametrize("persist,small", [(0, 2048), (1, 2048), (1, 64), (1, 1 << 20)])
+def test_persistent_small_steps_keep_results(persist, small):
+    """The small steps of every automaton run in one launch, a block per
+    automaton stepping it until it meets or until a step is too large, after
+    which the host goes on from the state the block left.  On and off, with
+    the limit moved so that the hand-over comes early (64), at the default
+    (2048) or as late as the block's buffers allow (1 << 20): the same r and
+    word as the oracle, singly and batched, and the same levels."""
+    cs = [(n, 2, I.cerny(n)) for n in (2, 3, 9, 24, 33)]
+    cs += [(n, k, rand_sync(n, k, i, base=97)) for i, (n, k) in
+           enumerate([(20, 2), (64, 2), (65, 3), (128, 2), (190, 3), (257, 2)])]
+    want = [oracle_rw(n, k, d) for n, k, d in cs]
+    srw.set_option("persist", persist)
+    srw.set_option("small_cand", small)
+    try:
+        for (n, k, d), w in zip(cs, want):
+            say("persist", persist, small, n, k)
+            assert srw.solve(n, k, d) == w
+        res = srw.solve_batch(cs)
+        assert [(st, (r, wd)) for st, r, wd in res] == [(srw.OK, w) for w in want]
+        n, k, d = cs[7]                    # random n = 128: levels after the hand-over too
+        srw.set_option("keep_levels", 1)
+        srw.solve(n, k, d)
+        _, _, info = O.bidir(n, k, d, keep_levels=True)
+        for side in (0, 1):
+            got = srw.last_levels(side, (n + 63) // 64)
+            exp = info["levels"][side]
+            assert len(got) == len(exp)
+            for L, ((gr, gp), (er, ep)) in enumerate(zip(got, exp)):
+                assert np.array_equal(gr, er), (side, L)
+                if L > 0:
+                    assert np.array_equal(gp.astype(np.int64), ep), (side, L)
+    finally:
+        srw.set_option("keep_levels", 0)
+        srw.set_option("persist", 1)
         srw.set_option("small_cand", 2048)
 
 
@@ -477,7 +632,7 @@ def test_cardinality_order_keeps_results(ysort):
     modes and batched; n=256 against the stored oracle values."""
     cs = [(n, k, rand_sync(n, k, i, base=83)) for i, (n, k) in
           enumerate([(70, 2), (130, 2), (100, 3), (160, 2)])]
-    want = [O.bidir(n, k, d)[:2] for n, k, d in cs]
+    want = [oracle_rw(n, k, d) for n, k, d in cs]
     g = golden("rand256.json")[:3]
     cs += [(c["n"], c["k"], I.random_automaton(c["n"], c["k"], c["seed"], c["attempt"])) for c in g]
     want += [(c["r"], [int(ch) for ch in c["word"]]) for c in g]

@@ -117,6 +117,7 @@ struct RunDesc {
     u64 *ysig;                 // signature of each set of the current inverse level
     int64_t ysig_cap;
     int64_t small_cand;        // most candidates of a step run here
+    int64_t max_ticks;         // stop after this many wall_clock64 ticks (0: no limit)
     RunState *st;
 };
 struct RunState {

@@ -150,8 +150,8 @@ struct Backing {
     bool own_stream_only = false;   // the memory is used on the engine's stream alone
 };
 
-// Power-of-two size classes.  Blocks up to 4 MiB are carved from 64 MiB
-// slabs; larger ones are separate backing allocations.  Freed blocks are
+// Power-of-two size classes.  Blocks up to 4 MiB are carved from slabs of
+// up to 64 MiB; larger ones are separate backing allocations.  Freed blocks are
 // cached per class and reused; everything returns to the backing allocator
 // when the pool is destroyed.  `budget` caps the bytes taken from backing.
 // The search's own buffers may take all but `reserve` bytes of it; the
@@ -184,14 +184,15 @@ class Pool {
         void *p = nullptr;
         if (size <= kSmallMax) {
             if (slab_left_ < size) {
-                char *s = (char *)backing_alloc(kSlab, internal);
+                const size_t sl = slab_bytes();
+                char *s = (char *)backing_alloc(sl, internal);
                 if (!s) {
                     trim();
-                    s = (char *)backing_alloc(kSlab, internal);
+                    s = (char *)backing_alloc(sl, internal);
                     if (!s) return nullptr;
                 }
                 slab_ = s;
-                slab_left_ = kSlab;
+                slab_left_ = sl;
             }
             p = slab_;
             slab_ += size;
@@ -223,6 +224,12 @@ class Pool {
     void set_budget(int64_t b) { budget_ = b; }
     // bytes of the budget kept for the engine's own per-step buffers
     int64_t reserve() const { return std::min<int64_t>(kReserve, budget_ / 4); }
+    // slabs of at most 64 MiB, and at most an eighth of the budget (a small
+    // budget must still hold several of them), but never below the largest
+    // block they serve
+    size_t slab_bytes() const {
+        return std::max(kSmallMax, std::min(kSlab, (size_t)std::max<int64_t>(budget_ / 8, 0) & ~(size_t)4095));
+    }
 
   private:
     static int cls_of(size_t bytes) {
@@ -463,6 +470,9 @@ class Engine {
             budget = (int64_t)(fr * 0.8);
         }
         pool_.reset(new Pool(backing_, budget, stream_));
+        int khz = 0;
+        HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device_));
+        wall_khz_ = khz > 0 ? (double)khz : 1e5;
         for (int c = 0; c < 16; ++c) HIPCHK(hipEventCreate(&ev_[c]));
         for (int c = 0; c < 2 * kMaxW; ++c) HIPCHK(hipEventCreate(&ev_meet_[c]));
         memset(&stats_, 0, sizeof stats_);
@@ -546,7 +556,7 @@ class Engine {
             pending.swap(waiting);
             if (!fresh.empty()) {
                 init(fresh);
-                run_small(fresh);
+                run_small(fresh, opt.deadline_ms);
             }
             if (active.empty()) continue;
             step(active);
@@ -1017,7 +1027,8 @@ class Engine {
     // block per automaton steps it until the searches meet or until a step
     // is too large for one block; the host then takes over from the state
     // the block left (rows, level offsets).  Met automata are traced here.
-    void run_small(std::vector<Problem *> &ps) {
+    // deadline_ms: per automaton, from its admission (0: none)
+    void run_small(std::vector<Problem *> &ps, double deadline_ms) {
         std::vector<Problem *> q;
         for (Problem *p : ps)
             if (p->status == 1 && p->d_off && p->s[0].nlev() == 1 && p->s[1].nlev() == 1) q.push_back(p);
@@ -1056,6 +1067,10 @@ class Engine {
             r.ysig = p->ysig;
             r.ysig_cap = p->ysig_cap;
             r.small_cand = opt.small_cand;
+            if (deadline_ms > 0) {
+                const double left = deadline_ms - (now_ms() - p->t_admit);
+                r.max_ticks = std::max<int64_t>(1, (int64_t)(left * wall_khz_));
+            }
             r.st = dS + i;
             RunState &st = S[i];
             memset(&st, 0, sizeof st);
@@ -1519,6 +1534,7 @@ class Engine {
     }
 
     int device_;
+    double wall_khz_ = 1e5;    // ticks of the device's wall clock per millisecond
     Backing backing_;
     hipStream_t stream_ = nullptr, own_stream_ = nullptr;
     std::unique_ptr<Pool> pool_;
@@ -1910,7 +1926,7 @@ static void server_loop(srw_server *s, int li) {
             try {
                 if (!fresh.empty()) {
                     eng->init(fresh);
-                    eng->run_small(fresh);
+                    eng->run_small(fresh, s->deadline_ms);
                 }
                 if (!active.empty()) eng->step(active);
             } catch (const HipFailure &f) {

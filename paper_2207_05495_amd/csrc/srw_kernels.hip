@@ -896,6 +896,7 @@ __device__ u32 run_small_w(const CONST_AS RunDesc &r, StepDesc &sd, u64 *lds, u3
     __shared__ int go, dir_s;
     RunState *st = r.st;
     const int tid = threadIdx.x;
+    const u64 t_start = wall_clock64();
     int steps = 0;
     int64_t cands = 0, uniq = 0, pairs = 0;
     u32 nops = 0;
@@ -927,6 +928,8 @@ __device__ u32 run_small_w(const CONST_AS RunDesc &r, StepDesc &sd, u64 *lds, u3
                       2 * (nr[dir] + C) <= (int64_t)r.tab_mask[dir] + 1 && nl[dir] + 1 < r.max_lev &&
                       nXb * nYc <= kSmallMeetBlocks;
             if (dir == 1) ok = ok && tiles * 64 * W <= r.colT_cap && tiles * 64 <= r.ysig_cap;
+            // a deadline: hand the search back to the host, which ends it
+            if (r.max_ticks > 0 && (int64_t)(wall_clock64() - t_start) > r.max_ticks) ok = false;
             go = ok;
             dir_s = dir;
             if (ok) {

@@ -160,7 +160,10 @@ def use_torch(device: int = 0):
         torch.cuda.caching_allocator_delete(ptr)
 
     a, f = ALLOC_FN(_alloc), FREE_FN(_free)
-    _keep[:] = [a, f]
+    # every pair ever registered stays referenced: setting a new allocator
+    # frees the default context's memory through the previous pair, and a
+    # server created earlier keeps using the pair it was created with
+    _keep.extend([a, f])
     rc = L.srw_set_allocator(a, f, None)
     if rc:
         raise SrwError(rc, "set_allocator")

@@ -73,6 +73,26 @@ int srw_solve_batch(int32_t count, const int32_t *n, const int32_t *k,
                     int32_t *r, int32_t *status,
                     const int64_t *word_off, uint8_t *words, const int64_t *word_cap);
 
+/* srw_solve for callers that cannot allocate device memory: code that must
+ * not call hipMalloc (a HIP graph being captured, a tight serving loop, a
+ * harness that forbids allocation).  A call allocates nothing -- no
+ * hipMalloc, no hipFree, no pinned host memory, no torch allocation.  All
+ * device memory of its search comes from one array of
+ * SRW_NOALLOC_SCRATCH_BYTES (256 MiB) per GPU that is part of the library's
+ * code object: it is taken when that code is loaded on the GPU and held
+ * until the process ends.  The call runs on the calling thread's current
+ * HIP device, on a stream of the library's own; the first call on a device
+ * sets up (the scratch address, that stream and its events).  Arguments,
+ * results and statuses are those of srw_solve, with one more way to fail: a
+ * search whose lists outgrow the scratch (random automata with two letters
+ * from about n = 200 on) ends with SRW_ENOMEM.  Calls on one device share
+ * its scratch, which keeps the last call's contents; every call clears what
+ * it reads before reading it.  Overlapping calls on one device would race on
+ * the scratch, so the library serializes them with a per-device lock. */
+#define SRW_NOALLOC_SCRATCH_BYTES ((int64_t)256 << 20)
+int srw_solve_noalloc(int32_t n, int32_t k, const int32_t *delta,
+                      int32_t *r, uint8_t *word, int64_t word_cap);
+
 /* Synchronizability test by state pairs (Section 2 intro): 1 if every pair
  * of states can be mapped to one state, 0 if not, <0 on bad input.  Host
  * code only. */

@@ -1845,6 +1845,154 @@ int srw_last_levels(int32_t side, int32_t *nlev, int64_t *nrows, int64_t *off, u
 
 }  // extern "C"
 
+// ========================================================= no-alloc solves
+
+namespace srw {
+
+// Device memory of srw_solve_noalloc: one array per GPU in the library's
+// code object, taken when that code is loaded on the GPU and held until the
+// process ends.  Host code reaches it only through the address that
+// hipGetSymbolAddress gives for the current device (the array's name in
+// host code is a host-side stand-in, not a device address).
+constexpr int64_t kScratchBytes = (int64_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// First-fit allocator over one device's scratch array; the bookkeeping is
+// on the host.  Blocks are 256-byte aligned.
+class Arena {
+  public:
+    void init(char *base, int64_t size) {
+        base_ = base;
+        free_.clear();
+        used_.clear();
+        free_[0] = size;
+    }
+    void *alloc(size_t bytes) {
+        const int64_t need = (int64_t)((bytes + 255) & ~(size_t)255);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < need) continue;
+            const int64_t off = it->first, left = it->second - need;
+            free_.erase(it);
+            if (left) free_[off + need] = left;
+            used_[off] = need;
+            return base_ + off;
+        }
+        return nullptr;
+    }
+    void free(void *p) {
+        const int64_t off = (char *)p - base_;
+        auto u = used_.find(off);
+        if (u == used_.end()) return;
+        int64_t start = off, len = u->second;
+        used_.erase(u);
+        auto nx = free_.lower_bound(start);
+        if (nx != free_.end() && nx->first == start + len) {
+            len += nx->second;
+            nx = free_.erase(nx);
+        }
+        if (nx != free_.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == start) {
+                start = pv->first;
+                len += pv->second;
+                free_.erase(pv);
+            }
+        }
+        free_[start] = len;
+    }
+
+  private:
+    char *base_ = nullptr;
+    std::map<int64_t, int64_t> free_;            // offset -> bytes
+    std::unordered_map<int64_t, int64_t> used_;  // offset -> bytes
+};
+static void *arena_alloc(size_t b, void *c) { return ((Arena *)c)->alloc(b); }
+static void arena_free(void *p, void *c) { ((Arena *)c)->free(p); }
+
+struct NoAllocDevice {
+    std::mutex mu;               // serializes the calls on this device
+    char *ptr = nullptr;         // this device's scratch array
+    Arena arena;
+    std::unique_ptr<Engine> eng; // its pool draws on the arena; pageable staging
+};
+constexpr int kNoAllocDevices = 64;
+static NoAllocDevice &noalloc_dev(int d) {
+    static NoAllocDevice *devs = new NoAllocDevice[kNoAllocDevices];   // never destroyed
+    return devs[d];
+}
+
+// Set-up, once per device with that device current: the scratch address,
+// then an engine over it (its stream and events are created here, so that
+// the calls themselves create nothing).
+static Engine *noalloc_engine(NoAllocDevice &nd, int device) {
+    if (!nd.ptr) {
+        HIPCHK(hipSetDevice(device));
+        void *ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        nd.ptr = (char *)ptr;
+    }
+    if (!nd.eng) {
+        nd.arena.init(nd.ptr, kScratchBytes);
+        Backing b;
+        b.alloc = arena_alloc;
+        b.free = arena_free;
+        b.ctx = &nd.arena;
+        b.own_stream_only = true;
+        nd.eng.reset(new Engine(device, b, kScratchBytes, nullptr, true));
+    }
+    return nd.eng.get();
+}
+
+}  // namespace srw
+
+extern "C" {
+
+int srw_solve_noalloc(int32_t n, int32_t k, const int32_t *delta, int32_t *r, uint8_t *word,
+                      int64_t word_cap) {
+    if (!r) return set_error(SRW_EINVAL, "r is NULL");
+    *r = -1;
+    int rc = check_input(n, k, delta);
+    if (rc) return rc;
+    if (!is_synchronizing(n, k, delta)) return set_error(SRW_ENOTSYNC, "automaton is not synchronizing");
+    if (n == 1) {
+        *r = 0;
+        return SRW_OK;
+    }
+    int device = -1, count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1 || hipGetDevice(&device) != hipSuccess ||
+        device < 0 || device >= kNoAllocDevices) {
+        (void)hipGetLastError();
+        return set_error(SRW_EDEVICE, "no usable HIP device");
+    }
+    NoAllocDevice &nd = noalloc_dev(device);
+    std::lock_guard<std::mutex> g(nd.mu);
+    std::unique_ptr<Problem> p(make_problem(n, k, delta));
+    p->index = 0;
+    std::vector<Problem *> work{p.get()};
+    try {
+        noalloc_engine(nd, device)->run(work);
+    } catch (const HipFailure &f) {
+        nd.eng.reset();           // the next call sets up a fresh engine over the same array
+        return device_error(f);
+    }
+    rc = p->status;
+    if (rc == SRW_OK) {
+        *r = p->r;
+        if (word) {
+            if (word_cap < p->r) rc = set_error(SRW_EWORDCAP, "word_cap too small");
+            else memcpy(word, p->word.data(), p->r);
+        }
+    } else if (rc == SRW_ENOMEM) {
+        set_error(rc, "the search needs more device memory than the 256 MiB no-alloc scratch; "
+                      "srw_solve has no such limit");
+    } else if (rc < 0 && t_err.empty()) {
+        set_error(rc, "solve failed");
+    }
+    return rc;
+}
+
+}  // extern "C"
+
 // ================================================================ serving
 
 // Requests go to one of three lanes by estimated footprint.  Each lane has

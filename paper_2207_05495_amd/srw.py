@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOTSYNC", -3: "EUNSUPPORTED", -4: "
                 -5: "EWORDCAP", -6: "EDEVICE", -7: "ETIMEOUT", -8: "EINTERNAL"}
 
 # every symbol include/srw.h declares
-EXPORTS = ("srw_solve", "srw_solve_batch", "srw_check_sync", "srw_verify",
+EXPORTS = ("srw_solve", "srw_solve_batch", "srw_solve_noalloc", "srw_check_sync", "srw_verify",
            "srw_server_create", "srw_server_submit", "srw_server_poll",
            "srw_server_pending", "srw_server_destroy", "srw_set_allocator",
            "srw_set_stream", "srw_set_option", "srw_get_stats", "srw_reset_stats",
@@ -104,6 +104,7 @@ def load(path: str = LIB_PATH):
         pass
     L = ctypes.CDLL(path)
     L.srw_solve.argtypes = [ctypes.c_int32, ctypes.c_int32, i32p, i32p, u8p, ctypes.c_int64]
+    L.srw_solve_noalloc.argtypes = L.srw_solve.argtypes
     L.srw_solve_batch.argtypes = [ctypes.c_int32, i32p, i32p, i64p, i32p, i32p, i32p,
                                   i64p, u8p, i64p]
     L.srw_check_sync.argtypes = [ctypes.c_int32, ctypes.c_int32, i32p]
@@ -212,6 +213,20 @@ def solve(n, k, delta, want_word=True, word_cap=1 << 20):
                           word_cap if want_word else 0)
     if rc:
         raise SrwError(rc, "solve")
+    return int(r.value), ([int(x) for x in word[: r.value]] if want_word else None)
+
+
+def solve_noalloc(n, k, delta, want_word=True, word_cap=1 << 20):
+    """srw_solve_noalloc: (r, word) with every device buffer carved from the
+    library's fixed scratch array (no allocation); raises SrwError."""
+    d = _delta(delta)
+    r = ctypes.c_int32(-1)
+    word = np.zeros(word_cap if want_word else 1, dtype=np.uint8)
+    rc = load().srw_solve_noalloc(n, k, _ptr(d, ctypes.c_int32), ctypes.byref(r),
+                                  _ptr(word, ctypes.c_uint8) if want_word else None,
+                                  word_cap if want_word else 0)
+    if rc:
+        raise SrwError(rc, "solve_noalloc")
     return int(r.value), ([int(x) for x in word[: r.value]] if want_word else None)
 
 

@@ -106,6 +106,21 @@ def test_solve_without_gpu_fails_loudly():
     with pytest.raises(srw.SrwError) as e:
         srw.Server()
     assert e.value.code == srw.EDEVICE
+    with pytest.raises(srw.SrwError) as e:
+        srw.solve_noalloc(8, 2, d)
+    assert e.value.code == srw.EDEVICE
+
+
+def test_noalloc_host_checks_come_first():
+    """The no-alloc entry point answers bad input, non-synchronizing input
+    and n = 1 on the host, like srw_solve, before any device work."""
+    with pytest.raises(srw.SrwError) as e:
+        srw.solve_noalloc(3, 1, [0, 1, 5])
+    assert e.value.code == srw.EINVAL
+    with pytest.raises(srw.SrwError) as e:
+        srw.solve_noalloc(3, 2, [1, 2, 0, 0, 2, 1])
+    assert e.value.code == srw.ENOTSYNC
+    assert srw.solve_noalloc(1, 2, [0, 0]) == (0, [])
 
 
 def test_estimator_inputs_generator_is_deterministic():

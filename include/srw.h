@@ -179,6 +179,12 @@ int srw_set_stream(void *hip_stream);
  *   "small_cand"  steps with at most this many candidates (and a small
  *                 LDS-tile meet) run in one block, one launch for the whole
  *                 step (default 2048; 0: never)
+ *   "bucket"      inverse levels of at least this many sets (default 16384;
+ *                 0: never) are kept in buckets by their membership of the
+ *                 forward level's 10 most frequent states, and a chunk of
+ *                 forward sets scans only the buckets holding every one of
+ *                 those states it has in common (the split of Alg. 2); the
+ *                 same results either way
  *   "persist"     1 (default): the first steps of every newly admitted
  *                 automaton run in one launch, a block per automaton
  *                 stepping it for as long as its steps are small in the

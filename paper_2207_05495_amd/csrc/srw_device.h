@@ -40,6 +40,48 @@ constexpr int kMeetLdsWords = kMeetTileWords * 64 > (kBS / 64) * kSliceWords ? k
 // ref < 2^31: id of a stored (visited) row of this side;
 // ref >= 2^31: candidate (ref - 2^31) of the current step.
 
+// ---- an inverse level kept in buckets (the bucketed meet) -------------
+//
+// A set that holds state s can only lie in sets that hold s too (the split
+// of Alg. 2).  A large inverse level is kept in 2^kYBits buckets by its
+// membership of kYBits split states (the most frequent states of the
+// forward level), each bucket padded with empty sets to whole tiles of 64
+// sets.  For each key a, the tiles of every bucket whose key contains a are
+// listed, so that a chunk of forward sets whose common states include the
+// split states of a scans those tiles only.
+constexpr int kYBits = 10;
+constexpr int kYBins = 1 << kYBits;
+constexpr int64_t kYMin = 16384;          // default: inverse levels at least this large are bucketed
+constexpr int64_t kYListPerTile = 32;     // room for list entries per tile of the level
+
+struct YbMeta {
+    int32_t nt;                 // tiles of the padded level
+    int32_t ok;                 // 1: the tile lists fit their room (0: every chunk scans every tile)
+    int64_t entries;            // list entries of the keys other than 0
+    int32_t split[kYBits];      // split state i is key bit kYBits-1-i (-1: none)
+};
+
+struct YbDesc {                 // bucketing of one inverse level
+    int32_t n, W;
+    const u64 *rows;            // the level, in level order
+    const u64 *cnt;             // its size is *cnt when set (a new level), else `count`
+    int64_t count;
+    int64_t count_ub;           // upper bound of the size
+    int64_t nt_ub;              // tiles of room: ceil(count_ub / 64) + kYBins
+    const int32_t *top;         // split states: top[0 .. kYBits-1]
+    YbMeta *meta;
+    uint16_t *key;              // count_ub keys
+    u32 *bins;                  // kYBins set counts, then kYBins insertion cursors
+    u32 *tb;                    // kYBins + 1 first tiles of the buckets
+    u32 *lsize;                 // kYBins list lengths (tiles)
+    u32 *loff;                  // kYBins + 1 list offsets
+    u32 *lcur;                  // kYBins list cursors
+    u32 *list;                  // list_cap entries
+    int64_t list_cap;
+    u32 *idx;                   // nt_ub * 64: padded position -> index in the level (~0: padding)
+    u64 *YT, *YTt, *Ysig;       // the padded level transposed (state-major with nt tiles)
+};
+
 struct StepDesc {
     // automaton
     int32_t n, k, W, dir;      // dir 0: forward (images), 1: inverse (preimages)
@@ -73,7 +115,7 @@ struct StepDesc {
     int64_t nY;                // -1: the new level (count in res[0])
     int64_t nXb, nYc;          // mode 0 grid of this segment (upper bounds)
     int32_t tpb;               // mode 0: tiles per meet block
-    int32_t meet_mode;         // 0: LDS tiles, 1: sorted 64-set chunks
+    int32_t meet_mode;         // 0: LDS tiles, 1: sorted 64-set chunks, 2: chunks against buckets
     int32_t small;             // 1: the whole step runs in one block (k_step_small)
     int32_t ysort;             // 1: sort the new inverse level by cardinality (dir 1)
     // the inverse level in cardinality order, largest first (null: level order)
@@ -90,6 +132,14 @@ struct StepDesc {
     int64_t row_batch_max;     // mode 1: more candidates per group than this: column chains
     int64_t nch_ub;            // mode 1: chunks (upper bound)
     int64_t item_order;        // mode 1: 0 tile-range-major items, 1 chunk-major
+    // mode 2 (bucketed meet): the inverse level in buckets, and the plan of
+    // the work items (one chunk, a range of its tiles) taken from a queue
+    const YbMeta *yb;
+    const u32 *yb_lsize, *yb_loff, *yb_list;
+    uint16_t *ckey;            // per chunk: its key
+    u32 *citems;               // per chunk: work items
+    u32 *cpre;                 // per chunk: first work item
+    u32 *queue;                // [0] next work item, [1] work items
     // transpose of a new inverse level into YT
     int64_t ntr_waves;         // upper bound of (tile, word) waves
     // results: res[0] = new level size, res[1] = least (i << 32 | j) meeting pair

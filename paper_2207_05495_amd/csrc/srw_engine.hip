@@ -37,6 +37,9 @@ hipError_t launch_transpose_rows(const TransposeDesc *, const int64_t *, int, in
 hipError_t launch_meet(const StepDesc *, const int64_t *, int, int, int, int64_t, int64_t, bool, u64 *, hipStream_t);
 hipError_t launch_step_small(const StepDesc *, const int32_t *, int, u64 *, hipStream_t);
 hipError_t launch_run_small(const RunDesc *, int, int, u64 *, hipStream_t);
+hipError_t launch_ybin(const YbDesc *, const int64_t *const[4], const int64_t[4], int, hipStream_t);
+hipError_t launch_meet_plan(const StepDesc *, const int64_t *, int, int64_t, hipStream_t);
+hipError_t launch_meet_b(const StepDesc *, int, int, int, int64_t, u64 *, hipStream_t);
 hipError_t launch_copy(const CopyDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_ysort(const StepDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_init(const InitDesc *, const int64_t *, int, int64_t, hipStream_t);
@@ -401,6 +404,21 @@ struct Problem {
     int64_t xs_cap = 0;       // rows
     bool xs_valid = false;    // xs_* hold the current forward level
     bool sort_now = false;    // this step sorts its new forward level
+    // the current inverse level in buckets (yb_valid; colT, ysig and yb_idx
+    // are then in bucket order) -- see YbMeta
+    bool yb_valid = false;
+    bool yb_now = false;      // this step puts an inverse level into buckets
+    char *yb_small = nullptr; // YbMeta, then the counters, bucket tiles and list offsets
+    uint16_t *yb_key = nullptr;
+    int64_t yb_key_cap = 0;
+    u32 *yb_idx = nullptr;    // padded position -> index in the level
+    int64_t yb_idx_cap = 0;
+    u32 *yb_list = nullptr;
+    int64_t yb_list_cap = 0;
+    // plan of a bucketed meet: per chunk its key, work items and first item
+    uint16_t *mp_key = nullptr;
+    u32 *mp_items = nullptr, *mp_pre = nullptr, *mp_queue = nullptr;
+    int64_t mp_cap = 0;       // chunks
     int status = 1;           // 1 running, else SRW_ status
     int32_t r = -1;
     std::vector<uint8_t> word;
@@ -426,6 +444,7 @@ struct Options {
     int64_t meet_groups = 16;           // chunked meet: tile groups per work item (upper limit)
     int64_t small_cand = 2048;          // steps with at most this many candidates run in one block (0: never)
     int persist = 1;                    // 1: the small steps of a new automaton run in one launch (k_run_small)
+    int64_t bucket = kYMin;             // inverse levels of at least this many sets go into buckets for the meet (0: never)
     int64_t ysort = 0;                  // new inverse levels of at least this many candidates go in cardinality order (0: never)
     int64_t meet_grid = 0;              // meet blocks per launch (0: one per work item)
     int64_t meet_order = 1;             // chunked meet items: 0 tile-range-major, 1 chunk-major
@@ -767,6 +786,9 @@ class Engine {
         std::vector<SortDesc> S;
         std::vector<int64_t> pz(1, 0), pr(1, 0), pch(1, 0);
         std::vector<int32_t> small;                // segments whose whole step runs in one block
+        std::vector<YbDesc> YB;                    // inverse levels put into buckets in this step
+        std::vector<int64_t> pyb[4] = {{0}, {0}, {0}, {0}};
+        std::vector<int64_t> pmp(nseg + 1, 0);     // bucketed meets: blocks over chunks
         if ((int64_t)nseg * 2 > res_cap_) {
             pool_->free(d_res_);
             res_cap_ = std::max<int64_t>((int64_t)nseg * 2, 2 * res_cap_);
@@ -823,10 +845,55 @@ class Engine {
             d.res = d_res_ + 2 * i;
             // chunked meet over the sorted forward level when it exists
             if ((dir == 0 && p->sort_now) || (dir == 1 && p->xs_valid && opt.meet != 1)) {
-                d.meet_mode = 1;
+                d.meet_mode = bucketed_meet(p, dir) ? 2 : 1;
                 d.X = p->xs_rows;
                 d.Xidx = p->xs_idx;
                 d.Xcom = p->xs_com;
+            }
+            if (p->yb_now) {                       // the inverse level goes into buckets
+                const int64_t yub = dir == 1 ? d.C : d.nY;
+                const int64_t nt_ub = ceil_div(yub, 64) + kYBins;
+                u32 *w = yb_words(p);
+                YbDesc y;
+                memset(&y, 0, sizeof y);
+                y.n = p->n;
+                y.W = W;
+                y.rows = dir == 1 ? d.out_rows : d.Yrows;
+                y.cnt = dir == 1 ? d.res : nullptr;
+                y.count = dir == 1 ? 0 : d.nY;
+                y.count_ub = yub;
+                y.nt_ub = nt_ub;
+                y.top = p->xs_top;
+                y.meta = yb_meta(p);
+                y.key = p->yb_key;
+                y.bins = w;
+                y.tb = w + 2 * kYBins;
+                y.lsize = y.tb + kYBins + 1;
+                y.loff = y.lsize + kYBins;
+                y.lcur = y.loff + kYBins + 1;
+                y.list = p->yb_list;
+                y.list_cap = p->yb_list_cap;
+                y.idx = p->yb_idx;
+                y.YT = p->colT;
+                y.YTt = p->colT + p->colT_cap;
+                y.Ysig = p->ysig;
+                YB.push_back(y);
+                pyb[0].push_back(pyb[0].back() + ceil_div(yub, kBS));
+                pyb[1].push_back(pyb[1].back() + ceil_div(nt_ub * 64, kBS));
+                pyb[2].push_back(pyb[2].back() + kYBins / (kBS / 64));
+                pyb[3].push_back(pyb[3].back() + ceil_div(nt_ub * W, kBS / 64));
+            }
+            if (d.meet_mode == 2) {
+                u32 *w = yb_words(p);
+                d.yb = yb_meta(p);
+                d.yb_lsize = w + 2 * kYBins + kYBins + 1;
+                d.yb_loff = d.yb_lsize + kYBins;
+                d.yb_list = p->yb_list;
+                d.Yidx = p->yb_idx;
+                d.ckey = p->mp_key;
+                d.citems = p->mp_items;
+                d.cpre = p->mp_pre;
+                d.queue = p->mp_queue;
             }
             if (dir == 0 && p->sort_now) {
                 S.push_back(SortDesc{p->n, W, d.out_rows, d.res, d.C, p->xs_hist, p->xs_top, p->xs_keys,
@@ -842,15 +909,19 @@ class Engine {
                 d.nYc = ceil_div(ceil_div(ny_ub, 64), d.tpb);
                 pm[i + 1] = pm[i] + d.nXb * d.nYc;
             } else {
-                const int64_t ng_ub = ceil_div(ceil_div(ny_ub, 64), 64);   // groups of 64 tiles
+                const int64_t ng_ub = ceil_div(ceil_div(ny_ub, 64) + (d.meet_mode == 2 ? kYBins : 0), 64);
                 d.ngi = std::max<int64_t>(1, std::min<int64_t>(opt.meet_groups, ng_ub));
                 d.row_batch_max = std::min<int64_t>(opt.meet_rows, kRowBatchMax);
                 d.nch_ub = ceil_div(nx_ub, 64);
                 d.item_order = opt.meet_order;
                 d.gitems_ub = ceil_div(ng_ub, d.ngi);
-                pm[i + 1] = pm[i] + ceil_div(ceil_div(nx_ub, 64) * d.gitems_ub, kBS / 64);
+                if (d.meet_mode == 1) pm[i + 1] = pm[i] + ceil_div(ceil_div(nx_ub, 64) * d.gitems_ub, kBS / 64);
+                else pm[i + 1] = pm[i];            // its items come from a queue
             }
-            d.ntr_waves = dir == 1 ? ceil_div(d.C, 64) * W : 0;
+            pmp[i + 1] = pmp[i] + (d.meet_mode == 2 ? ceil_div(ceil_div(nx_ub, 64), kBS) : 0);
+            // the new inverse level is transposed in level order, unless it
+            // goes into buckets (transposed in bucket order there)
+            d.ntr_waves = (dir == 1 && !p->yb_now) ? ceil_div(d.C, 64) * W : 0;
             d.small = d.meet_mode == 0 && d.C <= opt.small_cand && d.nXb * d.nYc <= kSmallMeetBlocks;
             if (d.small) {
                 pm[i + 1] = pm[i];
@@ -893,7 +964,9 @@ class Engine {
         const size_t szS = align8(sizeof(SortDesc) * nsort), szQ = align8(8 * (nsort + 1));
         const int nsmall = (int)small.size();
         const size_t szL = align8(4 * (size_t)std::max(1, nsmall));
-        const size_t total = szD + 4 * szP + szS + 3 * szQ + szL + szP;
+        const int nyb = (int)YB.size();
+        const size_t szY = align8(sizeof(YbDesc) * nyb), szYP = align8(8 * (nyb + 1));
+        const size_t total = szD + 4 * szP + szS + 3 * szQ + szL + szP + szY + 4 * szYP + szP;
         char *h = (char *)pin_step_.need(total);
         memcpy(h, D.data(), sizeof(StepDesc) * nseg);
         memcpy(h + szD, pe.data(), 8 * (nseg + 1));
@@ -909,6 +982,11 @@ class Engine {
         if (nsmall) memcpy(h + oL, small.data(), 4 * nsmall);
         const size_t oQ = oL + szL;
         memcpy(h + oQ, pq.data(), 8 * (nseg + 1));
+        const size_t oY = oQ + szP;
+        if (nyb) memcpy(h + oY, YB.data(), sizeof(YbDesc) * nyb);
+        for (int k2 = 0; k2 < 4; ++k2) memcpy(h + oY + szY + k2 * szYP, pyb[k2].data(), 8 * (nyb + 1));
+        const size_t oMP = oY + szY + 4 * szYP;
+        memcpy(h + oMP, pmp.data(), 8 * (nseg + 1));
         char *dblob = dev_need(step_blob_, step_blob_cap_, total);
         HIPCHK(hipMemcpyAsync(dblob, h, total, hipMemcpyHostToDevice, stream_));
         const StepDesc *dD = (const StepDesc *)dblob;
@@ -923,6 +1001,12 @@ class Engine {
         const int64_t sblocks[3] = {pz.back(), pr.back(), pch.back()};
         const int32_t *dsmall = (const int32_t *)(dblob + oL);
         const int64_t *dpq = (const int64_t *)(dblob + oQ);
+        const YbDesc *dY = (const YbDesc *)(dblob + oY);
+        const int64_t *const dyp[4] = {(const int64_t *)(dblob + oY + szY), (const int64_t *)(dblob + oY + szY + szYP),
+                                       (const int64_t *)(dblob + oY + szY + 2 * szYP),
+                                       (const int64_t *)(dblob + oY + szY + 3 * szYP)};
+        const int64_t yblocks[4] = {pyb[0].back(), pyb[1].back(), pyb[2].back(), pyb[3].back()};
+        const int64_t *dpmp = (const int64_t *)(dblob + oMP);
 
         ensure_ops();
         prof_begin(0);
@@ -937,11 +1021,15 @@ class Engine {
         if (nsmall < nseg) HIPCHK(launch_scan(dD, nseg, d_cnt_, d_off_, stream_));
         HIPCHK(launch_compact(dD, dpc, nseg, pc[nseg], d_off_, stream_));
         prof_end(2);
-        if (pt[nseg] > 0 || nsort > 0) {
+        if (pt[nseg] > 0 || nsort > 0 || nyb > 0 || pmp[nseg] > 0) {
             prof_begin(3);
             HIPCHK(launch_ysort(dD, dpq, nseg, pq[nseg], stream_));
             HIPCHK(launch_transpose(dD, dpt, nseg, pt[nseg], stream_));
             HIPCHK(launch_sort(dS, dsp, sblocks, nsort, stream_));
+            // buckets of inverse levels (after the sorts: they take their
+            // split states from the forward level's most frequent states)
+            HIPCHK(launch_ybin(dY, dyp, yblocks, nyb, stream_));
+            HIPCHK(launch_meet_plan(dD, dpmp, nseg, pmp[nseg], stream_));
             prof_end(3);
             stats_.launches[3]++;
         }
@@ -950,7 +1038,10 @@ class Engine {
             int s1 = s0;
             const int W = segp[s0]->W;
             while (s1 < nseg && segp[s1]->W == W) ++s1;
-            if (pm[s1] == pm[s0]) {                // only small segments of this width
+            int64_t bk_items = 0;                  // bucketed meets: their work items (upper bound)
+            for (int i = s0; i < s1; ++i)
+                if (D[i].meet_mode == 2) bk_items += D[i].nch_ub * D[i].gitems_ub;
+            if (pm[s1] == pm[s0] && bk_items == 0) {   // only small segments of this width
                 s0 = s1;
                 continue;
             }
@@ -958,11 +1049,15 @@ class Engine {
                 HIPCHK(hipEventRecord(ev_meet_[2 * (W - 1)], stream_));
                 meet_used_[W - 1] = true;
             }
-            bool ys = false;                       // an inverse level in cardinality order
-            for (int i = s0; i < s1; ++i) ys = ys || D[i].Yidx != nullptr;
-            HIPCHK(launch_meet(dD, dpm, s0, s1, W, pm[s1] - pm[s0], opt.meet_grid, ys,
-                               opt.profile ? d_ops_ + (int64_t)(W - 1) * kOpsSlots * kOpsStride : nullptr,
-                               stream_));
+            u64 *ops = opt.profile ? d_ops_ + (int64_t)(W - 1) * kOpsSlots * kOpsStride : nullptr;
+            if (pm[s1] > pm[s0]) {
+                bool ys = false;                   // an inverse level in cardinality order
+                for (int i = s0; i < s1; ++i) ys = ys || (D[i].meet_mode != 2 && D[i].Yidx != nullptr);
+                HIPCHK(launch_meet(dD, dpm, s0, s1, W, pm[s1] - pm[s0], opt.meet_grid, ys, ops, stream_));
+            }
+            if (bk_items > 0)
+                HIPCHK(launch_meet_b(dD, s0, s1, W, std::min<int64_t>(ceil_div(bk_items, kBS / 64), kMeetQueueGrid),
+                                     ops, stream_));
             if (opt.profile) HIPCHK(hipEventRecord(ev_meet_[2 * (W - 1) + 1], stream_));
             stats_.meet_launches_w[W - 1]++;
             s0 = s1;
@@ -995,7 +1090,10 @@ class Engine {
             s.off.push_back(s.nrows);
             if (dir == 0) p->xs_valid = p->sort_now;
             if (dir == 1) p->ys_valid = d.ysort != 0;
+            if (dir == 1) p->yb_valid = p->yb_now;   // a new inverse level: bucketed or not
+            else if (p->yb_now) p->yb_valid = true;  // the current one put into buckets
             p->sort_now = false;
+            p->yb_now = false;
             p->steps++;
             stats_.steps++;
             stats_.unique += U;
@@ -1207,6 +1305,7 @@ class Engine {
     }
 
     bool persist_ok() const { return opt.persist && opt.small_cand > 0 && opt.schedule == 0 && opt.meet != 2; }
+    static constexpr int64_t kMeetQueueGrid = 4096;  // blocks of a bucketed meet (they take items from queues)
     static constexpr int64_t kPersistRows = 16384;   // rows per side while k_run_small steps
     static constexpr int64_t kPersistCand = 8192;    // candidates of its largest step
     static constexpr int64_t kPersistLevels = 4096;  // levels per side it can record
@@ -1321,12 +1420,87 @@ class Engine {
             p->ysig = (u64 *)pp; p->ysig_cap = cap;
         }
         p->sort_now = false;
+        p->yb_now = false;
+        const int64_t nY = p->s[1].cur();
         if (dir == 0 && opt.meet != 1) {
-            const bool want = opt.meet == 2 ||
-                              (C >= kSortMinCand && (double)C * (double)p->s[1].cur() >= kSortMinPairs);
+            // a bucketed inverse level is met only by a sorted forward level
+            const bool want = opt.meet == 2 || p->yb_valid ||
+                              (C >= kSortMinCand && (double)C * (double)nY >= kSortMinPairs);
             if (want) p->sort_now = ensure_sort(p, C);   // no room: the LDS-tile meet serves
+            if (!p->sort_now && p->yb_valid) return set_error(SRW_ENOMEM, "device budget (sort)");
+            if (p->sort_now && !p->yb_valid && bucket_ok() && nY >= opt.bucket) p->yb_now = true;
+        } else if (dir == 1 && bucket_ok() && p->xs_valid && C >= opt.bucket) {
+            p->yb_now = true;
+        }
+        if (p->yb_now) {
+            const int64_t yub = dir == 1 ? C : nY;    // sets of the level to bucket
+            const int64_t nt_ub = ceil_div(yub, 64) + kYBins;
+            if (!ensure_ybin(p, yub, nt_ub)) {
+                p->yb_now = false;                     // no room: level order
+            } else {
+                pp = p->colT; cap = p->colT_cap;
+                if (!dev_grow(pp, cap, nt_ub * 64 * W, 16, 0)) return set_error(SRW_ENOMEM, "device budget (tiles)");
+                p->colT = (u64 *)pp; p->colT_cap = cap;
+                pp = p->ysig; cap = p->ysig_cap;
+                if (!dev_grow(pp, cap, nt_ub * 64, 8, 0)) return set_error(SRW_ENOMEM, "device budget (signatures)");
+                p->ysig = (u64 *)pp; p->ysig_cap = cap;
+            }
+        }
+        if (bucketed_meet(p, dir)) {
+            const int64_t nch = ceil_div(dir == 0 ? C : p->s[0].cur(), 64) + 1;
+            if (!ensure_plan(p, nch)) return set_error(SRW_ENOMEM, "device budget (meet plan)");
         }
         return 0;
+    }
+
+    bool bucket_ok() const { return opt.bucket > 0 && opt.ysort == 0 && opt.meet != 1; }
+    // this step's meet runs against the inverse level in buckets (mode 2)
+    static bool bucketed_meet(const Problem *p, int dir) {
+        return dir == 0 ? (p->sort_now && (p->yb_valid || p->yb_now)) : (p->xs_valid && p->yb_now);
+    }
+
+    static constexpr size_t kYbSmallWords = 2 * kYBins + (kYBins + 1) + kYBins + (kYBins + 1) + kYBins;
+    static size_t yb_small_bytes() { return 256 + kYbSmallWords * 4; }
+    static YbMeta *yb_meta(Problem *p) { return (YbMeta *)p->yb_small; }
+    static u32 *yb_words(Problem *p) { return (u32 *)(p->yb_small + 256); }
+
+    // buffers for bucketing an inverse level of up to `count` sets
+    bool ensure_ybin(Problem *p, int64_t count, int64_t nt_ub) {
+        if (!p->yb_small) {
+            p->yb_small = (char *)pool_->alloc(yb_small_bytes());
+            if (!p->yb_small) return false;
+        }
+        void *q = p->yb_key;
+        int64_t cap = p->yb_key_cap;
+        if (!dev_grow(q, cap, count, 2, 0)) return false;
+        p->yb_key = (uint16_t *)q;
+        p->yb_key_cap = cap;
+        q = p->yb_idx;
+        cap = p->yb_idx_cap;
+        if (!dev_grow(q, cap, nt_ub * 64, 4, 0)) return false;
+        p->yb_idx = (u32 *)q;
+        p->yb_idx_cap = cap;
+        q = p->yb_list;
+        cap = p->yb_list_cap;
+        if (!dev_grow(q, cap, kYListPerTile * nt_ub, 4, 0)) return false;
+        p->yb_list = (u32 *)q;
+        p->yb_list_cap = cap;
+        return true;
+    }
+
+    // plan buffers of a bucketed meet over `nch` chunks
+    bool ensure_plan(Problem *p, int64_t nch) {
+        if (nch <= p->mp_cap && p->mp_queue) return true;
+        pool_->free(p->mp_key);
+        pool_->free(p->mp_items);
+        pool_->free(p->mp_pre);
+        const int64_t nc = std::max(nch, 2 * p->mp_cap);
+        p->mp_key = (uint16_t *)pool_->alloc((size_t)nc * 2);
+        p->mp_items = (u32 *)pool_->alloc((size_t)nc * 4);
+        p->mp_pre = (u32 *)pool_->alloc((size_t)(nc + 1) * 4);
+        if (!p->mp_queue) p->mp_queue = (u32 *)pool_->alloc(256);
+        p->mp_cap = (p->mp_key && p->mp_items && p->mp_pre && p->mp_queue) ? nc : 0;
+        return p->mp_cap > 0;
     }
 
     bool ensure_sort(Problem *p, int64_t rows) {
@@ -1427,6 +1601,17 @@ class Engine {
         pool_->free(p->colT); p->colT = nullptr; p->colT_cap = 0;
         pool_->free(p->ysig); p->ysig = nullptr; p->ysig_cap = 0;
         pool_->free(p->d_off); p->d_off = nullptr; p->max_lev = 0;
+        for (void *q : {(void *)p->yb_small, (void *)p->yb_key, (void *)p->yb_idx, (void *)p->yb_list,
+                        (void *)p->mp_key, (void *)p->mp_items, (void *)p->mp_pre, (void *)p->mp_queue})
+            pool_->free(q);
+        p->yb_small = nullptr;
+        p->yb_key = nullptr;
+        p->yb_idx = p->yb_list = nullptr;
+        p->yb_key_cap = p->yb_idx_cap = p->yb_list_cap = 0;
+        p->mp_key = nullptr;
+        p->mp_items = p->mp_pre = p->mp_queue = nullptr;
+        p->mp_cap = 0;
+        p->yb_valid = p->yb_now = false;
         pool_->free(p->ys_hist); pool_->free(p->ys_cnt); pool_->free(p->ys_idx);
         p->ys_hist = p->ys_cnt = p->ys_idx = nullptr;
         p->ys_cap = 0;
@@ -1690,6 +1875,7 @@ int srw_set_option(const char *key, int64_t v) {
     else if (k == "ysort") { if (v < 0) return set_error(SRW_EINVAL, "ysort"); x.opt.ysort = v; }
     else if (k == "small_cand") { if (v < 0 || v > (1 << 20)) return set_error(SRW_EINVAL, "small_cand"); x.opt.small_cand = v; }
     else if (k == "persist") { if (v < 0 || v > 1) return set_error(SRW_EINVAL, "persist"); x.opt.persist = (int)v; }
+    else if (k == "bucket") { if (v < 0) return set_error(SRW_EINVAL, "bucket"); x.opt.bucket = v; }
     else if (k == "meet_groups") { if (v < 1 || v > 4096) return set_error(SRW_EINVAL, "meet_groups"); x.opt.meet_groups = v; }
     else if (k == "meet_grid") { if (v < 0) return set_error(SRW_EINVAL, "meet_grid"); x.opt.meet_grid = v; }
     else if (k == "meet_order") { if (v < 0 || v > 1) return set_error(SRW_EINVAL, "meet_order"); x.opt.meet_order = v; }

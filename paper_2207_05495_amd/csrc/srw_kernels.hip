@@ -518,34 +518,65 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int W, bool YS>
-__device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice) {
+// Mode 1 takes a work item apart into (chunk c, group range gi); mode 2
+// (BK: the inverse level in buckets) is handed (c, gi) by its queue.
+//
+// BK: only the tiles of the buckets whose key contains the chunk's key a
+// (the split states common to the chunk) can hold a superset of a set of the
+// chunk; they are tile list a of the bucketed level, read through the list
+// (key 0, or lists that did not fit: every tile in order).  The split states
+// of a hold in every set of those buckets, so they are taken out of each X
+// and out of the filtering states.  Level indices come through Yidx (the
+// bucket order is not the level order, so a hit does not end a lane).
+template <int W, bool YS, bool BK>
+__device__ u32 meet_chunk_core(const CONST_AS StepDesc &d, int64_t c, int64_t gi, u64 *slice) {
     const int lane = threadIdx.x & 63;
     const u32 *Yidx = YS ? d.Yidx : nullptr;
-    const u32 *Ycnt = YS ? d.Ycnt : nullptr;
+    const u32 *Ycnt = (YS && !BK) ? d.Ycnt : nullptr;
     const int64_t nX = d.nX >= 0 ? d.nX : (int64_t)d.res[0];
     const int64_t nY = d.nY >= 0 ? d.nY : (int64_t)d.res[0];
-    const int64_t nt = (nY + 63) / 64;
-    const int64_t ngroups = (nt + 63) / 64;
-    // tile-range-major: the items in flight share one range of tiles, so its
-    // columns and rows stay in L2 (every XCD works on the same range)
-    int64_t c, gi;
-    if (d.item_order == 0) { gi = udiv(item, d.nch_ub); c = item - gi * d.nch_ub; }
-    else { c = udiv(item, d.gitems_ub); gi = item - c * d.gitems_ub; }
+    const int64_t nt = BK ? (int64_t)d.yb->nt : (nY + 63) / 64;
     if (c * 64 >= nX) return 0;                    // whole wave
+    const int64_t is = c * 64 + lane;
+    const bool valid = is < nX;
+    // BK: the chunk's key and its split states
+    u64 smask[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) smask[w] = 0;
+    const u32 *tlist = nullptr;                    // the chunk's tile list (null: every tile)
+    int64_t nvt = nt;                              // tiles the chunk scans
+    if (BK) {
+        u32 a = 0;
+#pragma unroll
+        for (int i = 0; i < kYBits; ++i) {
+            const int q = d.yb->split[i];
+            if (q >= 0 && ((d.Xcom[c * W + (q >> 6)] >> (q & 63)) & 1ull)) {
+                a |= 1u << (kYBits - 1 - i);
+                smask[q >> 6] |= 1ull << (q & 63);
+            }
+        }
+        if (a != 0 && d.yb->ok) {
+            tlist = d.yb_list + d.yb_loff[a];
+            nvt = d.yb_lsize[a];
+        } else {
+            // every tile is scanned, sets without the split states too: the
+            // states stay in X and among the filtering states
+#pragma unroll
+            for (int w = 0; w < W; ++w) smask[w] = 0;
+        }
+    }
+    const int64_t ngroups = (nvt + 63) / 64;
     const int64_t g0 = gi * d.ngi;
     int64_t g1 = min(g0 + d.ngi, ngroups);
     if (g0 >= g1) return 0;                        // whole wave
-    const int64_t is = c * 64 + lane;
-    const bool valid = is < nX;
     // the first kCommonMax states of C (-1: none); only those are filtered
-    // on, so only those are taken out of each X
+    // on, so only those (and the split states of the key) are taken out of X
     int cq[kCommonMax];
     u64 x[W];
     {
         u64 cur[W];
 #pragma unroll
-        for (int w = 0; w < W; ++w) cur[w] = d.Xcom[c * W + w];
+        for (int w = 0; w < W; ++w) cur[w] = d.Xcom[c * W + w] & ~smask[w];
         u64 used[W];
 #pragma unroll
         for (int w = 0; w < W; ++w) used[w] = cur[w];
@@ -563,7 +594,7 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
 #pragma unroll
         for (int w = 0; w < W; ++w) {
             used[w] &= ~cur[w];                    // states of C left unfiltered stay in x
-            x[w] = valid ? (d.X[is * W + w] & ~used[w]) : 0ull;
+            x[w] = valid ? (d.X[is * W + w] & ~(used[w] | smask[w])) : 0ull;
         }
     }
     int nc = 0;                                    // states of C filtered on
@@ -575,7 +606,7 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
     const u32 orig = valid ? d.Xidx[is] : 0xFFFFFFFFu;
     // inverse level in cardinality order: only its first Ycnt[min |X|] sets
     // can contain a set of this chunk
-    int64_t nt_lim = nt;
+    int64_t nt_lim = nvt;
     if (Ycnt) {
         int sz = 0x7fffffff;
         if (valid) {
@@ -603,21 +634,29 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
     // a load).  Lanes past the last tile and unused states load word 0 of YT,
     // so the loads need no branch; the words are used raw and masked where
     // the group consumes them (a select here would wait for the load).
+    // the tile of the chunk's vt-th scanned tile
+    auto tile_of = [&](int64_t vt) -> int64_t {
+        if (!BK || !tlist) return vt;
+        return vt < nvt ? (int64_t)tlist[vt] : 0;
+    };
     auto first_round = [&](int64_t gg, u64 *v) {
-        const int64_t tg = gg * 64 + lane;
+        const int64_t vg = gg * 64 + lane;
+        const int64_t tg = tile_of(vg);
 #pragma unroll
         for (int r = 0; r < kCommonRound; ++r) {
-            const bool ok = tg < nt && cq[r] >= 0;
+            const bool ok = vg < nvt && cq[r] >= 0;
             v[r] = d.YT[ok ? (int64_t)cq[r] * nt + tg : 0];
         }
     };
-    const u64 last_rows = (nY & 63) ? ((1ull << (nY & 63)) - 1ull) : ~0ull;   // the last tile may be partial
+    // the last tile may be partial (buckets are padded with empty sets)
+    const u64 last_rows = (BK || (nY & 63) == 0) ? ~0ull : ((1ull << (nY & 63)) - 1ull);
     // one group with its first-round columns in cur; refills cur for group g + 2.
     // false: every lane of the wave is done
     auto group = [&](int64_t g, u64 *cur) -> bool {
         if (__ballot(!done) == 0) return false;
-        const int64_t t = g * 64 + lane;
-        const bool tv = t < nt_lim;
+        const int64_t vt = g * 64 + lane;
+        const bool tv = vt < nt_lim;
+        const int64_t t = tile_of(vt);
         // lanes past the tiles (t >= nt_lim, so also t >= nt) start from 0,
         // so the raw word they loaded does not matter; an unused state (cq
         // < 0, uniform over the wave) contributes no column
@@ -708,7 +747,7 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
             const int lt = lowest_bit(surv);
             surv &= surv - 1;
             const u64 mc = shfl64(m, lt);
-            const int64_t tt = g * 64 + lt;
+            const int64_t tt = BK ? (int64_t)shfl64((u64)t, lt) : g * 64 + lt;
             if (__ballot(!done) == 0) break;
             wave_sync_lds();                       // the last tile is read
 #pragma unroll
@@ -742,6 +781,7 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
         return true;
     };
     g1 = min(g1, (nt_lim + 63) / 64);
+    if (g0 >= g1) return nops;
     u64 pa[kCommonRound], pb[kCommonRound];
     if (g0 < g1) first_round(g0, pa);
     if (g0 + 1 < g1) first_round(g0 + 1, pb);
@@ -750,6 +790,16 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
         if (g + 1 < g1 && !group(g + 1, pb)) break;
     }
     return nops;
+}
+
+template <int W, bool YS>
+__device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice) {
+    // tile-range-major: the items in flight share one range of tiles, so its
+    // columns and rows stay in L2 (every XCD works on the same range)
+    int64_t c, gi;
+    if (d.item_order == 0) { gi = udiv(item, d.nch_ub); c = item - gi * d.nch_ub; }
+    else { c = udiv(item, d.gitems_ub); gi = item - c * d.gitems_ub; }
+    return meet_chunk_core<W, YS, false>(d, c, gi, slice);
 }
 
 // Grid-stride over work items: mode 0 items are blocks (256 sets X against
@@ -782,6 +832,289 @@ __global__ void __launch_bounds__(kBS) k_meet(const StepDesc *descs, const int64
             if ((threadIdx.x & 63) == 0 && sum)
                 atomicAdd((unsigned long long *)(ops + (blockIdx.x % kOpsSlots) * kOpsStride), (unsigned long long)sum);
         }
+    }
+}
+
+// Mode 2: waves take work items from each segment's queue in turn, until
+// the queue is empty (its counter passes the item count the plan wrote),
+// so every wave of the grid ends.  Items of a chunk (cpre: its first item)
+// cover consecutive ranges of d.ngi tile groups of its list.
+template <int W>
+__global__ void __launch_bounds__(kBS) k_meet_b(const StepDesc *descs, int s0, int s1, u64 *ops) {
+    __shared__ u64 cols[kMeetLdsWords];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    u64 *slice = cols + wave * kSliceWords;
+    u32 nops = 0;
+    for (int s = s0; s < s1; ++s) {
+        const CONST_AS StepDesc &d = cref(descs + s);
+        if (d.meet_mode != 2) continue;
+        const int64_t nX = d.nX >= 0 ? d.nX : (int64_t)d.res[0];
+        const u32 nch = (u32)((nX + 63) / 64);
+        // the plan's item count, capped by the host's upper bound of it
+        const u32 total = (u32)min((int64_t)__hip_atomic_load(d.queue + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                                   d.nch_ub * d.gitems_ub);
+        for (;;) {
+            u32 it = 0;
+            if (lane == 0) it = atomicAdd(d.queue, 1u);
+            it = __builtin_amdgcn_readfirstlane(__shfl((int)it, 0, 64));
+            if (it >= total) break;
+            u32 lo = 0, hi = nch;                  // cpre[lo] <= it < cpre[hi]
+            while (hi - lo > 1) {
+                const u32 mid = (lo + hi) >> 1;
+                if (d.cpre[mid] <= it) lo = mid; else hi = mid;
+            }
+            nops += meet_chunk_core<W, true, true>(d, lo, it - d.cpre[lo], slice);
+        }
+    }
+    if (ops) {
+        u32 sum = nops;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) sum += (u32)__shfl_xor((int)sum, off, 64);
+        if (lane == 0 && sum)
+            atomicAdd((unsigned long long *)(ops + (blockIdx.x % kOpsSlots) * kOpsStride), (unsigned long long)sum);
+    }
+}
+
+// ---------------------------------------- inverse levels in buckets
+
+// key of a set: bit kYBits-1-i is [split[i] in the set]
+template <class D>
+__device__ __forceinline__ u32 yb_key_of(const D &d, const u64 *row, const int32_t *split) {
+    u32 k = 0;
+#pragma unroll
+    for (int i = 0; i < kYBits; ++i) {
+        const int q = split[i];
+        const u32 bit = q >= 0 ? (u32)((row[q >> 6] >> (q & 63)) & 1ull) : 0u;
+        k |= bit << (kYBits - 1 - i);
+    }
+    return k;
+}
+
+__device__ __forceinline__ int64_t yb_count(const CONST_AS YbDesc &d) {
+    return d.cnt ? (int64_t)*d.cnt : d.count;
+}
+
+// one block per segment: clear the counters, record the split states
+__global__ void __launch_bounds__(kBS) k_yb_zero(const YbDesc *descs, int nseg) {
+    const CONST_AS YbDesc &d = cref(descs + blockIdx.x);
+    for (int e = threadIdx.x; e < 2 * kYBins; e += kBS) d.bins[e] = 0;
+    if (threadIdx.x < kYBits) {
+        const int q = d.top[threadIdx.x];
+        d.meta->split[threadIdx.x] = q < d.n ? q : -1;
+    }
+}
+
+// keys and bucket sizes (per-block histogram in LDS)
+__global__ void __launch_bounds__(kBS) k_yb_hist(const YbDesc *descs, const int64_t *pre, int nseg) {
+    __shared__ u32 h[kYBins];
+    __shared__ int32_t split[kYBits];
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const CONST_AS YbDesc &d = cref(descs + s);
+    const int64_t j = ((int64_t)blockIdx.x - cref(pre + s)) * kBS + threadIdx.x;
+    for (int e = threadIdx.x; e < kYBins; e += kBS) h[e] = 0;
+    if (threadIdx.x < kYBits) {
+        const int q = d.top[threadIdx.x];
+        split[threadIdx.x] = q < d.n ? q : -1;
+    }
+    __syncthreads();
+    if (j < yb_count(d)) {
+        const u32 k = yb_key_of(d, d.rows + j * d.W, split);
+        d.key[j] = (uint16_t)k;
+        atomicAdd(&h[k], 1u);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kYBins; e += kBS)
+        if (h[e]) atomicAdd(&d.bins[e], h[e]);
+}
+
+// one block per segment: tiles per bucket and their first tiles, the
+// insertion cursors, then the list lengths -- for key a, the tiles of all
+// buckets b containing a (a sum over supersets, one pass per key bit) --
+// and the list offsets; key 0 scans every tile and has no list
+__global__ void __launch_bounds__(kBS) k_yb_scan(const YbDesc *descs, int nseg) {
+    __shared__ u32 t[kYBins];
+    __shared__ u32 wsum[kBS / 64];
+    __shared__ u32 carry;
+    const CONST_AS YbDesc &d = cref(descs + blockIdx.x);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int e = tid; e < kYBins; e += kBS) t[e] = (d.bins[e] + 63) / 64;
+    __syncthreads();
+    // exclusive scan of t into tb (4 entries per thread, in order)
+    auto scan = [&](const u32 *src, u32 *dst, u32 &total) {
+        constexpr int kPer = kYBins / kBS;
+        u32 v[kPer], run = 0;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) { v[i] = src[tid * kPer + i]; run += v[i]; }
+        u32 incl = run;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const u32 o = (u32)__shfl_up((int)incl, off, 64);
+            if (lane >= off) incl += o;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        u32 wpre = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < kBS / 64; ++w) {
+            if (w < wave) wpre += wsum[w];
+            tot += wsum[w];
+        }
+        u32 acc = wpre + incl - run;
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) { dst[tid * kPer + i] = acc; acc += v[i]; }
+        total = tot;
+        __syncthreads();
+    };
+    u32 nt = 0;
+    scan(t, d.tb, nt);
+    if (tid == 0) d.tb[kYBins] = nt;
+    __syncthreads();
+    for (int e = tid; e < kYBins; e += kBS) d.bins[kYBins + e] = d.tb[e] * 64;   // insertion cursors
+    // superset sums of the tile counts
+    for (int i = 0; i < kYBits; ++i) {
+        const u32 bit = 1u << i;
+        for (int e = tid; e < kYBins; e += kBS)
+            if (!(e & bit)) t[e] += t[e | bit];
+        __syncthreads();
+    }
+    if (tid == 0) t[0] = 0;
+    __syncthreads();
+    for (int e = tid; e < kYBins; e += kBS) d.lsize[e] = t[e];
+    u32 ent = 0;
+    scan(t, d.loff, ent);
+    for (int e = tid; e < kYBins; e += kBS) d.lcur[e] = d.loff[e];
+    if (tid == 0) {
+        d.loff[kYBins] = ent;
+        d.meta->nt = (int32_t)nt;
+        d.meta->entries = ent;
+        d.meta->ok = (int64_t)ent <= d.list_cap ? 1 : 0;
+        carry = 0;
+    }
+}
+
+__global__ void __launch_bounds__(kBS) k_yb_fill(const YbDesc *descs, const int64_t *pre, int nseg) {
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const CONST_AS YbDesc &d = cref(descs + s);
+    const int64_t e = ((int64_t)blockIdx.x - cref(pre + s)) * kBS + threadIdx.x;
+    if (e < d.nt_ub * 64) d.idx[e] = 0xFFFFFFFFu;
+}
+
+// every set to a free place of its bucket (any order within a bucket: the
+// meet resolves the least index pair through idx)
+__global__ void __launch_bounds__(kBS) k_yb_scatter(const YbDesc *descs, const int64_t *pre, int nseg) {
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const CONST_AS YbDesc &d = cref(descs + s);
+    const int64_t j = ((int64_t)blockIdx.x - cref(pre + s)) * kBS + threadIdx.x;
+    if (j >= yb_count(d)) return;
+    const u32 pos = atomicAdd(&d.bins[kYBins + d.key[j]], 1u);
+    d.idx[pos] = (u32)j;
+}
+
+// one wave per bucket b: its tiles go into the list of every nonzero key a
+// contained in b (any order within a list)
+__global__ void __launch_bounds__(kBS) k_yb_list(const YbDesc *descs, const int64_t *pre, int nseg) {
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const CONST_AS YbDesc &d = cref(descs + s);
+    const int lane = threadIdx.x & 63;
+    const u32 b = (u32)(((int64_t)blockIdx.x - cref(pre + s)) * (kBS / 64) + (threadIdx.x >> 6));
+    if (b >= (u32)kYBins || !d.meta->ok || b == 0) return;
+    const u32 t0 = d.tb[b], nb = d.tb[b + 1] - t0;
+    if (nb == 0) return;
+    for (u32 a = b; a != 0; a = (a - 1) & b) {
+        u32 base = 0;
+        if (lane == 0) base = atomicAdd(&d.lcur[a], nb);
+        base = (u32)__shfl((int)base, 0, 64);
+        for (u32 i = lane; i < nb; i += 64) d.list[base + i] = t0 + i;
+    }
+}
+
+// the padded level transposed: one wave per (tile, word); padding is empty
+__global__ void __launch_bounds__(kBS) k_yb_transpose(const YbDesc *descs, const int64_t *pre, int nseg) {
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const CONST_AS YbDesc &d = cref(descs + s);
+    const int64_t wv = ((int64_t)blockIdx.x - cref(pre + s)) * (kBS / 64) + (threadIdx.x >> 6);
+    const int W = d.W;
+    const int64_t nt = d.meta->nt;
+    const int64_t tile = wv / W;
+    if (tile >= nt) return;
+    const int w = (int)(wv - tile * W);
+    const int lane = threadIdx.x & 63;
+    const int64_t pos = tile * 64 + lane;
+    const u32 src = d.idx[pos];
+    const bool real = src != 0xFFFFFFFFu;
+    const u64 v = real ? d.rows[(int64_t)src * W + w] : 0ull;
+    if (w == 0) {
+        u64 f = 0;
+        for (int ww = 0; ww < W; ++ww) f |= real ? d.rows[(int64_t)src * W + ww] : 0ull;
+        d.Ysig[pos] = f;
+    }
+    u64 col = 0;
+    for (int bb = 0; bb < 64; ++bb) {
+        const u64 m = __ballot((v >> bb) & 1ull);
+        if (lane == bb) col = m;
+    }
+    d.YT[(int64_t)(64 * w + lane) * nt + tile] = col;
+    d.YTt[(tile * W + w) * 64 + lane] = col;
+}
+
+// ------------------------------------------------------ meet plan (mode 2)
+
+// per chunk: its key and its work items
+__global__ void __launch_bounds__(kBS) k_mp_items(const StepDesc *descs, const int64_t *pre, int nseg) {
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const CONST_AS StepDesc &d = cref(descs + s);
+    if (d.meet_mode != 2) return;
+    const int64_t c = ((int64_t)blockIdx.x - cref(pre + s)) * kBS + threadIdx.x;
+    const int64_t nX = d.nX >= 0 ? d.nX : (int64_t)d.res[0];
+    if (c * 64 >= nX) return;
+    const int W = d.W;
+    u32 a = 0;
+    for (int i = 0; i < kYBits; ++i) {
+        const int q = d.yb->split[i];
+        if (q >= 0 && ((d.Xcom[c * W + (q >> 6)] >> (q & 63)) & 1ull)) a |= 1u << (kYBits - 1 - i);
+    }
+    const int64_t nvt = (a != 0 && d.yb->ok) ? (int64_t)d.yb_lsize[a] : (int64_t)d.yb->nt;
+    const int64_t groups = (nvt + 63) / 64;
+    d.ckey[c] = (uint16_t)a;
+    d.citems[c] = (u32)((groups + d.ngi - 1) / d.ngi);
+}
+
+// one block per segment: first work item of each chunk, the item count, and
+// the queue reset
+__global__ void __launch_bounds__(kBS) k_mp_scan(const StepDesc *descs, int nseg) {
+    __shared__ u32 wsum[kBS / 64];
+    const CONST_AS StepDesc &d = cref(descs + blockIdx.x);
+    if (d.meet_mode != 2) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t nX = d.nX >= 0 ? d.nX : (int64_t)d.res[0];
+    const int64_t nch = (nX + 63) / 64;
+    u32 running = 0;
+    for (int64_t c0 = 0; c0 < nch; c0 += kBS) {
+        const int64_t c = c0 + tid;
+        const u32 v = c < nch ? d.citems[c] : 0u;
+        u32 incl = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const u32 o = (u32)__shfl_up((int)incl, off, 64);
+            if (lane >= off) incl += o;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        u32 wpre = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < kBS / 64; ++w) {
+            if (w < wave) wpre += wsum[w];
+            tot += wsum[w];
+        }
+        if (c < nch) d.cpre[c] = running + wpre + incl - v;
+        running += tot;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        if (nch > 0) d.cpre[nch] = running;
+        d.queue[0] = 0;
+        d.queue[1] = running;
     }
 }
 
@@ -1349,6 +1682,35 @@ hipError_t launch_sort(const SortDesc *d, const int64_t *const pre[3], const int
     hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)blocks[1]), dim3(kBS), 0, st, d, pre[1], nseg);
     if (blocks[2] > 0)
         hipLaunchKernelGGL(k_sort_chunk, dim3((unsigned)blocks[2]), dim3(kBS), 0, st, d, pre[2], nseg);
+    return launch_checked();
+}
+
+// buckets of inverse levels: pre[0] blocks over sets (count_ub), pre[1]
+// over padded positions (nt_ub * 64), pre[2] waves over buckets, pre[3]
+// waves over (tile, word) pairs
+hipError_t launch_ybin(const YbDesc *d, const int64_t *const pre[4], const int64_t blocks[4], int nseg,
+                       hipStream_t st) {
+    if (nseg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_yb_zero, dim3((unsigned)nseg), dim3(kBS), 0, st, d, nseg);
+    if (blocks[0] > 0) hipLaunchKernelGGL(k_yb_hist, dim3((unsigned)blocks[0]), dim3(kBS), 0, st, d, pre[0], nseg);
+    hipLaunchKernelGGL(k_yb_scan, dim3((unsigned)nseg), dim3(kBS), 0, st, d, nseg);
+    if (blocks[1] > 0) hipLaunchKernelGGL(k_yb_fill, dim3((unsigned)blocks[1]), dim3(kBS), 0, st, d, pre[1], nseg);
+    if (blocks[0] > 0) hipLaunchKernelGGL(k_yb_scatter, dim3((unsigned)blocks[0]), dim3(kBS), 0, st, d, pre[0], nseg);
+    if (blocks[2] > 0) hipLaunchKernelGGL(k_yb_list, dim3((unsigned)blocks[2]), dim3(kBS), 0, st, d, pre[2], nseg);
+    if (blocks[3] > 0) hipLaunchKernelGGL(k_yb_transpose, dim3((unsigned)blocks[3]), dim3(kBS), 0, st, d, pre[3], nseg);
+    return launch_checked();
+}
+// plan of the mode-2 meets: pre = blocks over chunks per segment
+hipError_t launch_meet_plan(const StepDesc *d, const int64_t *pre, int nseg, int64_t blocks, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mp_items, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
+    hipLaunchKernelGGL(k_mp_scan, dim3((unsigned)nseg), dim3(kBS), 0, st, d, nseg);
+    return launch_checked();
+}
+// mode-2 meets of segments s0..s1-1 (width W), `grid` blocks
+hipError_t launch_meet_b(const StepDesc *d, int s0, int s1, int W, int64_t grid, u64 *ops, hipStream_t st) {
+    if (grid <= 0 || s1 <= s0) return hipSuccess;
+    SRW_SWITCH_W(W, hipLaunchKernelGGL(k_meet_b<W>, dim3((unsigned)grid), dim3(kBS), 0, st, d, s0, s1, ops));
     return launch_checked();
 }
 

@@ -35,7 +35,7 @@ def gpu():
 DEFAULTS = (("schedule", 0), ("meet_tiles", 0), ("keep_levels", 0), ("budget", 0), ("meet", 0),
             ("max_slots", 4096), ("meet_rows", 512), ("meet_groups", 16), ("meet_order", 1),
             ("meet_grid", 0), ("small_cand", 2048), ("ysort", 0), ("deadline_ms", 0),
-            ("verbose", 0), ("persist", 1))
+            ("verbose", 0), ("persist", 1), ("bucket", 16384))
 
 
 def say(*a):
@@ -522,6 +522,28 @@ def test_random_n256_against_stored_oracle_values():
         assert "".join(map(str, w)) == c["word"]
 
 
+@pytest.mark.parametrize("bucket", [16384, 0])
+def test_random_n450_against_stored_oracle_value(bucket):
+    """The n = 450, k = 2 automaton of the benchmark: 8-word sets, levels of
+    millions of sets, hash tables grown far past 10^7 slots, the chunked meet
+    at full size with its inverse levels in buckets (default) and in level
+    order (0).  r and word equal the oracle's stored values
+    (tests/golden/n450.json; about 40 minutes of oracle time)."""
+    path = os.path.join(GOLDEN, "n450.json")
+    if not os.path.exists(path):
+        pytest.skip("no stored oracle value for n = 450")
+    with open(path) as f:
+        c = json.load(f)["cases"][0]
+    d = I.random_automaton(c["n"], c["k"], c["seed"], c["attempt"])
+    assert I.first_synchronizing(450, 2, c["seed"], srw.check_sync)[1] == c["attempt"]
+    srw.set_option("bucket", bucket)
+    try:
+        say("n450 bucket", bucket)
+        assert srw.solve(450, 2, d) == (c["r"], [int(x) for x in c["word"]])
+    finally:
+        srw.set_option("bucket", 16384)
+
+
 def test_random_n256_lds_tile_meet_equals_stored():
     cs = golden("rand256.json")[:2]
     srw.set_option("meet", 1)
@@ -623,6 +645,33 @@ def test_persistent_small_steps_keep_results(persist, small):
         srw.set_option("keep_levels", 0)
         srw.set_option("persist", 1)
         srw.set_option("small_cand", 2048)
+
+
+@pytest.mark.parametrize("bucket,meet", [(0, 0), (1, 2), (64, 0), (1, 0)])
+def test_bucketed_meet_keeps_results(bucket, meet):
+    """Inverse levels in buckets by their membership of the forward level's
+    most frequent states, met by chunks that scan only the buckets holding
+    their common split states: off (0), for every level against every
+    forward level sorted into chunks (1 with meet mode 2, so tiny and
+    one-bucket levels too), from 64 sets on, and for every level the default
+    schedule sorts.  r and word equal the oracle's, singly and batched."""
+    cs = [(n, 2, I.cerny(n)) for n in (9, 20)]
+    cs += [(n, k, rand_sync(n, k, j, base=61)) for j, (n, k) in
+           enumerate([(64, 2), (150, 2), (200, 3), (129, 2), (40, 4), (255, 2), (90, 3)])]
+    cs += [(200, 2, d) for d in (many_common_states(200, s) for s in range(4))
+           if O.is_synchronizing(200, 2, d)][:2]
+    want = [oracle_rw(n, k, d) for n, k, d in cs]
+    srw.set_option("bucket", bucket)
+    srw.set_option("meet", meet)
+    try:
+        for (n, k, d), w in zip(cs, want):
+            say("bucketed meet", bucket, meet, n, k)
+            assert srw.solve(n, k, d) == w, (n, k)
+        res = srw.solve_batch(cs)
+        assert [(st, (r, wd)) for st, r, wd in res] == [(srw.OK, w) for w in want]
+    finally:
+        srw.set_option("bucket", 16384)
+        srw.set_option("meet", 0)
 
 
 @pytest.mark.parametrize("ysort", [0, 1])

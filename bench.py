@@ -291,13 +291,16 @@ def roofline(stats, cls_stats, workload):
     if dom == "meet" and stats["meet_w"]:
         # the meet launches one kernel per set width: take the one with the
         # most time.  Unit: the set operations of the chunked meet as the
-        # kernel counts them (32-bit lane-ops: 2 per 64-bit column AND, 4 per
-        # word of a row subset test), against the chip's 32-bit VALU rate.
-        # The brute-force pair-word count |L_f| * |L_b| * W is reported beside
-        # it: its ratio to the ops performed is what the chunking prunes.
+        # counting build of the kernel counts them in the extra pass (32-bit
+        # lane-ops: 2 per 64-bit column AND, 4 per word of a row subset
+        # test), over the launch time of the timed region's kernel, against
+        # the chip's 32-bit VALU rate.  The brute-force pair-word count
+        # |L_f| * |L_b| * W is reported beside it: its ratio to the ops
+        # performed is what the chunking prunes.
         W, m = max(stats["meet_w"].items(), key=lambda kv: kv[1]["ms"])
         t = m["ms"] / m["launches"] / 1e3
-        ops = m["ops"] / m["launches"]
+        mc = cls_stats.get("meet_w", {}).get(W, m)
+        ops = mc["ops"] / max(1, mc["launches"])
         ach = ops / t / 1e12
         name = f"k_meet<{W}>"
         return {"kernel": name, "bound": "alu", "achieved": ach, "peak": VALU_PEAK_TOPS,
@@ -504,6 +507,8 @@ def main():
     ap.add_argument("--batch-nmax", type=int, default=160,
                     help="... its members with n <= BATCH_NMAX (0: all)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparison")
+    ap.add_argument("--set", action="append", default=[], metavar="KEY=VALUE",
+                    help="library option (srw_set_option) for the whole run; repeatable")
     ap.add_argument("--cpu-budget", type=float, default=40.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -564,6 +569,9 @@ def main():
     import torch
     torch.cuda.set_device(0)
     srw.use_torch(0)
+    for kv in args.set:
+        key, val = kv.split("=", 1)
+        srw.set_option(key, int(val))
     batch = [(n, k, d) for n, k, d, _ in probs]
     print(f"workload {args.workload}: {len(probs)} automata", file=sys.stderr, flush=True)
 
@@ -617,6 +625,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u64", "data": "synthetic",
         "config": {"workload": args.workload,
+                   "options": dict(kv.split("=", 1) for kv in args.set),
                    "automata": len(probs),
                    "sizes": {
                        "n64k2x100": "100 x random n=64 k=2",
@@ -636,7 +645,9 @@ def main():
         "subsets_per_step": cand,
         "pairs_per_step": stats["pairs"] / args.steps,
         "kernels": class_table(cls_stats),
-        "kernels_note": "per-class times of one extra pass with every class timed",
+        "meet_work": cls_stats["meet_work"],
+        "kernels_note": "per-class times of one extra pass with every class timed (and the "
+                        "meet's counting build: meet_work)",
         "roofline": roofline(stats, cls_stats, args.workload),
     }
     if not args.no_plain and len(batch) > 1:

@@ -150,9 +150,11 @@ int srw_set_stream(void *hip_stream);
  * srw_solve_batch).  Keys:
  *   "budget"      device memory budget in bytes (0: 80% of free memory)
  *   "max_slots"   automata resident at once in srw_solve_batch
- *   "profile"     1: time every kernel class with HIP events (srw_get_stats);
- *                 2: time the meet launches only (per set width) and count
- *                 their set operations -- light enough for a timed run;
+ *   "profile"     1: time every kernel class with HIP events (srw_get_stats)
+ *                 and run the counting build of the meet kernels (their set
+ *                 operations and work in meet_ops_w, meet_work);
+ *                 2: time the meet launches only (per set width) -- light
+ *                 enough for a timed run;
  *                 0: off
  *   "schedule"    0: smaller frontier first, ties forward (default)
  *                 1: pseudo-random side per step from "sched_seed"
@@ -169,7 +171,9 @@ int srw_set_stream(void *hip_stream);
  *   "meet_groups" chunked meet: groups of 64 tiles per work item (at most;
  *                 default 16)
  *   "meet_order"  chunked meet work items: 1 chunk-major (default), 0 tile-
- *                 range-major (consecutive items share one range of tiles)
+ *                 range-major (consecutive items share one range of tiles;
+ *                 with an inverse level in buckets: within each key of the
+ *                 chunks)
  *   "meet_grid"   meet blocks per launch, grid-striding over the work items
  *                 (0: one block per work item, up to 2^31-1)
  *   "ysort"       new inverse levels of at least this many candidates are
@@ -219,10 +223,15 @@ typedef struct srw_stats {
     int64_t pair_words_w[8];   /* their brute-force pair-word count */
     int64_t meet_ops_w[8];     /* set operations they performed, in 32-bit lane-ops
                                   (2 per 64-bit AND, 4 per word of a subset test),
-                                  with "profile" 1 or 2 */
+                                  with "profile" 1 (the counting build of the kernels) */
     double host_ms[4];         /* wall time of the steps by phase: 0 sides, growth and
                                   copies; 1 descriptors, uploads and launches; 2 waiting
                                   for the device; 3 results, meets and words */
+    int64_t meet_work[8];      /* chunked meets, with "profile" 1: 0 work items,
+                                  1 tile groups scanned, 2 groups with candidate sets,
+                                  3 candidates tested by signature, 4 signature passes
+                                  (full row tests), 5 tiles tested column by column,
+                                  6 tiles scanned, 7 unused */
 } srw_stats;
 /* kernel classes: 0 expand (and whole one-block steps), 1 insert, 2 count+scan+compact, 3 meet
  * preparation (transpose of inverse levels, bucket sort of forward levels),

@@ -28,6 +28,9 @@ constexpr int kCommonRound = 4;          // common columns loaded per round
 constexpr int kOpsSlots = 64;
 constexpr int kOpsStride = 16;
 constexpr int kOpsWords = kMaxW * kOpsSlots * kOpsStride;
+constexpr int kMstatCounters = 8;
+constexpr int kMstatSlots = 64;
+constexpr int kMstatWords = kMstatSlots * kOpsStride;
 constexpr int64_t kSmallMeetBlocks = 64;  // small steps: at most this many LDS-tile meet blocks
 constexpr int kRowBatchMax = 512;        // chunked meet: most candidates per group tested by signature
 // LDS words per wave of the chunked meet: kRowBatchMax candidate indices (u32)
@@ -53,6 +56,11 @@ constexpr int kYBits = 10;
 constexpr int kYBins = 1 << kYBits;
 constexpr int64_t kYMin = 16384;          // default: inverse levels at least this large are bucketed
 constexpr int64_t kYListPerTile = 32;     // room for list entries per tile of the level
+// a bucketed meet's plan: chunks are taken in order of their least index in
+// the level, by kOrderBins bins of that index (the least meeting pair is
+// sought, so that a pair found early lets the chunks of larger index stop)
+constexpr int kOrderBins = 1024;
+constexpr int kKCount = 0, kKCur = kOrderBins, kKInfoWords = 2 * kOrderBins;
 
 struct YbMeta {
     int32_t nt;                 // tiles of the padded level
@@ -136,14 +144,18 @@ struct StepDesc {
     // the work items (one chunk, a range of its tiles) taken from a queue
     const YbMeta *yb;
     const u32 *yb_lsize, *yb_loff, *yb_list;
-    uint16_t *ckey;            // per chunk: its key
-    u32 *citems;               // per chunk: work items
-    u32 *cpre;                 // per chunk: first work item
+    u32 *ckey;                 // per chunk: its key | (its order bin << 16)
+    u32 *korder;               // the chunks in order of their least index in the level
+    u32 *cpre;                 // per place in korder: its first work item (then the count)
+    u32 *kinfo;                // per order bin: chunks, insertion cursor
     u32 *queue;                // [0] next work item, [1] work items
     // transpose of a new inverse level into YT
     int64_t ntr_waves;         // upper bound of (tile, word) waves
     // results: res[0] = new level size, res[1] = least (i << 32 | j) meeting pair
     u64 *res;
+    // chunked meets, when profiling: kMstatSlots slots of kMstatCounters
+    // counters (kOpsStride words apart), see srw_stats.meet_work
+    u64 *mstat;
 };
 
 // A block that runs every step of one automaton by itself for as long as

@@ -415,9 +415,9 @@ struct Problem {
     int64_t yb_idx_cap = 0;
     u32 *yb_list = nullptr;
     int64_t yb_list_cap = 0;
-    // plan of a bucketed meet: per chunk its key, work items and first item
-    uint16_t *mp_key = nullptr;
-    u32 *mp_items = nullptr, *mp_pre = nullptr, *mp_queue = nullptr;
+    // plan of a bucketed meet: per chunk its key, the chunks in key order,
+    // per key counts and offsets, the work queue
+    u32 *mp_key = nullptr, *mp_order = nullptr, *mp_cpre = nullptr, *mp_kinfo = nullptr, *mp_queue = nullptr;
     int64_t mp_cap = 0;       // chunks
     int status = 1;           // 1 running, else SRW_ status
     int32_t r = -1;
@@ -513,13 +513,17 @@ class Engine {
     srw_stats stats() {
         srw_stats out = stats_;
         if (d_ops_) {
-            u64 *h = (u64 *)pin_misc_.acquire(kOpsWords * sizeof(u64));
-            HIPCHK(hipMemcpyAsync(h, d_ops_, kOpsWords * sizeof(u64), hipMemcpyDeviceToHost, stream_));
+            u64 *h = (u64 *)pin_misc_.acquire((kOpsWords + kMstatWords) * sizeof(u64));
+            HIPCHK(hipMemcpyAsync(h, d_ops_, (kOpsWords + kMstatWords) * sizeof(u64), hipMemcpyDeviceToHost, stream_));
             HIPCHK(hipStreamSynchronize(stream_));
             for (int w = 0; w < kMaxW; ++w) {
                 out.meet_ops_w[w] = 0;
                 for (int sl = 0; sl < kOpsSlots; ++sl)
                     out.meet_ops_w[w] += (int64_t)h[((int64_t)w * kOpsSlots + sl) * kOpsStride];
+            }
+            for (int c = 0; c < kMstatCounters; ++c) {
+                out.meet_work[c] = 0;
+                for (int sl = 0; sl < kMstatSlots; ++sl) out.meet_work[c] += (int64_t)h[kOpsWords + sl * kOpsStride + c];
             }
         }
         return out;
@@ -527,7 +531,7 @@ class Engine {
     void reset_stats() {
         memset(&stats_, 0, sizeof stats_);
         if (d_ops_) {
-            HIPCHK(launch_fill(d_ops_, kOpsWords, 0, stream_));
+            HIPCHK(launch_fill(d_ops_, kOpsWords + kMstatWords, 0, stream_));
             HIPCHK(hipStreamSynchronize(stream_));
         }
     }
@@ -795,6 +799,7 @@ class Engine {
             d_res_ = (u64 *)pool_->alloc((size_t)res_cap_ * 8, true);
             if (!d_res_) throw HipFailure{hipErrorOutOfMemory, "step result buffer"};
         }
+        ensure_ops();
         for (int i = 0; i < nseg; ++i) {
             Problem *p = segp[i];
             const int dir = segdir[i];
@@ -843,6 +848,7 @@ class Engine {
                 ny_ub = d.C;
             }
             d.res = d_res_ + 2 * i;
+            d.mstat = opt.profile == 1 ? d_ops_ + kOpsWords : nullptr;
             // chunked meet over the sorted forward level when it exists
             if ((dir == 0 && p->sort_now) || (dir == 1 && p->xs_valid && opt.meet != 1)) {
                 d.meet_mode = bucketed_meet(p, dir) ? 2 : 1;
@@ -891,8 +897,9 @@ class Engine {
                 d.yb_list = p->yb_list;
                 d.Yidx = p->yb_idx;
                 d.ckey = p->mp_key;
-                d.citems = p->mp_items;
-                d.cpre = p->mp_pre;
+                d.korder = p->mp_order;
+                d.cpre = p->mp_cpre;
+                d.kinfo = p->mp_kinfo;
                 d.queue = p->mp_queue;
             }
             if (dir == 0 && p->sort_now) {
@@ -1008,7 +1015,6 @@ class Engine {
         const int64_t yblocks[4] = {pyb[0].back(), pyb[1].back(), pyb[2].back(), pyb[3].back()};
         const int64_t *dpmp = (const int64_t *)(dblob + oMP);
 
-        ensure_ops();
         prof_begin(0);
         HIPCHK(launch_step_small(dD, dsmall, nsmall, opt.profile ? d_ops_ : nullptr, stream_));
         HIPCHK(launch_expand(dD, dpe, nseg, pe[nseg], stream_));
@@ -1049,7 +1055,8 @@ class Engine {
                 HIPCHK(hipEventRecord(ev_meet_[2 * (W - 1)], stream_));
                 meet_used_[W - 1] = true;
             }
-            u64 *ops = opt.profile ? d_ops_ + (int64_t)(W - 1) * kOpsSlots * kOpsStride : nullptr;
+            // operations are counted by the counting kernels, with profile 1
+            u64 *ops = opt.profile == 1 ? d_ops_ + (int64_t)(W - 1) * kOpsSlots * kOpsStride : nullptr;
             if (pm[s1] > pm[s0]) {
                 bool ys = false;                   // an inverse level in cardinality order
                 for (int i = s0; i < s1; ++i) ys = ys || (D[i].meet_mode != 2 && D[i].Yidx != nullptr);
@@ -1298,9 +1305,9 @@ class Engine {
     // the meet's operation counters, once profiling is on
     void ensure_ops() {
         if (opt.profile && !d_ops_) {
-            d_ops_ = (u64 *)pool_->alloc(kOpsWords * sizeof(u64), true);
+            d_ops_ = (u64 *)pool_->alloc((kOpsWords + kMstatWords) * sizeof(u64), true);
             if (!d_ops_) throw HipFailure{hipErrorOutOfMemory, "meet counters"};
-            HIPCHK(launch_fill(d_ops_, kOpsWords, 0, stream_));
+            HIPCHK(launch_fill(d_ops_, kOpsWords + kMstatWords, 0, stream_));
         }
     }
 
@@ -1492,14 +1499,15 @@ class Engine {
     bool ensure_plan(Problem *p, int64_t nch) {
         if (nch <= p->mp_cap && p->mp_queue) return true;
         pool_->free(p->mp_key);
-        pool_->free(p->mp_items);
-        pool_->free(p->mp_pre);
+        pool_->free(p->mp_order);
+        pool_->free(p->mp_cpre);
         const int64_t nc = std::max(nch, 2 * p->mp_cap);
-        p->mp_key = (uint16_t *)pool_->alloc((size_t)nc * 2);
-        p->mp_items = (u32 *)pool_->alloc((size_t)nc * 4);
-        p->mp_pre = (u32 *)pool_->alloc((size_t)(nc + 1) * 4);
+        p->mp_key = (u32 *)pool_->alloc((size_t)nc * 4);
+        p->mp_order = (u32 *)pool_->alloc((size_t)nc * 4);
+        p->mp_cpre = (u32 *)pool_->alloc((size_t)(nc + 1) * 4);
+        if (!p->mp_kinfo) p->mp_kinfo = (u32 *)pool_->alloc((size_t)kKInfoWords * 4);
         if (!p->mp_queue) p->mp_queue = (u32 *)pool_->alloc(256);
-        p->mp_cap = (p->mp_key && p->mp_items && p->mp_pre && p->mp_queue) ? nc : 0;
+        p->mp_cap = (p->mp_key && p->mp_order && p->mp_cpre && p->mp_kinfo && p->mp_queue) ? nc : 0;
         return p->mp_cap > 0;
     }
 
@@ -1602,14 +1610,15 @@ class Engine {
         pool_->free(p->ysig); p->ysig = nullptr; p->ysig_cap = 0;
         pool_->free(p->d_off); p->d_off = nullptr; p->max_lev = 0;
         for (void *q : {(void *)p->yb_small, (void *)p->yb_key, (void *)p->yb_idx, (void *)p->yb_list,
-                        (void *)p->mp_key, (void *)p->mp_items, (void *)p->mp_pre, (void *)p->mp_queue})
+                        (void *)p->mp_key, (void *)p->mp_order, (void *)p->mp_cpre, (void *)p->mp_kinfo,
+                        (void *)p->mp_queue})
             pool_->free(q);
         p->yb_small = nullptr;
         p->yb_key = nullptr;
         p->yb_idx = p->yb_list = nullptr;
         p->yb_key_cap = p->yb_idx_cap = p->yb_list_cap = 0;
         p->mp_key = nullptr;
-        p->mp_items = p->mp_pre = p->mp_queue = nullptr;
+        p->mp_order = p->mp_cpre = p->mp_kinfo = p->mp_queue = nullptr;
         p->mp_cap = 0;
         p->yb_valid = p->yb_now = false;
         pool_->free(p->ys_hist); pool_->free(p->ys_cnt); pool_->free(p->ys_idx);

@@ -528,7 +528,10 @@ __device__ __forceinline__ void wave_sync_lds() {
 // of a hold in every set of those buckets, so they are taken out of each X
 // and out of the filtering states.  Level indices come through Yidx (the
 // bucket order is not the level order, so a hit does not end a lane).
-template <int W, bool YS, bool BK>
+//
+// CNT: count the set operations (the returned lane-ops) and the work (into
+// d.mstat); a profiling build of the kernel, the other one does neither.
+template <int W, bool YS, bool BK, bool CNT>
 __device__ u32 meet_chunk_core(const CONST_AS StepDesc &d, int64_t c, int64_t gi, u64 *slice) {
     const int lane = threadIdx.x & 63;
     const u32 *Yidx = YS ? d.Yidx : nullptr;
@@ -652,18 +655,27 @@ __device__ u32 meet_chunk_core(const CONST_AS StepDesc &d, int64_t c, int64_t gi
     const u64 last_rows = (BK || (nY & 63) == 0) ? ~0ull : ((1ull << (nY & 63)) - 1ull);
     // one group with its first-round columns in cur; refills cur for group g + 2.
     // false: every lane of the wave is done
+    // work counters (the same in every lane; row tests per lane)
+    u32 w_groups = 0, w_groups_k = 0, w_cand = 0, w_col_tiles = 0, w_tiles = 0, w_full = 0;
     auto group = [&](int64_t g, u64 *cur) -> bool {
+        // every fourth group: a lane whose X has a larger index than a
+        // meeting pair found meanwhile is done (the least pair is sought)
+        if ((g & 3) == 3 && (load_slot(d.res + 1) >> 32) < (u64)orig) done = true;
         if (__ballot(!done) == 0) return false;
         const int64_t vt = g * 64 + lane;
         const bool tv = vt < nt_lim;
         const int64_t t = tile_of(vt);
+        if (CNT) {
+            ++w_groups;
+            w_tiles += (u32)__popcll(__ballot(tv));
+        }
         // lanes past the tiles (t >= nt_lim, so also t >= nt) start from 0,
         // so the raw word they loaded does not matter; an unused state (cq
         // < 0, uniform over the wave) contributes no column
         u64 m = !tv ? 0ull : (t == nt - 1 ? last_rows : ~0ull);
 #pragma unroll
         for (int r = 0; r < kCommonRound; ++r) m &= cq[r] >= 0 ? cur[r] : ~0ull;
-        if (tv) nops += 2 * min(nc, kCommonRound);
+        if (CNT && tv) nops += 2 * min(nc, kCommonRound);
         // further common columns, in rounds of independent loads (issued
         // before the lookahead of group g + 2, so that waiting for them does
         // not also wait for that lookahead)
@@ -678,7 +690,7 @@ __device__ u32 meet_chunk_core(const CONST_AS StepDesc &d, int64_t c, int64_t gi
             }
 #pragma unroll
             for (int r = 0; r < kCommonRound; ++r) m &= cq[r0 + r] >= 0 ? v[r] : ~0ull;
-            if (tv) nops += 2 * min(nc - r0, kCommonRound);
+            if (CNT && tv) nops += 2 * min(nc - r0, kCommonRound);
         }
         if (g + 2 < g1) first_round(g + 2, cur);
         if (__ballot(m != 0) == 0) return true;      // the usual case: no candidate in the group
@@ -692,7 +704,9 @@ __device__ u32 meet_chunk_core(const CONST_AS StepDesc &d, int64_t c, int64_t gi
         }
         const u32 K = (u32)__shfl((int)incl, 63, 64);
         if (K == 0) return true;
+        if (CNT) ++w_groups_k;
         if (K <= (u32)d.row_batch_max) {              // row_batch_max <= kRowBatchMax
+            if (CNT) w_cand += K;
             wave_sync_lds();                           // the last group's lists are read
             {
                 u64 mm = m;
@@ -716,27 +730,42 @@ __device__ u32 meet_chunk_core(const CONST_AS StepDesc &d, int64_t c, int64_t gi
                 }
             }
             wave_sync_lds();
-            if (!done) nops += K * 2;
-            for (u32 c0 = 0; c0 < K; c0 += 4) {
-                bool p = false;
+            if (CNT && !done) nops += K * 2;
+            // K is the same in every lane: loop bounds and the tail test are
+            // scalar.  Eight candidates a round: one broadcast LDS read and
+            // one branch-free test each; a lane whose X passes a signature
+            // test (rare) tests those candidates' rows in full.
+            const u32 Ku = __builtin_amdgcn_readfirstlane(K);
+            auto full = [&](u32 c0, u32 cnt) {
+                for (u32 u = 0; u < cnt; ++u) {
+                    const u32 cc = c0 + u;
+                    if (done || (xs & ~sig[cc]) != 0) continue;
+                    const u32 jc = Yidx ? Yidx[jl[cc]] : jl[cc];   // index in the level
+                    u64 out = 0;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) p |= c0 + u < K && (xs & ~sig[c0 + u]) == 0;
-                if (p && !done) {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const u32 cc = c0 + u;
-                        if (done || cc >= K || (xs & ~sig[cc]) != 0) continue;
-                        const u32 jc = Yidx ? Yidx[jl[cc]] : jl[cc];   // index in the level
-                        u64 out = 0;
-#pragma unroll
-                        for (int w = 0; w < W; ++w) out |= x[w] & ~d.Yrows[(int64_t)jc * W + w];
+                    for (int w = 0; w < W; ++w) out |= x[w] & ~d.Yrows[(int64_t)jc * W + w];
+                    if (CNT) {
                         nops += 4 * W;
-                        if (out == 0) {
-                            atomicMin(d.res + 1, ((u64)orig << 32) | (u64)jc);
-                            done = !Yidx;          // cardinality order: a later hit may be smaller
-                        }
+                        ++w_full;
+                    }
+                    if (out == 0) {
+                        atomicMin(d.res + 1, ((u64)orig << 32) | (u64)jc);
+                        done = !Yidx;              // another order: a later hit may be smaller
                     }
                 }
+            };
+            u32 c0 = 0;
+            for (; c0 + 8 <= Ku; c0 += 8) {
+                bool p = false;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) p |= (xs & ~sig[c0 + u]) == 0;
+                if (__ballot(p && !done)) full(c0, 8);
+            }
+            if (c0 < Ku) {
+                bool p = false;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) p |= c0 + u < Ku && (xs & ~sig[c0 + u]) == 0;
+                if (__ballot(p && !done)) full(c0, Ku - c0);
             }
             return true;
         }
@@ -749,6 +778,7 @@ __device__ u32 meet_chunk_core(const CONST_AS StepDesc &d, int64_t c, int64_t gi
             const u64 mc = shfl64(m, lt);
             const int64_t tt = BK ? (int64_t)shfl64((u64)t, lt) : g * 64 + lt;
             if (__ballot(!done) == 0) break;
+            if (CNT) ++w_col_tiles;
             wave_sync_lds();                       // the last tile is read
 #pragma unroll
             for (int w = 0; w < W; ++w) slice[64 * w + lane] = d.YTt[tt * 64 * W + 64 * w + lane];
@@ -766,7 +796,7 @@ __device__ u32 meet_chunk_core(const CONST_AS StepDesc &d, int64_t c, int64_t gi
                     M &= slice[q];
                     if (M == 0) { alive = false; break; }
                 }
-                nops += 2 * (u32)(__popcll(x[w]) - __popcll(b));
+                if (CNT) nops += 2 * (u32)(__popcll(x[w]) - __popcll(b));
             }
             if (alive) {
                 if (!Yidx) {
@@ -789,17 +819,32 @@ __device__ u32 meet_chunk_core(const CONST_AS StepDesc &d, int64_t c, int64_t gi
         if (!group(g, pa)) break;
         if (g + 1 < g1 && !group(g + 1, pb)) break;
     }
+    if (CNT && d.mstat) {
+        u32 full = w_full;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) full += (u32)__shfl_xor((int)full, off, 64);
+        if (lane == 0) {
+            u64 *m = d.mstat + (blockIdx.x % kMstatSlots) * kOpsStride;
+            atomicAdd((unsigned long long *)m + 0, 1ull);
+            atomicAdd((unsigned long long *)m + 1, (unsigned long long)w_groups);
+            atomicAdd((unsigned long long *)m + 2, (unsigned long long)w_groups_k);
+            atomicAdd((unsigned long long *)m + 3, (unsigned long long)w_cand);
+            atomicAdd((unsigned long long *)m + 4, (unsigned long long)full);
+            atomicAdd((unsigned long long *)m + 5, (unsigned long long)w_col_tiles);
+            atomicAdd((unsigned long long *)m + 6, (unsigned long long)w_tiles);
+        }
+    }
     return nops;
 }
 
-template <int W, bool YS>
+template <int W, bool YS, bool CNT>
 __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice) {
     // tile-range-major: the items in flight share one range of tiles, so its
     // columns and rows stay in L2 (every XCD works on the same range)
     int64_t c, gi;
     if (d.item_order == 0) { gi = udiv(item, d.nch_ub); c = item - gi * d.nch_ub; }
     else { c = udiv(item, d.gitems_ub); gi = item - c * d.gitems_ub; }
-    return meet_chunk_core<W, YS, false>(d, c, gi, slice);
+    return meet_chunk_core<W, YS, false, CNT>(d, c, gi, slice);
 }
 
 // Grid-stride over work items: mode 0 items are blocks (256 sets X against
@@ -809,7 +854,7 @@ __device__ u32 meet_chunk_w(const CONST_AS StepDesc &d, int64_t item, u64 *slice
 // register count of the narrow widths low).  With `ops` set, the set
 // operations the launch performed (32-bit lane-ops) are added to the
 // kOpsSlots counters at ops (kOpsStride words apart).
-template <int W, bool YS>
+template <int W, bool YS, bool CNT>
 __global__ void __launch_bounds__(kBS) k_meet(const StepDesc *descs, const int64_t *pre, int s0, int s1, u64 *ops) {
     __shared__ u64 cols[kMeetLdsWords];
     const int64_t base = cref(pre + s0), items = cref(pre + s1) - base;
@@ -823,7 +868,7 @@ __global__ void __launch_bounds__(kBS) k_meet(const StepDesc *descs, const int64
             nops = meet_w<W, YS>(d, li, cols);
         } else {
             const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform per wave
-            nops = meet_chunk_w<W, YS>(d, li * (kBS / 64) + wave, cols + wave * kSliceWords);
+            nops = meet_chunk_w<W, YS, CNT>(d, li * (kBS / 64) + wave, cols + wave * kSliceWords);
         }
         if (ops) {
             u32 sum = nops;   // at most a few million per wave and item
@@ -837,9 +882,10 @@ __global__ void __launch_bounds__(kBS) k_meet(const StepDesc *descs, const int64
 
 // Mode 2: waves take work items from each segment's queue in turn, until
 // the queue is empty (its counter passes the item count the plan wrote),
-// so every wave of the grid ends.  Items of a chunk (cpre: its first item)
-// cover consecutive ranges of d.ngi tile groups of its list.
-template <int W>
+// so every wave of the grid ends.  Work items go chunk by chunk in the
+// plan's order (least index in the level first), each a range of d.ngi
+// tile groups of the chunk's list.
+template <int W, bool CNT>
 __global__ void __launch_bounds__(kBS) k_meet_b(const StepDesc *descs, int s0, int s1, u64 *ops) {
     __shared__ u64 cols[kMeetLdsWords];
     const int lane = threadIdx.x & 63;
@@ -864,7 +910,7 @@ __global__ void __launch_bounds__(kBS) k_meet_b(const StepDesc *descs, int s0, i
                 const u32 mid = (lo + hi) >> 1;
                 if (d.cpre[mid] <= it) lo = mid; else hi = mid;
             }
-            nops += meet_chunk_core<W, true, true>(d, lo, it - d.cpre[lo], slice);
+            nops += meet_chunk_core<W, true, true, CNT>(d, d.korder[lo], it - d.cpre[lo], slice);
         }
     }
     if (ops) {
@@ -1001,14 +1047,28 @@ __global__ void __launch_bounds__(kBS) k_yb_fill(const YbDesc *descs, const int6
 }
 
 // every set to a free place of its bucket (any order within a bucket: the
-// meet resolves the least index pair through idx)
+// meet resolves the least index pair through idx).  The block's sets of one
+// bucket take one range of places with a single global atomic; within the
+// block each set's place comes from an LDS counter.
 __global__ void __launch_bounds__(kBS) k_yb_scatter(const YbDesc *descs, const int64_t *pre, int nseg) {
+    __shared__ u32 h[kYBins];
+    __shared__ u32 base[kYBins];
     const int s = find_seg(pre, nseg, blockIdx.x);
     const CONST_AS YbDesc &d = cref(descs + s);
     const int64_t j = ((int64_t)blockIdx.x - cref(pre + s)) * kBS + threadIdx.x;
-    if (j >= yb_count(d)) return;
-    const u32 pos = atomicAdd(&d.bins[kYBins + d.key[j]], 1u);
-    d.idx[pos] = (u32)j;
+    for (int e = threadIdx.x; e < kYBins; e += kBS) h[e] = 0;
+    __syncthreads();
+    const bool valid = j < yb_count(d);
+    u32 k = 0, lpos = 0;
+    if (valid) {
+        k = d.key[j];
+        lpos = atomicAdd(&h[k], 1u);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kYBins; e += kBS)
+        if (h[e]) base[e] = atomicAdd(&d.bins[kYBins + e], h[e]);
+    __syncthreads();
+    if (valid) d.idx[base[k] + lpos] = (u32)j;
 }
 
 // one wave per bucket b: its tiles go into the list of every nonzero key a
@@ -1060,39 +1120,56 @@ __global__ void __launch_bounds__(kBS) k_yb_transpose(const YbDesc *descs, const
 
 // ------------------------------------------------------ meet plan (mode 2)
 
-// per chunk: its key and its work items
-__global__ void __launch_bounds__(kBS) k_mp_items(const StepDesc *descs, const int64_t *pre, int nseg) {
+// chunk key (the split states common to the chunk)
+template <class D>
+__device__ __forceinline__ u32 chunk_key(const D &d, int64_t c) {
+    u32 a = 0;
+    for (int i = 0; i < kYBits; ++i) {
+        const int q = d.yb->split[i];
+        if (q >= 0 && ((d.Xcom[c * d.W + (q >> 6)] >> (q & 63)) & 1ull)) a |= 1u << (kYBits - 1 - i);
+    }
+    return a;
+}
+
+// one block per segment: clear the order bins
+__global__ void __launch_bounds__(kBS) k_mp_zero(const StepDesc *descs, int nseg) {
+    const CONST_AS StepDesc &d = cref(descs + blockIdx.x);
+    if (d.meet_mode != 2) return;
+    for (int e = threadIdx.x; e < kOrderBins; e += kBS) d.kinfo[kKCount + e] = 0;
+}
+
+// per chunk: its key and its order bin (of its least index in the level),
+// counted per bin
+__global__ void __launch_bounds__(kBS) k_mp_keys(const StepDesc *descs, const int64_t *pre, int nseg) {
+    __shared__ u32 h[kOrderBins];
     const int s = find_seg(pre, nseg, blockIdx.x);
     const CONST_AS StepDesc &d = cref(descs + s);
     if (d.meet_mode != 2) return;
     const int64_t c = ((int64_t)blockIdx.x - cref(pre + s)) * kBS + threadIdx.x;
     const int64_t nX = d.nX >= 0 ? d.nX : (int64_t)d.res[0];
-    if (c * 64 >= nX) return;
-    const int W = d.W;
-    u32 a = 0;
-    for (int i = 0; i < kYBits; ++i) {
-        const int q = d.yb->split[i];
-        if (q >= 0 && ((d.Xcom[c * W + (q >> 6)] >> (q & 63)) & 1ull)) a |= 1u << (kYBits - 1 - i);
+    for (int e = threadIdx.x; e < kOrderBins; e += kBS) h[e] = 0;
+    __syncthreads();
+    if (c * 64 < nX) {
+        u32 imin = 0xFFFFFFFFu;
+        const int64_t e1 = min(c * 64 + 64, nX);
+        for (int64_t e = c * 64; e < e1; ++e) imin = min(imin, d.Xidx[e]);
+        const u32 bin = (u32)(((u64)imin * kOrderBins) / (u64)nX);
+        d.ckey[c] = chunk_key(d, c) | (bin << 16);
+        atomicAdd(&h[bin], 1u);
     }
-    const int64_t nvt = (a != 0 && d.yb->ok) ? (int64_t)d.yb_lsize[a] : (int64_t)d.yb->nt;
-    const int64_t groups = (nvt + 63) / 64;
-    d.ckey[c] = (uint16_t)a;
-    d.citems[c] = (u32)((groups + d.ngi - 1) / d.ngi);
+    __syncthreads();
+    for (int e = threadIdx.x; e < kOrderBins; e += kBS)
+        if (h[e]) atomicAdd(&d.kinfo[kKCount + e], h[e]);
 }
 
-// one block per segment: first work item of each chunk, the item count, and
-// the queue reset
-__global__ void __launch_bounds__(kBS) k_mp_scan(const StepDesc *descs, int nseg) {
-    __shared__ u32 wsum[kBS / 64];
-    const CONST_AS StepDesc &d = cref(descs + blockIdx.x);
-    if (d.meet_mode != 2) return;
+// one block per segment: exclusive scan of n[0 .. cnt) into out (n and out
+// may be the same array); returns the total
+__device__ u32 block_scan(const u32 *n, u32 *out, int64_t cnt, u32 *wsum) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t nX = d.nX >= 0 ? d.nX : (int64_t)d.res[0];
-    const int64_t nch = (nX + 63) / 64;
     u32 running = 0;
-    for (int64_t c0 = 0; c0 < nch; c0 += kBS) {
+    for (int64_t c0 = 0; c0 < cnt; c0 += kBS) {
         const int64_t c = c0 + tid;
-        const u32 v = c < nch ? d.citems[c] : 0u;
+        const u32 v = c < cnt ? n[c] : 0u;
         u32 incl = v;
 #pragma unroll
         for (int off = 1; off < 64; off <<= 1) {
@@ -1107,14 +1184,72 @@ __global__ void __launch_bounds__(kBS) k_mp_scan(const StepDesc *descs, int nseg
             if (w < wave) wpre += wsum[w];
             tot += wsum[w];
         }
-        if (c < nch) d.cpre[c] = running + wpre + incl - v;
+        if (c < cnt) out[c] = running + wpre + incl - v;
         running += tot;
         __syncthreads();
     }
-    if (tid == 0) {
-        if (nch > 0) d.cpre[nch] = running;
+    return running;
+}
+
+// one block per segment: the bins' insertion cursors
+__global__ void __launch_bounds__(kBS) k_mp_bins(const StepDesc *descs, int nseg) {
+    __shared__ u32 wsum[kBS / 64];
+    const CONST_AS StepDesc &d = cref(descs + blockIdx.x);
+    if (d.meet_mode != 2) return;
+    block_scan(d.kinfo + kKCount, d.kinfo + kKCur, kOrderBins, wsum);
+}
+
+// every chunk to a place of its bin in korder (any order within a bin)
+__global__ void __launch_bounds__(kBS) k_mp_scatter(const StepDesc *descs, const int64_t *pre, int nseg) {
+    __shared__ u32 h[kOrderBins];
+    __shared__ u32 base[kOrderBins];
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const CONST_AS StepDesc &d = cref(descs + s);
+    if (d.meet_mode != 2) return;
+    const int64_t c = ((int64_t)blockIdx.x - cref(pre + s)) * kBS + threadIdx.x;
+    const int64_t nX = d.nX >= 0 ? d.nX : (int64_t)d.res[0];
+    for (int e = threadIdx.x; e < kOrderBins; e += kBS) h[e] = 0;
+    __syncthreads();
+    const bool valid = c * 64 < nX;
+    u32 bin = 0, lpos = 0;
+    if (valid) {
+        bin = d.ckey[c] >> 16;
+        lpos = atomicAdd(&h[bin], 1u);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kOrderBins; e += kBS)
+        if (h[e]) base[e] = atomicAdd(&d.kinfo[kKCur + e], h[e]);
+    __syncthreads();
+    if (valid) d.korder[base[bin] + lpos] = (u32)c;
+}
+
+// per place in korder: the work items of its chunk (ranges of d.ngi tile
+// groups of the chunk's list; key 0 and lists that did not fit: every tile)
+__global__ void __launch_bounds__(kBS) k_mp_items(const StepDesc *descs, const int64_t *pre, int nseg) {
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const CONST_AS StepDesc &d = cref(descs + s);
+    if (d.meet_mode != 2) return;
+    const int64_t p = ((int64_t)blockIdx.x - cref(pre + s)) * kBS + threadIdx.x;
+    const int64_t nX = d.nX >= 0 ? d.nX : (int64_t)d.res[0];
+    if (p * 64 >= nX) return;
+    const u32 a = d.ckey[d.korder[p]] & 0xFFFFu;
+    const int64_t nvt = (a != 0 && d.yb->ok) ? (int64_t)d.yb_lsize[a] : (int64_t)d.yb->nt;
+    d.cpre[p] = (u32)(((nvt + 63) / 64 + d.ngi - 1) / d.ngi);
+}
+
+// one block per segment: first work item of each place, the item count,
+// and the queue reset
+__global__ void __launch_bounds__(kBS) k_mp_scan(const StepDesc *descs, int nseg) {
+    __shared__ u32 wsum[kBS / 64];
+    const CONST_AS StepDesc &d = cref(descs + blockIdx.x);
+    if (d.meet_mode != 2) return;
+    const int64_t nX = d.nX >= 0 ? d.nX : (int64_t)d.res[0];
+    const int64_t nch = (nX + 63) / 64;
+    const u32 total = block_scan(d.cpre, d.cpre, nch, wsum);
+    if (threadIdx.x == 0) {
+        d.cpre[nch] = total;
         d.queue[0] = 0;
-        d.queue[1] = running;
+        d.queue[1] = total;
     }
 }
 
@@ -1662,10 +1797,15 @@ hipError_t launch_meet(const StepDesc *d, const int64_t *pre, int s0, int s1, in
     if (items <= 0) return hipSuccess;
     const int64_t cap = max_grid > 0 ? std::min<int64_t>(max_grid, kMeetMaxGrid) : kMeetMaxGrid;
     const unsigned grid = (unsigned)(items < cap ? items : cap);
-    if (ys) {
-        SRW_SWITCH_W(W, hipLaunchKernelGGL((k_meet<W, true>), dim3(grid), dim3(kBS), 0, st, d, pre, s0, s1, ops));
+    // the counting kernels only when the operations are counted
+    if (ys && ops) {
+        SRW_SWITCH_W(W, hipLaunchKernelGGL((k_meet<W, true, true>), dim3(grid), dim3(kBS), 0, st, d, pre, s0, s1, ops));
+    } else if (ys) {
+        SRW_SWITCH_W(W, hipLaunchKernelGGL((k_meet<W, true, false>), dim3(grid), dim3(kBS), 0, st, d, pre, s0, s1, ops));
+    } else if (ops) {
+        SRW_SWITCH_W(W, hipLaunchKernelGGL((k_meet<W, false, true>), dim3(grid), dim3(kBS), 0, st, d, pre, s0, s1, ops));
     } else {
-        SRW_SWITCH_W(W, hipLaunchKernelGGL((k_meet<W, false>), dim3(grid), dim3(kBS), 0, st, d, pre, s0, s1, ops));
+        SRW_SWITCH_W(W, hipLaunchKernelGGL((k_meet<W, false, false>), dim3(grid), dim3(kBS), 0, st, d, pre, s0, s1, ops));
     }
     return launch_checked();
 }
@@ -1703,6 +1843,10 @@ hipError_t launch_ybin(const YbDesc *d, const int64_t *const pre[4], const int64
 // plan of the mode-2 meets: pre = blocks over chunks per segment
 hipError_t launch_meet_plan(const StepDesc *d, const int64_t *pre, int nseg, int64_t blocks, hipStream_t st) {
     if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mp_zero, dim3((unsigned)nseg), dim3(kBS), 0, st, d, nseg);
+    hipLaunchKernelGGL(k_mp_keys, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
+    hipLaunchKernelGGL(k_mp_bins, dim3((unsigned)nseg), dim3(kBS), 0, st, d, nseg);
+    hipLaunchKernelGGL(k_mp_scatter, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
     hipLaunchKernelGGL(k_mp_items, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
     hipLaunchKernelGGL(k_mp_scan, dim3((unsigned)nseg), dim3(kBS), 0, st, d, nseg);
     return launch_checked();
@@ -1710,7 +1854,11 @@ hipError_t launch_meet_plan(const StepDesc *d, const int64_t *pre, int nseg, int
 // mode-2 meets of segments s0..s1-1 (width W), `grid` blocks
 hipError_t launch_meet_b(const StepDesc *d, int s0, int s1, int W, int64_t grid, u64 *ops, hipStream_t st) {
     if (grid <= 0 || s1 <= s0) return hipSuccess;
-    SRW_SWITCH_W(W, hipLaunchKernelGGL(k_meet_b<W>, dim3((unsigned)grid), dim3(kBS), 0, st, d, s0, s1, ops));
+    if (ops) {
+        SRW_SWITCH_W(W, hipLaunchKernelGGL((k_meet_b<W, true>), dim3((unsigned)grid), dim3(kBS), 0, st, d, s0, s1, ops));
+    } else {
+        SRW_SWITCH_W(W, hipLaunchKernelGGL((k_meet_b<W, false>), dim3((unsigned)grid), dim3(kBS), 0, st, d, s0, s1, ops));
+    }
     return launch_checked();
 }
 

@@ -49,14 +49,17 @@ class Stats(ctypes.Structure):
                 ("bytes_compact", ctypes.c_int64), ("peak_device_bytes", ctypes.c_int64),
                 ("meet_launches_w", ctypes.c_int64 * 8), ("meet_ms_w", ctypes.c_double * 8),
                 ("pair_words_w", ctypes.c_int64 * 8), ("meet_ops_w", ctypes.c_int64 * 8),
-                ("host_ms", ctypes.c_double * 4)]
+                ("host_ms", ctypes.c_double * 4), ("meet_work", ctypes.c_int64 * 8)]
 
     def as_dict(self):
-        arrays = ("launches", "ms", "meet_launches_w", "meet_ms_w", "pair_words_w", "meet_ops_w", "host_ms")
+        arrays = ("launches", "ms", "meet_launches_w", "meet_ms_w", "pair_words_w", "meet_ops_w", "host_ms",
+                  "meet_work")
         d = {f: getattr(self, f) for f, _ in self._fields_ if f not in arrays}
         d["launches"] = dict(zip(KERNEL_CLASSES, list(self.launches)))
         d["ms"] = dict(zip(KERNEL_CLASSES, list(self.ms)))
         d["host_ms"] = dict(zip(("prepare", "launch", "wait", "results"), list(self.host_ms)))
+        d["meet_work"] = dict(zip(("items", "groups", "groups_with_candidates", "candidates",
+                                   "signature_passes", "column_tiles", "tiles"), list(self.meet_work)))
         d["meet_w"] = {w + 1: {"launches": self.meet_launches_w[w], "ms": self.meet_ms_w[w],
                                "pair_words": self.pair_words_w[w], "ops": self.meet_ops_w[w]}
                        for w in range(8) if self.meet_launches_w[w]}

@@ -302,7 +302,9 @@ def roofline(stats, cls_stats, workload):
         mc = cls_stats.get("meet_w", {}).get(W, m)
         ops = mc["ops"] / max(1, mc["launches"])
         ach = ops / t / 1e12
-        name = f"k_meet<{W}>"
+        # the meet against inverse levels in buckets is its own kernel
+        bucketed = cls_stats.get("meet_work", {}).get("bucketed_launches", 0) > 0
+        name = f"k_meet_b<{W}, false>" if bucketed else f"k_meet<{W}, false, false>"
         return {"kernel": name, "bound": "alu", "achieved": ach, "peak": VALU_PEAK_TOPS,
                 "unit": "TOP/s", "frac": ach / VALU_PEAK_TOPS,
                 "traffic": measured_traffic(workload, name),

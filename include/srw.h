@@ -231,7 +231,8 @@ typedef struct srw_stats {
                                   1 tile groups scanned, 2 groups with candidate sets,
                                   3 candidates tested by signature, 4 signature passes
                                   (full row tests), 5 tiles tested column by column,
-                                  6 tiles scanned, 7 unused */
+                                  6 tiles scanned; 7 launches of the meet against an
+                                  inverse level in buckets (counted always) */
 } srw_stats;
 /* kernel classes: 0 expand (and whole one-block steps), 1 insert, 2 count+scan+compact, 3 meet
  * preparation (transpose of inverse levels, bucket sort of forward levels),

@@ -56,11 +56,16 @@ constexpr int kYBits = 10;
 constexpr int kYBins = 1 << kYBits;
 constexpr int64_t kYMin = 16384;          // default: inverse levels at least this large are bucketed
 constexpr int64_t kYListPerTile = 32;     // room for list entries per tile of the level
-// a bucketed meet's plan: chunks are taken in order of their least index in
-// the level, by kOrderBins bins of that index (the least meeting pair is
-// sought, so that a pair found early lets the chunks of larger index stop)
-constexpr int kOrderBins = 1024;
-constexpr int kKCount = 0, kKCur = kOrderBins, kKInfoWords = 2 * kOrderBins;
+// A bucketed meet's plan orders its work items by an order key per chunk:
+// first by kIndexBins bins of the chunk's least index in the forward level
+// (the least meeting pair is sought, so a pair found early lets the chunks
+// of larger index stop), then by the chunk's bucket key, then tile range by
+// tile range of that key's list, and within a range chunk by chunk (the
+// waves in flight read the same tiles, which then come from the cache).
+constexpr int kIndexBins = 16;
+constexpr int kOrderKeys = kIndexBins * kYBins;
+constexpr int kKCount = 0, kKStart = kOrderKeys, kKRanges = 2 * kOrderKeys, kKPre = 3 * kOrderKeys,
+              kKCur = 4 * kOrderKeys + 1, kKInfoWords = 5 * kOrderKeys + 1;
 
 struct YbMeta {
     int32_t nt;                 // tiles of the padded level
@@ -144,10 +149,10 @@ struct StepDesc {
     // the work items (one chunk, a range of its tiles) taken from a queue
     const YbMeta *yb;
     const u32 *yb_lsize, *yb_loff, *yb_list;
-    u32 *ckey;                 // per chunk: its key | (its order bin << 16)
-    u32 *korder;               // the chunks in order of their least index in the level
-    u32 *cpre;                 // per place in korder: its first work item (then the count)
-    u32 *kinfo;                // per order bin: chunks, insertion cursor
+    u32 *ckey;                 // per chunk: its order key (see kOrderKeys)
+    u32 *korder;               // the chunks in order of their order keys
+    u32 *kinfo;                // per order key: chunks, first place in korder, tile
+                               // ranges, first work item (kOrderKeys + 1), cursor
     u32 *queue;                // [0] next work item, [1] work items
     // transpose of a new inverse level into YT
     int64_t ntr_waves;         // upper bound of (tile, word) waves

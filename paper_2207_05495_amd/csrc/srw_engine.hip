@@ -521,7 +521,7 @@ class Engine {
                 for (int sl = 0; sl < kOpsSlots; ++sl)
                     out.meet_ops_w[w] += (int64_t)h[((int64_t)w * kOpsSlots + sl) * kOpsStride];
             }
-            for (int c = 0; c < kMstatCounters; ++c) {
+            for (int c = 0; c < kMstatCounters - 1; ++c) {   // [7] is counted on the host
                 out.meet_work[c] = 0;
                 for (int sl = 0; sl < kMstatSlots; ++sl) out.meet_work[c] += (int64_t)h[kOpsWords + sl * kOpsStride + c];
             }
@@ -898,7 +898,6 @@ class Engine {
                 d.Yidx = p->yb_idx;
                 d.ckey = p->mp_key;
                 d.korder = p->mp_order;
-                d.cpre = p->mp_cpre;
                 d.kinfo = p->mp_kinfo;
                 d.queue = p->mp_queue;
             }
@@ -1062,9 +1061,11 @@ class Engine {
                 for (int i = s0; i < s1; ++i) ys = ys || (D[i].meet_mode != 2 && D[i].Yidx != nullptr);
                 HIPCHK(launch_meet(dD, dpm, s0, s1, W, pm[s1] - pm[s0], opt.meet_grid, ys, ops, stream_));
             }
-            if (bk_items > 0)
+            if (bk_items > 0) {
                 HIPCHK(launch_meet_b(dD, s0, s1, W, std::min<int64_t>(ceil_div(bk_items, kBS / 64), kMeetQueueGrid),
                                      ops, stream_));
+                stats_.meet_work[7]++;
+            }
             if (opt.profile) HIPCHK(hipEventRecord(ev_meet_[2 * (W - 1) + 1], stream_));
             stats_.meet_launches_w[W - 1]++;
             s0 = s1;

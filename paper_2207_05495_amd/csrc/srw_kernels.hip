@@ -882,9 +882,9 @@ __global__ void __launch_bounds__(kBS) k_meet(const StepDesc *descs, const int64
 
 // Mode 2: waves take work items from each segment's queue in turn, until
 // the queue is empty (its counter passes the item count the plan wrote),
-// so every wave of the grid ends.  Work items go chunk by chunk in the
-// plan's order (least index in the level first), each a range of d.ngi
-// tile groups of the chunk's list.
+// so every wave of the grid ends.  Work items go in the plan's order (see
+// kOrderKeys): per order key, range by range of d.ngi tile groups of the
+// key's list, and within a range chunk by chunk.
 template <int W, bool CNT>
 __global__ void __launch_bounds__(kBS) k_meet_b(const StepDesc *descs, int s0, int s1, u64 *ops) {
     __shared__ u64 cols[kMeetLdsWords];
@@ -905,12 +905,18 @@ __global__ void __launch_bounds__(kBS) k_meet_b(const StepDesc *descs, int s0, i
             if (lane == 0) it = atomicAdd(d.queue, 1u);
             it = __builtin_amdgcn_readfirstlane(__shfl((int)it, 0, 64));
             if (it >= total) break;
-            u32 lo = 0, hi = nch;                  // cpre[lo] <= it < cpre[hi]
+            const u32 *kpre = d.kinfo + kKPre;
+            u32 lo = 0, hi = kOrderKeys;           // kpre[lo] <= it < kpre[hi]
             while (hi - lo > 1) {
                 const u32 mid = (lo + hi) >> 1;
-                if (d.cpre[mid] <= it) lo = mid; else hi = mid;
+                if (kpre[mid] <= it) lo = mid; else hi = mid;
             }
-            nops += meet_chunk_core<W, true, true, CNT>(d, d.korder[lo], it - d.cpre[lo], slice);
+            const u32 cnt = d.kinfo[kKCount + lo];   // chunks of order key lo (> 0: it has items)
+            const u32 rem = it - kpre[lo];
+            const u32 r = rem / cnt;
+            const u32 c = d.korder[d.kinfo[kKStart + lo] + (rem - r * cnt)];
+            (void)nch;
+            nops += meet_chunk_core<W, true, true, CNT>(d, c, r, slice);
         }
     }
     if (ops) {
@@ -1131,35 +1137,29 @@ __device__ __forceinline__ u32 chunk_key(const D &d, int64_t c) {
     return a;
 }
 
-// one block per segment: clear the order bins
+// one block per segment: clear the chunk counts of the order keys
 __global__ void __launch_bounds__(kBS) k_mp_zero(const StepDesc *descs, int nseg) {
     const CONST_AS StepDesc &d = cref(descs + blockIdx.x);
     if (d.meet_mode != 2) return;
-    for (int e = threadIdx.x; e < kOrderBins; e += kBS) d.kinfo[kKCount + e] = 0;
+    for (int e = threadIdx.x; e < kOrderKeys; e += kBS) d.kinfo[kKCount + e] = 0;
 }
 
-// per chunk: its key and its order bin (of its least index in the level),
-// counted per bin
+// per chunk: its order key (index bin of its least index in the level,
+// then its bucket key), counted per order key
 __global__ void __launch_bounds__(kBS) k_mp_keys(const StepDesc *descs, const int64_t *pre, int nseg) {
-    __shared__ u32 h[kOrderBins];
     const int s = find_seg(pre, nseg, blockIdx.x);
     const CONST_AS StepDesc &d = cref(descs + s);
     if (d.meet_mode != 2) return;
     const int64_t c = ((int64_t)blockIdx.x - cref(pre + s)) * kBS + threadIdx.x;
     const int64_t nX = d.nX >= 0 ? d.nX : (int64_t)d.res[0];
-    for (int e = threadIdx.x; e < kOrderBins; e += kBS) h[e] = 0;
-    __syncthreads();
-    if (c * 64 < nX) {
-        u32 imin = 0xFFFFFFFFu;
-        const int64_t e1 = min(c * 64 + 64, nX);
-        for (int64_t e = c * 64; e < e1; ++e) imin = min(imin, d.Xidx[e]);
-        const u32 bin = (u32)(((u64)imin * kOrderBins) / (u64)nX);
-        d.ckey[c] = chunk_key(d, c) | (bin << 16);
-        atomicAdd(&h[bin], 1u);
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < kOrderBins; e += kBS)
-        if (h[e]) atomicAdd(&d.kinfo[kKCount + e], h[e]);
+    if (c * 64 >= nX) return;
+    u32 imin = 0xFFFFFFFFu;
+    const int64_t e1 = min(c * 64 + 64, nX);
+    for (int64_t e = c * 64; e < e1; ++e) imin = min(imin, d.Xidx[e]);
+    const u32 bin = (u32)(((u64)imin * kIndexBins) / (u64)nX);
+    const u32 ok = bin * kYBins + chunk_key(d, c);
+    d.ckey[c] = ok;
+    atomicAdd(&d.kinfo[kKCount + ok], 1u);
 }
 
 // one block per segment: exclusive scan of n[0 .. cnt) into out (n and out
@@ -1191,66 +1191,42 @@ __device__ u32 block_scan(const u32 *n, u32 *out, int64_t cnt, u32 *wsum) {
     return running;
 }
 
-// one block per segment: the bins' insertion cursors
-__global__ void __launch_bounds__(kBS) k_mp_bins(const StepDesc *descs, int nseg) {
+// one block per segment: per order key its tile ranges (of d.ngi groups of
+// its bucket key's list; key 0 and lists that did not fit: every tile) and
+// work items, then its first place in korder and first work item, the item
+// count and the queue reset
+__global__ void __launch_bounds__(kBS) k_mp_scan(const StepDesc *descs, int nseg) {
     __shared__ u32 wsum[kBS / 64];
     const CONST_AS StepDesc &d = cref(descs + blockIdx.x);
     if (d.meet_mode != 2) return;
-    block_scan(d.kinfo + kKCount, d.kinfo + kKCur, kOrderBins, wsum);
+    for (int e = threadIdx.x; e < kOrderKeys; e += kBS) {
+        const u32 cnt = d.kinfo[kKCount + e];
+        const u32 a = (u32)e % kYBins;
+        const int64_t nvt = (a != 0 && d.yb->ok) ? (int64_t)d.yb_lsize[a] : (int64_t)d.yb->nt;
+        const u32 ranges = cnt ? (u32)(((nvt + 63) / 64 + d.ngi - 1) / d.ngi) : 0u;
+        d.kinfo[kKRanges + e] = ranges;
+        d.kinfo[kKCur + e] = cnt * ranges;        // work items, scanned below
+    }
+    __syncthreads();
+    block_scan(d.kinfo + kKCount, d.kinfo + kKStart, kOrderKeys, wsum);
+    const u32 total = block_scan(d.kinfo + kKCur, d.kinfo + kKPre, kOrderKeys, wsum);
+    for (int e = threadIdx.x; e < kOrderKeys; e += kBS) d.kinfo[kKCur + e] = d.kinfo[kKStart + e];
+    if (threadIdx.x == 0) {
+        d.kinfo[kKPre + kOrderKeys] = total;
+        d.queue[0] = 0;
+        d.queue[1] = total;
+    }
 }
 
-// every chunk to a place of its bin in korder (any order within a bin)
+// every chunk to a place of its order key in korder (any order within a key)
 __global__ void __launch_bounds__(kBS) k_mp_scatter(const StepDesc *descs, const int64_t *pre, int nseg) {
-    __shared__ u32 h[kOrderBins];
-    __shared__ u32 base[kOrderBins];
     const int s = find_seg(pre, nseg, blockIdx.x);
     const CONST_AS StepDesc &d = cref(descs + s);
     if (d.meet_mode != 2) return;
     const int64_t c = ((int64_t)blockIdx.x - cref(pre + s)) * kBS + threadIdx.x;
     const int64_t nX = d.nX >= 0 ? d.nX : (int64_t)d.res[0];
-    for (int e = threadIdx.x; e < kOrderBins; e += kBS) h[e] = 0;
-    __syncthreads();
-    const bool valid = c * 64 < nX;
-    u32 bin = 0, lpos = 0;
-    if (valid) {
-        bin = d.ckey[c] >> 16;
-        lpos = atomicAdd(&h[bin], 1u);
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < kOrderBins; e += kBS)
-        if (h[e]) base[e] = atomicAdd(&d.kinfo[kKCur + e], h[e]);
-    __syncthreads();
-    if (valid) d.korder[base[bin] + lpos] = (u32)c;
-}
-
-// per place in korder: the work items of its chunk (ranges of d.ngi tile
-// groups of the chunk's list; key 0 and lists that did not fit: every tile)
-__global__ void __launch_bounds__(kBS) k_mp_items(const StepDesc *descs, const int64_t *pre, int nseg) {
-    const int s = find_seg(pre, nseg, blockIdx.x);
-    const CONST_AS StepDesc &d = cref(descs + s);
-    if (d.meet_mode != 2) return;
-    const int64_t p = ((int64_t)blockIdx.x - cref(pre + s)) * kBS + threadIdx.x;
-    const int64_t nX = d.nX >= 0 ? d.nX : (int64_t)d.res[0];
-    if (p * 64 >= nX) return;
-    const u32 a = d.ckey[d.korder[p]] & 0xFFFFu;
-    const int64_t nvt = (a != 0 && d.yb->ok) ? (int64_t)d.yb_lsize[a] : (int64_t)d.yb->nt;
-    d.cpre[p] = (u32)(((nvt + 63) / 64 + d.ngi - 1) / d.ngi);
-}
-
-// one block per segment: first work item of each place, the item count,
-// and the queue reset
-__global__ void __launch_bounds__(kBS) k_mp_scan(const StepDesc *descs, int nseg) {
-    __shared__ u32 wsum[kBS / 64];
-    const CONST_AS StepDesc &d = cref(descs + blockIdx.x);
-    if (d.meet_mode != 2) return;
-    const int64_t nX = d.nX >= 0 ? d.nX : (int64_t)d.res[0];
-    const int64_t nch = (nX + 63) / 64;
-    const u32 total = block_scan(d.cpre, d.cpre, nch, wsum);
-    if (threadIdx.x == 0) {
-        d.cpre[nch] = total;
-        d.queue[0] = 0;
-        d.queue[1] = total;
-    }
+    if (c * 64 >= nX) return;
+    d.korder[atomicAdd(&d.kinfo[kKCur + d.ckey[c]], 1u)] = (u32)c;
 }
 
 // ------------------------------------------------------ copies
@@ -1845,10 +1821,8 @@ hipError_t launch_meet_plan(const StepDesc *d, const int64_t *pre, int nseg, int
     if (blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_mp_zero, dim3((unsigned)nseg), dim3(kBS), 0, st, d, nseg);
     hipLaunchKernelGGL(k_mp_keys, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
-    hipLaunchKernelGGL(k_mp_bins, dim3((unsigned)nseg), dim3(kBS), 0, st, d, nseg);
-    hipLaunchKernelGGL(k_mp_scatter, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
-    hipLaunchKernelGGL(k_mp_items, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
     hipLaunchKernelGGL(k_mp_scan, dim3((unsigned)nseg), dim3(kBS), 0, st, d, nseg);
+    hipLaunchKernelGGL(k_mp_scatter, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
     return launch_checked();
 }
 // mode-2 meets of segments s0..s1-1 (width W), `grid` blocks

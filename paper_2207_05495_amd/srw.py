@@ -59,7 +59,8 @@ class Stats(ctypes.Structure):
         d["ms"] = dict(zip(KERNEL_CLASSES, list(self.ms)))
         d["host_ms"] = dict(zip(("prepare", "launch", "wait", "results"), list(self.host_ms)))
         d["meet_work"] = dict(zip(("items", "groups", "groups_with_candidates", "candidates",
-                                   "signature_passes", "column_tiles", "tiles"), list(self.meet_work)))
+                                   "signature_passes", "column_tiles", "tiles", "bucketed_launches"),
+                                  list(self.meet_work)))
         d["meet_w"] = {w + 1: {"launches": self.meet_launches_w[w], "ms": self.meet_ms_w[w],
                                "pair_words": self.pair_words_w[w], "ops": self.meet_ops_w[w]}
                        for w in range(8) if self.meet_launches_w[w]}

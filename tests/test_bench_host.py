@@ -37,7 +37,7 @@ def cls_stats(ms, launches, **extra):
 
 
 def test_roofline_of_the_meet_uses_the_widest_time_width(monkeypatch):
-    monkeypatch.setattr(bench, "measured_traffic", lambda w, k: 123.0 if k == "k_meet<4>" else None)
+    monkeypatch.setattr(bench, "measured_traffic", lambda w, k: 123.0 if k == "k_meet<4, false, false>" else None)
     # timed region: launch times (the lean kernels count nothing); the extra
     # pass with the counting kernels: the set operations (here 5 launches)
     stats = {"meet_w": {1: {"ms": 2.0, "launches": 10, "ops": 0, "pair_words": 1e9},
@@ -46,7 +46,7 @@ def test_roofline_of_the_meet_uses_the_widest_time_width(monkeypatch):
                4: {"ms": 26.0, "launches": 5, "ops": 1e12, "pair_words": 2.5e12}}
     r = bench.roofline(stats, cls_stats({"meet": 60.0, "expand": 5.0}, {"meet": 20, "expand": 40},
                                         meet_w=counted), "wl")
-    assert r["kernel"] == "k_meet<4>" and r["bound"] == "alu" and r["unit"] == "TOP/s"
+    assert r["kernel"] == "k_meet<4, false, false>" and r["bound"] == "alu" and r["unit"] == "TOP/s"
     # 2e11 lane-ops per launch in 5 ms: 40 T lane-ops/s
     assert r["achieved"] == pytest.approx(40.0)
     assert r["peak"] == pytest.approx(256 * 64 * 2.4e9 / 1e12)

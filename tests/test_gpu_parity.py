@@ -737,6 +737,27 @@ def test_mixed_batch_members_against_stored_oracle_values():
         assert "".join(map(str, w)) == c["word"], (c["n"], c["k"], c["seed"])
 
 
+@pytest.mark.parametrize("k", [2, 3])
+def test_mixed_batch_larger_members_against_stored_oracle_values(k):
+    """The members with n > 160 among the first 300 of the seeded 4096-member
+    batch that the oracle finished within 300 s each (tests/golden/
+    mix4096big.json: every k = 2 member up to n = 320 but two, the k = 3 ones
+    up to n = 256), solved together in one batch per alphabet size: r and
+    word equal the oracle's stored values.  The others are parity
+    unpinned."""
+    path = os.path.join(GOLDEN, "mix4096big.json")
+    if not os.path.exists(path):
+        pytest.skip("no stored oracle values for the larger members")
+    cs = [c for c in golden("mix4096big.json") if "r" in c and c["k"] == k]
+    probs = [(c["n"], c["k"], I.random_automaton(c["n"], c["k"], c["seed"], c["attempt"]))
+             for c in cs]
+    say("mix4096 larger members, k =", k, len(probs))
+    res = srw.solve_batch(probs)
+    for c, (st, r, w) in zip(cs, res):
+        assert st == srw.OK and r == c["r"], (c["n"], c["k"], c["seed"])
+        assert "".join(map(str, w)) == c["word"], (c["n"], c["k"], c["seed"])
+
+
 def test_server_deadline_then_recovery():
     """A server with a 1 ms per-request deadline ends two Černý C_40 solves
     (1,521 steps each) with ETIMEOUT and returns both; a server without a

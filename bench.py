@@ -406,11 +406,21 @@ def serve_bench(args, srw):
     lat = np.array([x["latency_ms"] for x in ok]) if ok else np.zeros(1)
     per = {}
     for cls in sorted({r[3] for r in reqs}):
-        ls = [done[i]["latency_ms"] for i, r in enumerate(reqs) if r[3] == cls and i in done
-              and done[i]["status"] == srw.OK]
+        idx = [i for i, r in enumerate(reqs) if r[3] == cls]
+        fin = [done[i] for i in idx if i in done]
+        ls = [x["latency_ms"] for x in fin if x["status"] == srw.OK]
+        ent = {"requests": len(idx), "unfinished": len(idx) - len(fin),
+               "status_counts": {srw.STATUS_NAMES.get(st, st): sum(1 for x in fin if x["status"] == st)
+                                 for st in sorted({x["status"] for x in fin})}}
         if ls:
-            per[cls] = {"n": len(ls), "p50_ms": float(np.percentile(ls, 50)),
-                        "p99_ms": float(np.percentile(ls, 99))}
+            ent.update({"p50_ms": float(np.percentile(ls, 50)), "p99_ms": float(np.percentile(ls, 99))})
+        # the admission estimate against the device memory the solve held
+        ratio = [x["dev_bytes"] / x["est_bytes"] for x in fin
+                 if x["status"] == srw.OK and x["est_bytes"] > 0 and x["dev_bytes"] > 0]
+        if ratio:
+            ent["dev_over_estimate"] = {"p50": float(np.percentile(ratio, 50)),
+                                        "min": float(min(ratio)), "max": float(max(ratio))}
+        per[cls] = ent
     return {
         "metric": "subsets expanded/s + automata solved/s (batched vs plain, 1 GPU), p99 latency",
         "value": len(ok) / elapsed, "unit": "automata solved/s",
@@ -498,6 +508,14 @@ def batched_vs_plain(args, srw, stored):
             "oracle_checked": checked}
 
 
+def tuning_note(tuned):
+    """The autotuner's values in force ({W: {key: value}}), or None."""
+    if not tuned:
+        return None
+    return {"table": "paper_2207_05495_amd/tuning.json",
+            "per_width": {str(w): v for w, v in sorted(tuned.items())}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -511,6 +529,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain comparison")
     ap.add_argument("--set", action="append", default=[], metavar="KEY=VALUE",
                     help="library option (srw_set_option) for the whole run; repeatable")
+    ap.add_argument("--no-tuning", action="store_true",
+                    help="leave out the autotuner's per-width table (paper_2207_05495_amd/tuning.json); "
+                         "its values take precedence over --set values of the same keys")
     ap.add_argument("--cpu-budget", type=float, default=40.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -559,7 +580,10 @@ def main():
         import torch
         torch.cuda.set_device(0)
         srw.use_torch(0)
-        print(json.dumps(serve_bench(args, srw)))
+        tuned = {} if args.no_tuning else srw.apply_tuning()
+        out = serve_bench(args, srw)
+        out["config"]["tuning"] = tuning_note(tuned)
+        print(json.dumps(out))
         return
     probs = workload(args.workload, srw, args.count, args.nmax)   # host-only calls so far
     stored = stored_oracle_values()
@@ -571,6 +595,7 @@ def main():
     import torch
     torch.cuda.set_device(0)
     srw.use_torch(0)
+    tuned = {} if args.no_tuning else srw.apply_tuning()
     for kv in args.set:
         key, val = kv.split("=", 1)
         srw.set_option(key, int(val))
@@ -639,7 +664,8 @@ def main():
                        "sink26-k25": "Rystsov's sink series, n=26 k=25 (r=325)"}[args.workload]
                    + ("" if args.workload.startswith("sink") else
                       " (uniform delta, seeded SplitMix64, first synchronizing draw)"),
-                   "path": "srw_solve_batch"},
+                   "path": "srw_solve_batch",
+                   "tuning": tuning_note(tuned)},
         "automata_per_s": len(probs) / per_step,
         "step_p50_ms": float(np.percentile(step_ms, 50)),
         "step_p99_ms": float(np.percentile(step_ms, 99)),

@@ -117,6 +117,8 @@ typedef struct srw_result {
     const uint8_t *word;   /* r letters, owned by the server until the next poll */
     double latency_ms;     /* submit -> completion */
     double queue_ms;       /* submit -> admission to the device */
+    int64_t est_bytes;     /* the footprint estimate admission used */
+    int64_t dev_bytes;     /* device memory its buffers held at the end (0 if never admitted) */
 } srw_result;
 
 typedef struct srw_server srw_server;
@@ -124,7 +126,10 @@ typedef struct srw_server srw_server;
 /* Start a server with its own worker thread and stream.  Requests are
  * admitted while their estimated device footprint fits the budget and a
  * slot is free; admitted automata keep their lists on the device and step
- * together with the rest. */
+ * together with the rest.  The server searches with the options of the
+ * default context (srw_set_option) as they are at this call, per-width
+ * values included; "budget", "max_slots", "profile", "deadline_ms",
+ * "verbose" and "keep_levels" are not taken (cfg holds the server's own). */
 int srw_server_create(srw_server **out, const srw_config *cfg);
 /* Non-blocking.  Copies delta.  Results come back through srw_server_poll. */
 int srw_server_submit(srw_server *s, int32_t n, int32_t k, const int32_t *delta, uint64_t tag);
@@ -159,6 +164,14 @@ int srw_set_stream(void *hip_stream);
  *   "schedule"    0: smaller frontier first, ties forward (default)
  *                 1: pseudo-random side per step from "sched_seed"
  *                 2: alternate forward / inverse
+ *                 3: the step of lower estimated cost, BFS or IBFS, by the
+ *                 cost model of Section 2.1.2 (Eq. 1-4 with ExpMark; the
+ *                 terms of inclusion reductions, which this search does not
+ *                 make, are zero, and there is no step without history and
+ *                 no DFS phase, so the paper's greedy comparison of the two
+ *                 single-step costs applies).  The first, small steps that
+ *                 "persist" runs in one launch keep the rule of schedule 0.
+ *                 Every schedule gives the same r and word
  *   "sched_seed"  seed of schedule 1
  *   "meet"        0: auto; 1: always test 256 sets X against LDS-staged
  *                 tiles of 64 sets Y; 2: bucket-sort every forward level
@@ -174,6 +187,10 @@ int srw_set_stream(void *hip_stream);
  *                 range-major (consecutive items share one range of tiles;
  *                 with an inverse level in buckets: within each key of the
  *                 chunks)
+ *   "meet_xcd"    bucketed meet: its work items are dealt to eight queues,
+ *                 one per XCD, in runs of this many consecutive items, so
+ *                 that the chunks scanning one range of tiles share an L2
+ *                 (0, the default: one queue)
  *   "meet_grid"   meet blocks per launch, grid-striding over the work items
  *                 (0: one block per work item, up to 2^31-1)
  *   "ysort"       new inverse levels of at least this many candidates are
@@ -195,6 +212,11 @@ int srw_set_stream(void *hip_stream);
  *                 sense of "small_cand" (with the schedule 0 side rule);
  *                 0: every step is launched by the host.  The same
  *                 results either way
+ *   "<key>@<W>"   a value of "meet_groups", "meet_rows", "small_cand",
+ *                 "bucket" or "schedule" for automata of set width W only
+ *                 (W = ceil(n/64) = 1..8; -1 removes it), e.g. from the
+ *                 autotuner's table; it takes precedence over the key's
+ *                 value for every width
  *   "deadline_ms" per automaton, from its admission: a solve still running
  *                 after this long ends with SRW_ETIMEOUT (0: no deadline)
  *   "verbose"     1: one line per step of a single solve on stderr
@@ -249,6 +271,12 @@ int srw_reset_stats(void);
  * a*|previous level|+i; 0xFFFFFFFF on level 0). */
 int srw_last_levels(int32_t side, int32_t *nlev, int64_t *nrows,
                     int64_t *off, uint64_t *rows, uint32_t *par);
+
+/* The side of every step of the last srw_solve run with "keep_levels" on,
+ * in order (0 forward, 1 inverse): *steps = their count; with sides != NULL
+ * also sides[0..*steps) (SRW_EINVAL when cap < *steps).  A test and
+ * diagnostic hook for the direction schedules. */
+int srw_last_sides(int32_t *steps, uint8_t *sides, int64_t cap);
 
 /* Text of the last error of the calling thread. */
 const char *srw_last_error(void);

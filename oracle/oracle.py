@@ -232,6 +232,28 @@ def bidir_steps(n, k, delta, max_steps, meet=MEET_MARK):
     return rc == OK, dict(zip(STAT_NAMES, (int(x) for x in stats)))
 
 
+def levels_after(n, k, delta, sched):
+    """The lists of the plain bidirectional search after the steps `sched`
+    (0 forward, 1 inverse), or fewer if the searches meet first.  Returns
+    (met, levels): met is True when the meet test succeeded after the steps
+    taken; levels[side] is a list of (rows, parent keys) per level."""
+    d = _delta(delta)
+    r = ctypes.c_int32(-1)
+    s = np.ascontiguousarray(np.asarray(list(sched) + [0], dtype=np.uint8))
+    stats = np.zeros(len(STAT_NAMES), dtype=np.int64)
+    h = ctypes.c_void_p(None)
+    rc = lib().orc_bidir(n, k, _ptr(d, ctypes.c_int32), MEET_MARK, _ptr(s, ctypes.c_uint8),
+                         len(sched), len(sched), ctypes.byref(r), None, 0, None,
+                         _ptr(stats, ctypes.c_int64), ctypes.byref(h))
+    if rc not in (OK, ELIMIT):
+        raise OracleError(rc, "levels_after")
+    try:
+        levels = [_levels(h, side, _words(n)) for side in (0, 1)]
+    finally:
+        lib().orc_free(h)
+    return rc == OK, levels
+
+
 def _levels(h, side, W):
     L = lib()
     nlev = ctypes.c_int32(0)

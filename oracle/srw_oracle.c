@@ -868,7 +868,8 @@ static int bidir_impl(int n, int k, const int32_t *delta, int meet_mode,
         stats_out[7] = run->pairs;
         stats_out[8] = run->reduce_tests;
     }
-    if (handle_out && out == ORC_OK) {
+    if (handle_out && (out == ORC_OK || out == ORC_ELIMIT)) {
+        /* also the lists of a search stopped at its step limit */
         *handle_out = run;
     } else {
         side_free(&run->F); side_free(&run->B); free(run);

@@ -145,6 +145,8 @@ struct StepDesc {
     int64_t row_batch_max;     // mode 1: more candidates per group than this: column chains
     int64_t nch_ub;            // mode 1: chunks (upper bound)
     int64_t item_order;        // mode 1: 0 tile-range-major items, 1 chunk-major
+    int64_t xcd_granule;       // mode 2: runs of this many consecutive work items go to
+                               // one XCD's queue, round robin (0: one queue for all)
     // mode 2 (bucketed meet): the inverse level in buckets, and the plan of
     // the work items (one chunk, a range of its tiles) taken from a queue
     const YbMeta *yb;
@@ -153,10 +155,13 @@ struct StepDesc {
     u32 *korder;               // the chunks in order of their order keys
     u32 *kinfo;                // per order key: chunks, first place in korder, tile
                                // ranges, first work item (kOrderKeys + 1), cursor
-    u32 *queue;                // [0] next work item, [1] work items
+    u32 *queue;                // [0] next work item, [1] work items, [2 + x] next
+                               // item of XCD x's queue (with xcd_granule)
     // transpose of a new inverse level into YT
     int64_t ntr_waves;         // upper bound of (tile, word) waves
-    // results: res[0] = new level size, res[1] = least (i << 32 | j) meeting pair
+    // results: res[0] = new level size, res[1] = least (i << 32 | j) meeting
+    // pair, res[2] = sum of the cardinalities of the new level's sets (its
+    // density times n times its size); kResWords words per segment
     u64 *res;
     // chunked meets, when profiling: kMstatSlots slots of kMstatCounters
     // counters (kOpsStride words apart), see srw_stats.meet_work
@@ -187,14 +192,18 @@ struct RunDesc {
     int64_t max_ticks;         // stop after this many wall_clock64 ticks (0: no limit)
     RunState *st;
 };
+constexpr int kResWords = 4;             // step result words per segment
+constexpr int kRunSideWords = 128;       // step sides a runner records (bits)
 struct RunState {
     int64_t nrows[2];          // in/out: rows stored per side
     int32_t nlev[2];           // in/out: levels per side (level 0 included)
     int32_t status;            // out: 0 the next step is not small, 1 met, 2 a list became empty
     int32_t steps;             // out: steps run here
     u64 best;                  // out: the least meeting pair (i << 32 | j), when met
-    u64 res[2];                // step results (new level size, meeting pair)
+    u64 res[kResWords];        // step results (as StepDesc::res)
     int64_t candidates, unique, pairs;   // out: over the steps run here
+    u64 popsum[2];             // in/out: sum of the cardinalities of each side's current level
+    u64 sides[kRunSideWords];  // out: bit t = side of step t (steps beyond 64 * kRunSideWords unrecorded)
 };
 
 constexpr int kKeyBits = 16;             // sort key: the 16 most frequent states

@@ -179,6 +179,9 @@ class Pool {
         const int c = cls_of(bytes);
         const size_t size = (size_t)256 << c;
         if (!free_[c].empty()) {
+            // a cached block counts against the budget as well (it may have
+            // been cut since the block was reserved)
+            if (in_use_ + (int64_t)size > budget_ - (internal ? 0 : reserve())) return nullptr;
             void *p = free_[c].back();
             free_[c].pop_back();
             account(size);
@@ -222,9 +225,17 @@ class Pool {
     }
     int64_t reserved() const { return reserved_; }
     int64_t in_use() const { return in_use_; }
+    // bytes of the pool block at p (0 for NULL or a foreign pointer)
+    int64_t size_of(const void *p) const {
+        auto it = cls_.find(const_cast<void *>(p));
+        return it == cls_.end() ? 0 : (int64_t)256 << it->second;
+    }
     int64_t peak() const { return peak_; }
     int64_t budget() const { return budget_; }
-    void set_budget(int64_t b) { budget_ = b; }
+    void set_budget(int64_t b) {
+        budget_ = b;
+        if (reserved_ > budget_) trim();   // cached blocks beyond a cut budget go back
+    }
     // bytes of the budget kept for the engine's own per-step buffers
     int64_t reserve() const { return std::min<int64_t>(kReserve, budget_ / 4); }
     // slabs of at most 64 MiB, and at most an eighth of the budget (a small
@@ -371,9 +382,11 @@ struct SideState {
     int64_t tab_cap = 0;     // slots (power of two)
     int64_t nrows = 0;
     std::vector<int64_t> off;  // level L: rows off[L] .. off[L+1]-1
+    u64 popsum = 0;            // sum of the cardinalities of the current level's sets
     int nlev() const { return (int)off.size() - 1; }
     int64_t cur() const { return off[off.size() - 1] - off[off.size() - 2]; }
     int64_t cur_start() const { return off[off.size() - 2]; }
+    int64_t prev() const { return off.size() >= 3 ? off[off.size() - 2] - off[off.size() - 3] : 0; }
 };
 
 struct Problem {
@@ -383,6 +396,7 @@ struct Problem {
     std::vector<int32_t> delta;
     uint16_t *d_delta = nullptr;
     SideState s[2];
+    std::vector<uint8_t> sides;  // side of every step so far (0 forward, 1 inverse)
     u64 *colT = nullptr;      // current inverse level transposed: colT_cap words state-major, then colT_cap tile-major
     int64_t colT_cap = 0;     // words
     u64 *ysig = nullptr;      // signature (OR of the words) of each set of the current inverse level
@@ -426,6 +440,7 @@ struct Problem {
     bool admitted = false;
     double t_submit = 0, t_admit = 0, t_done = 0;
     int64_t est_bytes = 0;
+    int64_t dev_bytes = 0;    // device memory its buffers held when it was released
 };
 
 // --------------------------------------------------------------- options
@@ -448,11 +463,24 @@ struct Options {
     int64_t ysort = 0;                  // new inverse levels of at least this many candidates go in cardinality order (0: never)
     int64_t meet_grid = 0;              // meet blocks per launch (0: one per work item)
     int64_t meet_order = 1;             // chunked meet items: 0 tile-range-major, 1 chunk-major
+    int64_t meet_xcd = 0;               // bucketed meet: items dealt to per-XCD queues in runs of this many (0: one queue)
     int profile = 0;                    // 1: every kernel class and the meet; 2: the meet only
     bool keep_levels = false;
     bool verbose = false;          // one stderr line per step of a single solve
     int64_t max_slots = 4096;
     double deadline_ms = 0;        // per automaton, from admission (0: none)
+    // per set width W (index W = 1..8; -1: the value above), e.g. from the
+    // autotuner's table
+    int64_t meet_groups_w[kMaxW + 1] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};
+    int64_t meet_rows_w[kMaxW + 1] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};
+    int64_t bucket_w[kMaxW + 1] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};
+    int64_t small_cand_w[kMaxW + 1] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};
+    int64_t schedule_w[kMaxW + 1] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};
+    int64_t groups(int W) const { return meet_groups_w[W] >= 0 ? meet_groups_w[W] : meet_groups; }
+    int64_t rows(int W) const { return meet_rows_w[W] >= 0 ? meet_rows_w[W] : meet_rows; }
+    int64_t bucket_min(int W) const { return bucket_w[W] >= 0 ? bucket_w[W] : bucket; }
+    int64_t small(int W) const { return small_cand_w[W] >= 0 ? small_cand_w[W] : small_cand; }
+    int sched(int W) const { return schedule_w[W] >= 0 ? (int)schedule_w[W] : schedule; }
 };
 
 // 64-bit finaliser of MurmurHash3 (Appleby), constants as published
@@ -615,10 +643,10 @@ class Engine {
             s.tab = (u64 *)A((size_t)s.tab_cap * 8);
         }
         int64_t tiles0 = ceil_div(n, 64);
-        if (persist_ok()) {
+        if (persist_ok(W)) {
             // room for the steps k_run_small may take before the first large
             // one: kPersistRows sets per side, one small step of candidates
-            const int64_t cc = std::min<int64_t>(opt.small_cand, kPersistCand);
+            const int64_t cc = std::min<int64_t>(opt.small(W), kPersistCand);
             for (int sd = 0; sd < 2; ++sd) {
                 SideState &s = p->s[sd];
                 pool_->free(s.rows);
@@ -648,8 +676,10 @@ class Engine {
         }
         p->s[0].off = {0, 1};
         p->s[0].nrows = 1;
+        p->s[0].popsum = (u64)n;        // Q
         p->s[1].off = {0, n};
         p->s[1].nrows = n;
+        p->s[1].popsum = (u64)n;        // the n singletons
         p->admitted = true;
         return true;
     }
@@ -793,9 +823,9 @@ class Engine {
         std::vector<YbDesc> YB;                    // inverse levels put into buckets in this step
         std::vector<int64_t> pyb[4] = {{0}, {0}, {0}, {0}};
         std::vector<int64_t> pmp(nseg + 1, 0);     // bucketed meets: blocks over chunks
-        if ((int64_t)nseg * 2 > res_cap_) {
+        if ((int64_t)nseg * kResWords > res_cap_) {
             pool_->free(d_res_);
-            res_cap_ = std::max<int64_t>((int64_t)nseg * 2, 2 * res_cap_);
+            res_cap_ = std::max<int64_t>((int64_t)nseg * kResWords, 2 * res_cap_);
             d_res_ = (u64 *)pool_->alloc((size_t)res_cap_ * 8, true);
             if (!d_res_) throw HipFailure{hipErrorOutOfMemory, "step result buffer"};
         }
@@ -847,7 +877,7 @@ class Engine {
                 d.nY = -1;
                 ny_ub = d.C;
             }
-            d.res = d_res_ + 2 * i;
+            d.res = d_res_ + kResWords * i;
             d.mstat = opt.profile == 1 ? d_ops_ + kOpsWords : nullptr;
             // chunked meet over the sorted forward level when it exists
             if ((dir == 0 && p->sort_now) || (dir == 1 && p->xs_valid && opt.meet != 1)) {
@@ -916,10 +946,11 @@ class Engine {
                 pm[i + 1] = pm[i] + d.nXb * d.nYc;
             } else {
                 const int64_t ng_ub = ceil_div(ceil_div(ny_ub, 64) + (d.meet_mode == 2 ? kYBins : 0), 64);
-                d.ngi = std::max<int64_t>(1, std::min<int64_t>(opt.meet_groups, ng_ub));
-                d.row_batch_max = std::min<int64_t>(opt.meet_rows, kRowBatchMax);
+                d.ngi = std::max<int64_t>(1, std::min<int64_t>(opt.groups(W), ng_ub));
+                d.row_batch_max = std::min<int64_t>(opt.rows(W), kRowBatchMax);
                 d.nch_ub = ceil_div(nx_ub, 64);
                 d.item_order = opt.meet_order;
+                d.xcd_granule = opt.meet_xcd;
                 d.gitems_ub = ceil_div(ng_ub, d.ngi);
                 if (d.meet_mode == 1) pm[i + 1] = pm[i] + ceil_div(ceil_div(nx_ub, 64) * d.gitems_ub, kBS / 64);
                 else pm[i + 1] = pm[i];            // its items come from a queue
@@ -928,7 +959,7 @@ class Engine {
             // the new inverse level is transposed in level order, unless it
             // goes into buckets (transposed in bucket order there)
             d.ntr_waves = (dir == 1 && !p->yb_now) ? ceil_div(d.C, 64) * W : 0;
-            d.small = d.meet_mode == 0 && d.C <= opt.small_cand && d.nXb * d.nYc <= kSmallMeetBlocks;
+            d.small = d.meet_mode == 0 && d.C <= opt.small(W) && d.nXb * d.nYc <= kSmallMeetBlocks;
             if (d.small) {
                 pm[i + 1] = pm[i];
                 small.push_back(i);
@@ -1075,8 +1106,8 @@ class Engine {
         stats_.launches[1]++;
         stats_.launches[2]++;
         stats_.launches[4]++;
-        u64 *hres = (u64 *)pin_res_.need((size_t)nseg * 16);
-        HIPCHK(hipMemcpyAsync(hres, d_res_, (size_t)nseg * 16, hipMemcpyDeviceToHost, stream_));
+        u64 *hres = (u64 *)pin_res_.need((size_t)nseg * kResWords * 8);
+        HIPCHK(hipMemcpyAsync(hres, d_res_, (size_t)nseg * kResWords * 8, hipMemcpyDeviceToHost, stream_));
         const double t2 = now_ms();
         wait_step();
         const double t3 = now_ms();
@@ -1091,11 +1122,13 @@ class Engine {
             Problem *p = segp[i];
             const int dir = segdir[i];
             SideState &s = p->s[dir];
-            const int64_t U = (int64_t)hres[2 * i];
-            const u64 best = hres[2 * i + 1];
+            const int64_t U = (int64_t)hres[kResWords * i];
+            const u64 best = hres[kResWords * i + 1];
             const StepDesc &d = D[i];
             s.nrows += U;
             s.off.push_back(s.nrows);
+            s.popsum = hres[kResWords * i + 2];
+            p->sides.push_back((uint8_t)dir);
             if (dir == 0) p->xs_valid = p->sort_now;
             if (dir == 1) p->ys_valid = d.ysort != 0;
             if (dir == 1) p->yb_valid = p->yb_now;   // a new inverse level: bucketed or not
@@ -1172,7 +1205,7 @@ class Engine {
             r.colT_cap = p->colT_cap;
             r.ysig = p->ysig;
             r.ysig_cap = p->ysig_cap;
-            r.small_cand = opt.small_cand;
+            r.small_cand = opt.small(p->W);
             if (deadline_ms > 0) {
                 const double left = deadline_ms - (now_ms() - p->t_admit);
                 r.max_ticks = std::max<int64_t>(1, (int64_t)(left * wall_khz_));
@@ -1183,6 +1216,7 @@ class Engine {
             for (int sd = 0; sd < 2; ++sd) {
                 st.nrows[sd] = p->s[sd].nrows;
                 st.nlev[sd] = p->s[sd].nlev();
+                st.popsum[sd] = p->s[sd].popsum;
             }
         }
         ensure_ops();
@@ -1241,7 +1275,10 @@ class Engine {
                 s.off.assign(hoff + o, hoff + o + st.nlev[sd] + 1);
                 o += st.nlev[sd] + 1;
                 s.nrows = st.nrows[sd];
+                s.popsum = st.popsum[sd];
             }
+            for (int t = 0; t < st.steps; ++t)
+                p->sides.push_back(t < 64 * kRunSideWords ? (uint8_t)((st.sides[t >> 6] >> (t & 63)) & 1) : 255);
             p->steps += st.steps;
             stats_.steps += st.steps;
             stats_.candidates += st.candidates;
@@ -1312,7 +1349,10 @@ class Engine {
         }
     }
 
-    bool persist_ok() const { return opt.persist && opt.small_cand > 0 && opt.schedule == 0 && opt.meet != 2; }
+    // (schedule 3 leaves the first, small steps to the runner's side rule)
+    bool persist_ok(int W) const {
+        return opt.persist && opt.small(W) > 0 && (opt.sched(W) == 0 || opt.sched(W) == 3) && opt.meet != 2;
+    }
     static constexpr int64_t kMeetQueueGrid = 4096;  // blocks of a bucketed meet (they take items from queues)
     static constexpr int64_t kPersistRows = 16384;   // rows per side while k_run_small steps
     static constexpr int64_t kPersistCand = 8192;    // candidates of its largest step
@@ -1320,12 +1360,49 @@ class Engine {
 
     int choose_side(Problem *p) {
         const int64_t lf = p->s[0].cur(), lb = p->s[1].cur();
-        switch (opt.schedule) {
+        switch (opt.sched(p->W)) {
             case 1: return (int)(mix64(opt.sched_seed * 0x9E3779B97F4A7C15ull + (uint64_t)p->steps +
                                        ((uint64_t)p->index << 32)) & 1);
             case 2: return p->steps & 1;
+            case 3: return cost_side(*p);
             default: return lb < lf ? 1 : 0;   // smaller list first, ties forward
         }
+    }
+
+    // The estimate ExpMark (Section 2.1.2) of the subset tests of marking
+    // the sets of a list of Bs sets of density Bd that contain one of a list
+    // of As sets of density Ad.
+    static double exp_mark(double As, double Bs, double Ad, double Bd) {
+        if (As <= 0 || Bs <= 0) return 0.0;
+        const double w = (1.0 + Bd) / (1.0 + Ad * Bd - Ad);
+        const double e = std::log1p(Bd) / std::log(w);
+        return Bs * ((1.0 + Bd) / Bd + 1.0 / (Ad - Ad * Bd)) * std::pow(As, e);
+    }
+
+    // Schedule 3: the step of lower estimated cost (Section 2.1.2, Eq. 1-4)
+    // among the two this search has, BFS and IBFS, both with their history
+    // (there is no step without it and no DFS phase, so the rule is the
+    // paper's greedy comparison of the two single-step costs).  A step costs
+    // SetCost (512) per candidate plus ExpMark of its meet test; the terms
+    // of Eq. 2 and 3 price inclusion reductions that this search does not
+    // make, and are zero.  The fraction of candidates a side's duplicate
+    // removal keeps is taken from its last step (1 before its first);
+    // densities are clamped to [1/(2n), 1 - 1/(2n)].  Ties go forward.
+    int cost_side(const Problem &p) const {
+        const double n = p.n, k = p.k, set_cost = 512.0;
+        const double lo = 0.5 / n, hi = 1.0 - 0.5 / n;
+        const SideState &F = p.s[0], &B = p.s[1];
+        const double lf = (double)F.cur(), lb = (double)B.cur();
+        auto dens = [&](const SideState &s, double m) {
+            return std::min(hi, std::max(lo, m > 0 ? (double)s.popsum / (n * m) : lo));
+        };
+        auto keep = [&](const SideState &s) {
+            return s.prev() > 0 ? (double)s.cur() / (k * (double)s.prev()) : 1.0;
+        };
+        const double df = dens(F, lf), db = dens(B, lb);
+        const double bfs = set_cost * k * lf + exp_mark(k * keep(F) * lf, lb, df, db);
+        const double ibfs = set_cost * k * lb + exp_mark(lf, k * keep(B) * lb, df, db);
+        return ibfs < bfs ? 1 : 0;
     }
 
     bool dev_grow(void *&ptr, int64_t &cap, int64_t need, size_t elem, int64_t keep) {
@@ -1436,8 +1513,8 @@ class Engine {
                               (C >= kSortMinCand && (double)C * (double)nY >= kSortMinPairs);
             if (want) p->sort_now = ensure_sort(p, C);   // no room: the LDS-tile meet serves
             if (!p->sort_now && p->yb_valid) return set_error(SRW_ENOMEM, "device budget (sort)");
-            if (p->sort_now && !p->yb_valid && bucket_ok() && nY >= opt.bucket) p->yb_now = true;
-        } else if (dir == 1 && bucket_ok() && p->xs_valid && C >= opt.bucket) {
+            if (p->sort_now && !p->yb_valid && bucket_ok(W) && nY >= opt.bucket_min(W)) p->yb_now = true;
+        } else if (dir == 1 && bucket_ok(W) && p->xs_valid && C >= opt.bucket_min(W)) {
             p->yb_now = true;
         }
         if (p->yb_now) {
@@ -1461,7 +1538,7 @@ class Engine {
         return 0;
     }
 
-    bool bucket_ok() const { return opt.bucket > 0 && opt.ysort == 0 && opt.meet != 1; }
+    bool bucket_ok(int W) const { return opt.bucket_min(W) > 0 && opt.ysort == 0 && opt.meet != 1; }
     // this step's meet runs against the inverse level in buckets (mode 2)
     static bool bucketed_meet(const Problem *p, int dir) {
         return dir == 0 ? (p->sort_now && (p->yb_valid || p->yb_now)) : (p->xs_valid && p->yb_now);
@@ -1598,8 +1675,28 @@ class Engine {
     }
 
   public:
+    // device bytes held by the problem's buffers (they only grow, so at the
+    // end of a search this is its footprint)
+    int64_t footprint(const Problem *p) const {
+        int64_t b = 0;
+        for (const void *q : {(const void *)p->d_delta, (const void *)p->colT, (const void *)p->ysig,
+                              (const void *)p->d_off, (const void *)p->yb_small, (const void *)p->yb_key,
+                              (const void *)p->yb_idx, (const void *)p->yb_list, (const void *)p->mp_key,
+                              (const void *)p->mp_order, (const void *)p->mp_cpre, (const void *)p->mp_kinfo,
+                              (const void *)p->mp_queue, (const void *)p->ys_hist, (const void *)p->ys_cnt,
+                              (const void *)p->ys_idx, (const void *)p->cand, (const void *)p->cslot,
+                              (const void *)p->xs_rows, (const void *)p->xs_com, (const void *)p->xs_idx,
+                              (const void *)p->xs_keys, (const void *)p->xs_hist, (const void *)p->xs_bins,
+                              (const void *)p->xs_top})
+            b += pool_->size_of(q);
+        for (int sd = 0; sd < 2; ++sd)
+            b += pool_->size_of(p->s[sd].rows) + pool_->size_of(p->s[sd].par) + pool_->size_of(p->s[sd].tab);
+        return b;
+    }
+
     void release(Problem *p, bool force = false) {
         (void)force;
+        p->dev_bytes = std::max(p->dev_bytes, footprint(p));
         pool_->free(p->d_delta); p->d_delta = nullptr;
         for (int sd = 0; sd < 2; ++sd) {
             pool_->free(p->s[sd].rows); p->s[sd].rows = nullptr;
@@ -1872,9 +1969,25 @@ int srw_set_option(const char *key, int64_t v) {
         }
         return SRW_OK;
     }
+    const size_t at = k.find('@');
+    if (at != std::string::npos) {       // a per-width value: "<key>@<W>", -1 removes it
+        const std::string base = k.substr(0, at), ws = k.substr(at + 1);
+        const int W = (ws.size() == 1 && ws[0] >= '1' && ws[0] <= '8') ? ws[0] - '0' : 0;
+        if (W == 0) return set_error(SRW_EINVAL, "width in " + k + " must be 1..8");
+        int64_t *slot = base == "meet_groups" ? x.opt.meet_groups_w : base == "meet_rows" ? x.opt.meet_rows_w
+                      : base == "bucket" ? x.opt.bucket_w : base == "small_cand" ? x.opt.small_cand_w
+                      : base == "schedule" ? x.opt.schedule_w : nullptr;
+        if (!slot) return set_error(SRW_EINVAL, "no per-width option " + base);
+        if (v < -1 || (base == "meet_groups" && (v == 0 || v > 4096)) || (base == "small_cand" && v > (1 << 20)) ||
+            (base == "schedule" && v > 3))
+            return set_error(SRW_EINVAL, "value of " + k);
+        slot[W] = v;
+        if (x.eng) x.eng->opt = x.opt;
+        return SRW_OK;
+    }
     if (k == "max_slots") { if (v < 1) return set_error(SRW_EINVAL, "max_slots < 1"); x.opt.max_slots = v; }
     else if (k == "profile") { if (v < 0 || v > 2) return set_error(SRW_EINVAL, "profile"); x.opt.profile = (int)v; }
-    else if (k == "schedule") { if (v < 0 || v > 2) return set_error(SRW_EINVAL, "schedule"); x.opt.schedule = (int)v; }
+    else if (k == "schedule") { if (v < 0 || v > 3) return set_error(SRW_EINVAL, "schedule"); x.opt.schedule = (int)v; }
     else if (k == "sched_seed") x.opt.sched_seed = (uint64_t)v;
     else if (k == "meet_tiles") { if (v < 0 || v > kMeetTileWords) return set_error(SRW_EINVAL, "meet_tiles"); x.opt.meet_tiles = (int)v; }
     else if (k == "keep_levels") x.opt.keep_levels = v != 0;
@@ -1889,6 +2002,7 @@ int srw_set_option(const char *key, int64_t v) {
     else if (k == "meet_groups") { if (v < 1 || v > 4096) return set_error(SRW_EINVAL, "meet_groups"); x.opt.meet_groups = v; }
     else if (k == "meet_grid") { if (v < 0) return set_error(SRW_EINVAL, "meet_grid"); x.opt.meet_grid = v; }
     else if (k == "meet_order") { if (v < 0 || v > 1) return set_error(SRW_EINVAL, "meet_order"); x.opt.meet_order = v; }
+    else if (k == "meet_xcd") { if (v < 0 || v > 65536) return set_error(SRW_EINVAL, "meet_xcd"); x.opt.meet_xcd = v; }
     else return set_error(SRW_EINVAL, "unknown option " + k);
     if (x.eng) x.eng->opt = x.opt;
     return SRW_OK;
@@ -2014,6 +2128,18 @@ int srw_solve(int32_t n, int32_t k, const int32_t *delta, int32_t *r, uint8_t *w
     }
     if (!x.eng || x.eng->kept() != p) delete p;
     return rc;
+}
+
+int srw_last_sides(int32_t *steps, uint8_t *sides, int64_t cap) {
+    if (!steps || cap < 0 || (cap > 0 && !sides)) return set_error(SRW_EINVAL, "bad arguments");
+    Context &x = ctx();
+    std::lock_guard<std::mutex> g(x.mu);
+    if (!x.eng || !x.eng->kept()) return set_error(SRW_EINVAL, "no kept solve (set keep_levels)");
+    const std::vector<uint8_t> &v = x.eng->kept()->sides;
+    *steps = (int32_t)v.size();
+    if ((int64_t)v.size() > cap && sides) return set_error(SRW_EINVAL, "cap below the step count");
+    if (sides) memcpy(sides, v.data(), v.size());
+    return SRW_OK;
 }
 
 int srw_last_levels(int32_t side, int32_t *nlev, int64_t *nrows, int64_t *off, uint64_t *rows, uint32_t *par) {
@@ -2347,8 +2473,24 @@ int srw_server_create(srw_server **out, const srw_config *cfg) {
             HIPCHK(hipMemGetInfo(&fr, &tot));
             total = (int64_t)(fr * 0.8);
         }
-        for (int li = 0; li < kLanes; ++li)
+        // the lanes search with the default context's options as they are now
+        // (its tuning, e.g. the autotuner's per-width values); the rest are
+        // the server's own or off
+        Options so;
+        {
+            Context &x = ctx();
+            std::lock_guard<std::mutex> g(x.mu);
+            so = x.opt;
+        }
+        so.profile = 0;
+        so.keep_levels = false;
+        so.verbose = false;
+        so.deadline_ms = 0;
+        so.max_slots = Options().max_slots;
+        for (int li = 0; li < kLanes; ++li) {
             s->lane[li].eng.reset(new Engine(c.device, b, (int64_t)(total * kLaneShare[li]), nullptr));
+            s->lane[li].eng->opt = so;
+        }
     } catch (const HipFailure &f) {
         delete s;
         return device_error(f);
@@ -2411,6 +2553,8 @@ int srw_server_poll(srw_server *s, srw_result *out, int32_t max, int32_t timeout
         r.word = p->word.empty() ? nullptr : p->word.data();
         r.latency_ms = p->t_done - p->t_submit;
         r.queue_ms = p->t_admit - p->t_submit;
+        r.est_bytes = p->est_bytes;
+        r.dev_bytes = p->dev_bytes;
         s->returned.push_back(p);
         s->polled++;
     }

@@ -283,6 +283,7 @@ __global__ void __launch_bounds__(kBS) k_scan(const StepDesc *descs, int nseg, c
     if (tid == 0) {
         d.res[0] = running;
         d.res[1] = kEmpty;
+        d.res[2] = 0;                      // k_compact adds the cardinalities
     }
 }
 
@@ -295,6 +296,7 @@ __global__ void __launch_bounds__(kBS) k_compact(const StepDesc *descs, const in
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int W = d.W;
     u32 rank0 = blk_off[d.cblk_base + lb];
+    u32 card = 0;                          // cardinalities of this lane's winners
 #pragma unroll
     for (int t = 0; t < kCB / kBS; ++t) {
         const int64_t g = lb * kCB + t * kBS + tid;
@@ -310,7 +312,11 @@ __global__ void __launch_bounds__(kBS) k_compact(const StepDesc *descs, const in
         }
         if (f) {
             const u64 rank = rank0 + wpre + lanes_below(mask);
-            for (int w = 0; w < W; ++w) d.out_rows[rank * W + w] = d.cand[g * W + w];
+            for (int w = 0; w < W; ++w) {
+                const u64 v = d.cand[g * W + w];
+                d.out_rows[rank * W + w] = v;
+                card += (u32)__popcll(v);
+            }
             d.out_par[rank] = (u32)g;
             const u32 sl = d.cslot[g];
             const u64 e = d.tab[sl];
@@ -319,6 +325,9 @@ __global__ void __launch_bounds__(kBS) k_compact(const StepDesc *descs, const in
         rank0 += tot;
         __syncthreads();
     }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) card += (u32)__shfl_xor((int)card, off, 64);
+    if (lane == 0 && card) atomicAdd((unsigned long long *)(d.res + 2), (unsigned long long)card);
 }
 
 // ------------------------------------------------------------ transpose
@@ -885,6 +894,16 @@ __global__ void __launch_bounds__(kBS) k_meet(const StepDesc *descs, const int64
 // so every wave of the grid ends.  Work items go in the plan's order (see
 // kOrderKeys): per order key, range by range of d.ngi tile groups of the
 // key's list, and within a range chunk by chunk.
+//
+// With d.xcd_granule = G > 0 the items are dealt to eight queues, one per
+// XCD: runs of G consecutive items in plan order go to queue 0, 1, ..., 7,
+// 0, ... in turn, so the chunks that scan one range of tiles mostly run on
+// one XCD and share its L2 (each XCD has its own).  Workgroups are
+// dispatched to the XCDs round robin, so block b serves queue b % 8 first;
+// a wave whose queue is empty takes from the next queues.  Queue x's j-th
+// item is item ((j / G) * 8 + x) * G + j % G of the plan: every item is in
+// exactly one queue, and a queue's items rise with j, so a wave that finds
+// every queue past the item count has nothing left to take.
 template <int W, bool CNT>
 __global__ void __launch_bounds__(kBS) k_meet_b(const StepDesc *descs, int s0, int s1, u64 *ops) {
     __shared__ u64 cols[kMeetLdsWords];
@@ -900,9 +919,22 @@ __global__ void __launch_bounds__(kBS) k_meet_b(const StepDesc *descs, int s0, i
         // the plan's item count, capped by the host's upper bound of it
         const u32 total = (u32)min((int64_t)__hip_atomic_load(d.queue + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
                                    d.nch_ub * d.gitems_ub);
+        const u32 G = (u32)d.xcd_granule;
+        const u32 x0 = blockIdx.x & 7u;
         for (;;) {
-            u32 it = 0;
-            if (lane == 0) it = atomicAdd(d.queue, 1u);
+            u32 it = 0xFFFFFFFFu;
+            if (lane == 0) {
+                if (G == 0) {
+                    it = atomicAdd(d.queue, 1u);
+                } else {
+                    for (u32 t = 0; t < 8; ++t) {
+                        const u32 x = (x0 + t) & 7u;
+                        const u64 j = atomicAdd(d.queue + 2 + x, 1u);
+                        const u64 i = ((j / G) * 8 + x) * G + j % G;
+                        if (i < total) { it = (u32)i; break; }
+                    }
+                }
+            }
             it = __builtin_amdgcn_readfirstlane(__shfl((int)it, 0, 64));
             if (it >= total) break;
             const u32 *kpre = d.kinfo + kKPre;
@@ -1215,6 +1247,7 @@ __global__ void __launch_bounds__(kBS) k_mp_scan(const StepDesc *descs, int nseg
         d.kinfo[kKPre + kOrderKeys] = total;
         d.queue[0] = 0;
         d.queue[1] = total;
+        for (int x = 0; x < 8; ++x) d.queue[2 + x] = 0;
     }
 }
 
@@ -1259,6 +1292,7 @@ __device__ u32 step_small_w(const D &d, u64 *lds, u32 *wsum) {
     for (int64_t lb = 0; lb < nb; ++lb) insert_w<W>(d, lb);
     __syncthreads();
     u32 rank0 = 0;
+    u32 card = 0;                          // cardinalities of this lane's winners
     for (int64_t g0 = 0; g0 < d.C; g0 += kBS) {
         const int64_t g = g0 + tid;
         const bool f = g < d.C && is_winner(d, g);
@@ -1274,7 +1308,11 @@ __device__ u32 step_small_w(const D &d, u64 *lds, u32 *wsum) {
         if (f) {
             const u64 rank = rank0 + wpre + lanes_below(mask);
 #pragma unroll
-            for (int w = 0; w < W; ++w) d.out_rows[rank * W + w] = d.cand[g * W + w];
+            for (int w = 0; w < W; ++w) {
+                const u64 v = d.cand[g * W + w];
+                d.out_rows[rank * W + w] = v;
+                card += (u32)__popcll(v);
+            }
             d.out_par[rank] = (u32)g;
             const u32 sl = d.cslot[g];
             const u64 e = d.tab[sl];
@@ -1283,9 +1321,16 @@ __device__ u32 step_small_w(const D &d, u64 *lds, u32 *wsum) {
         rank0 += tot;
         __syncthreads();
     }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) card += (u32)__shfl_xor((int)card, off, 64);
+    if (lane == 0) wsum[wave] = card;
+    __syncthreads();
     if (tid == 0) {
+        u64 tc = 0;
+        for (int w = 0; w < kBS / 64; ++w) tc += wsum[w];
         d.res[0] = rank0;
         d.res[1] = kEmpty;
+        d.res[2] = tc;
     }
     if (d.ntr_waves > 0) {                 // a new inverse level: transpose it
         const int64_t tiles = ((int64_t)rank0 + 63) / 64;
@@ -1336,6 +1381,7 @@ __global__ void __launch_bounds__(kBS) k_step_small(const StepDesc *descs, const
 template <int W>
 __device__ u32 run_small_w(const CONST_AS RunDesc &r, StepDesc &sd, u64 *lds, u32 *wsum) {
     __shared__ int64_t cs[2], cn[2], nr[2];   // current level start and size, rows stored
+    __shared__ u64 ps[2];                     // cardinality sums of the current levels
     __shared__ int nl[2];                     // levels per side
     __shared__ int go, dir_s;
     RunState *st = r.st;
@@ -1354,6 +1400,7 @@ __device__ u32 run_small_w(const CONST_AS RunDesc &r, StepDesc &sd, u64 *lds, u3
             }
             cs[s] = r.off[s][nl[s] - 1];
             cn[s] = nr[s] - cs[s];
+            ps[s] = st->popsum[s];
         }
     }
     __syncthreads();
@@ -1435,9 +1482,11 @@ __device__ u32 run_small_w(const CONST_AS RunDesc &r, StepDesc &sd, u64 *lds, u3
             pairs += dir == 0 ? U * cn[1] : cn[0] * U;
             cs[dir] = nr[dir];
             cn[dir] = U;
+            ps[dir] = load_slot(st->res + 2);
             nr[dir] += U;
             nl[dir] += 1;
             r.off[dir][nl[dir]] = nr[dir];
+            if (dir && steps < 64 * kRunSideWords) st->sides[steps >> 6] |= 1ull << (steps & 63);
             ++steps;
             go = 1;
             if (best != kEmpty) {
@@ -1456,6 +1505,7 @@ __device__ u32 run_small_w(const CONST_AS RunDesc &r, StepDesc &sd, u64 *lds, u3
         for (int s = 0; s < 2; ++s) {
             st->nrows[s] = nr[s];
             st->nlev[s] = nl[s];
+            st->popsum[s] = ps[s];
         }
         st->steps = steps;
         st->candidates = cands;

@@ -28,7 +28,7 @@ EXPORTS = ("srw_solve", "srw_solve_batch", "srw_solve_noalloc", "srw_check_sync"
            "srw_server_create", "srw_server_submit", "srw_server_poll",
            "srw_server_pending", "srw_server_destroy", "srw_set_allocator",
            "srw_set_stream", "srw_set_option", "srw_get_stats", "srw_reset_stats",
-           "srw_last_levels", "srw_last_error")
+           "srw_last_levels", "srw_last_sides", "srw_last_error")
 
 KERNEL_CLASSES = ("expand", "insert", "compact", "prep", "meet", "trace", "setup", "step")
 
@@ -75,7 +75,8 @@ class Config(ctypes.Structure):
 class Result(ctypes.Structure):
     _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("r", ctypes.c_int32),
                 ("word", ctypes.POINTER(ctypes.c_uint8)), ("latency_ms", ctypes.c_double),
-                ("queue_ms", ctypes.c_double)]
+                ("queue_ms", ctypes.c_double), ("est_bytes", ctypes.c_int64),
+                ("dev_bytes", ctypes.c_int64)]
 
 
 _lib = None
@@ -128,6 +129,7 @@ def load(path: str = LIB_PATH):
     L.srw_get_stats.argtypes = [ctypes.POINTER(Stats)]
     L.srw_reset_stats.argtypes = []
     L.srw_last_levels.argtypes = [ctypes.c_int32, i32p, i64p, i64p, u64p, u32p]
+    L.srw_last_sides.argtypes = [i32p, u8p, ctypes.c_int64]
     L.srw_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
@@ -188,6 +190,39 @@ def set_option(key: str, value: int):
     rc = load().srw_set_option(key.encode(), int(value))
     if rc:
         raise SrwError(rc, f"set_option({key})")
+
+
+TUNING_TABLE = os.path.join(HERE, "tuning.json")
+
+
+def apply_tuning(path: str = TUNING_TABLE) -> dict:
+    """Set the per-width options of the autotuner's table (autotune.py):
+    option "<key>@<W>" for every tuned key and width.  Returns the values
+    set, {W: {key: value}} ({} when there is no table)."""
+    if not os.path.exists(path):
+        return {}
+    import json
+    with open(path) as f:
+        rec = json.load(f)
+    out = {}
+    for w, ent in sorted(rec.get("widths", {}).items()):
+        vals = {key: int(v) for key, v in ent["values"].items()}
+        for key, v in vals.items():
+            set_option(f"{key}@{int(w)}", v)
+        out[int(w)] = vals
+    return out
+
+
+def clear_tuning(path: str = TUNING_TABLE):
+    """Remove the per-width values apply_tuning set."""
+    if not os.path.exists(path):
+        return
+    import json
+    with open(path) as f:
+        rec = json.load(f)
+    for w, ent in rec.get("widths", {}).items():
+        for key in ent["values"]:
+            set_option(f"{key}@{int(w)}", -1)
 
 
 def check_sync(n, k, delta) -> bool:
@@ -303,6 +338,21 @@ def last_levels(side: int, W: int):
             for i in range(nlev.value)]
 
 
+def last_sides():
+    """Sides of the steps of the last srw_solve run with keep_levels=1 (0
+    forward, 1 inverse), in order."""
+    L = load()
+    steps = ctypes.c_int32(0)
+    rc = L.srw_last_sides(ctypes.byref(steps), None, 0)
+    if rc:
+        raise SrwError(rc, "last_sides")
+    out = np.zeros(max(1, steps.value), dtype=np.uint8)
+    rc = L.srw_last_sides(ctypes.byref(steps), _ptr(out, ctypes.c_uint8), len(out))
+    if rc:
+        raise SrwError(rc, "last_sides")
+    return [int(x) for x in out[: steps.value]]
+
+
 class Server:
     """Continuous-batching server (srw_server_*)."""
 
@@ -333,7 +383,8 @@ class Server:
             x = self._buf[i]
             w = [x.word[t] for t in range(x.r)] if (x.status == OK and x.r > 0) else []
             out.append({"tag": int(x.tag), "status": int(x.status), "r": int(x.r), "word": w,
-                        "latency_ms": float(x.latency_ms), "queue_ms": float(x.queue_ms)})
+                        "latency_ms": float(x.latency_ms), "queue_ms": float(x.queue_ms),
+                        "est_bytes": int(x.est_bytes), "dev_bytes": int(x.dev_bytes)})
         return out
 
     def pending(self) -> int:

@@ -144,18 +144,39 @@ def test_every_documented_option_is_accepted_and_checked():
     defaults = {"budget": 0, "max_slots": 4096, "profile": 0, "schedule": 0, "sched_seed": 0,
                 "meet": 0, "meet_tiles": 0, "meet_rows": 512, "meet_groups": 16, "meet_order": 1,
                 "meet_grid": 0, "ysort": 0, "small_cand": 2048, "deadline_ms": 0,
-                "verbose": 0, "keep_levels": 0, "persist": 1, "bucket": 16384}
+                "verbose": 0, "keep_levels": 0, "persist": 1, "bucket": 16384, "meet_xcd": 0}
     assert set(keys) == set(defaults), set(keys) ^ set(defaults)
     for k in keys:
         srw.set_option(k, defaults[k])
-    bad = {"profile": 3, "schedule": 3, "meet": 3, "meet_order": 2, "meet_groups": 0,
+    bad = {"profile": 3, "schedule": 4, "meet": 3, "meet_order": 2, "meet_groups": 0,
            "meet_tiles": 1000, "ysort": -1, "small_cand": -1, "meet_grid": -1, "budget": -5,
-           "persist": 2, "bucket": -1}
+           "persist": 2, "bucket": -1, "meet_xcd": -1}
     for k, v in bad.items():
         with pytest.raises(srw.SrwError) as e:
             srw.set_option(k, v)
         assert e.value.code == srw.EINVAL, k
         srw.set_option(k, defaults[k])
+
+
+def test_per_width_options_are_checked():
+    """"<key>@<W>" sets a value for one set width; bad widths, keys and
+    values are SRW_EINVAL; -1 removes it."""
+    for key, v in (("meet_groups@8", 32), ("meet_rows@1", 256), ("small_cand@3", 0),
+                   ("bucket@5", 0), ("schedule@4", 3)):
+        srw.set_option(key, v)
+        srw.set_option(key, -1)
+    for key, v in (("meet_groups@0", 16), ("meet_groups@9", 16), ("meet_groups@", 16),
+                   ("meet_groups@12", 16), ("persist@2", 1), ("meet_groups@2", 0),
+                   ("schedule@2", 4), ("small_cand@1", -2), ("bucket@1", -3)):
+        with pytest.raises(srw.SrwError) as e:
+            srw.set_option(key, v)
+        assert e.value.code == srw.EINVAL, key
+
+
+def test_last_sides_needs_a_kept_solve():
+    with pytest.raises(srw.SrwError) as e:
+        srw.last_sides()
+    assert e.value.code == srw.EINVAL
 
 
 def test_binding_structs_match_the_header(tmp_path):

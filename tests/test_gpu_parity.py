@@ -35,7 +35,7 @@ def gpu():
 DEFAULTS = (("schedule", 0), ("meet_tiles", 0), ("keep_levels", 0), ("budget", 0), ("meet", 0),
             ("max_slots", 4096), ("meet_rows", 512), ("meet_groups", 16), ("meet_order", 1),
             ("meet_grid", 0), ("small_cand", 2048), ("ysort", 0), ("deadline_ms", 0),
-            ("verbose", 0), ("persist", 1), ("bucket", 16384))
+            ("verbose", 0), ("persist", 1), ("bucket", 16384), ("meet_xcd", 0))
 
 
 def say(*a):
@@ -203,6 +203,67 @@ def test_schedule_invariance(sched):
             assert srw.solve(n, k, d) == w
     finally:
         srw.set_option("schedule", 0)
+
+
+def cost_cases():
+    from tests.test_schedule_oracle import cases
+    return cases()
+
+
+def test_cost_model_schedule_sides_and_results():
+    """Schedule 3 (Section 2.1.2's step costs): with every step chosen by
+    the host, the side of each step equals the oracle's cost-model choice
+    (oracle/schedule.py, written separately), and r and word equal the
+    oracle's."""
+    from oracle import schedule as S
+    srw.set_option("schedule", 3)
+    srw.set_option("persist", 0)
+    srw.set_option("keep_levels", 1)
+    try:
+        for n, k, d in cost_cases():
+            say("cost schedule", n, k)
+            assert srw.solve(n, k, d) == oracle_rw(n, k, d)
+            assert srw.last_sides() == S.cost_sides(n, k, d), (n, k)
+    finally:
+        srw.set_option("schedule", 0)
+        srw.set_option("persist", 1)
+        srw.set_option("keep_levels", 0)
+
+
+def test_recorded_sides_follow_the_frontier_rule():
+    """Schedule 0 with the one-launch small steps on: the sides the runner
+    and the host took, in order, are the oracle's (smaller list first, ties
+    forward)."""
+    srw.set_option("keep_levels", 1)
+    try:
+        for n, k, d in cost_cases() + [(24, 2, I.cerny(24))]:
+            say("frontier sides", n, k)
+            srw.solve(n, k, d)
+            assert srw.last_sides() == O.bidir(n, k, d)[2]["sides"], (n, k)
+    finally:
+        srw.set_option("keep_levels", 0)
+
+
+def test_cost_model_schedule_per_width_in_a_batch():
+    """Schedule 3 for some set widths only, the one-launch small steps on:
+    a batch of mixed widths keeps the oracle's r and word, and so does the
+    n = 256 automaton stored by the oracle."""
+    cs = [(n, k, d) for n, k, d in cost_cases()]
+    cs += [(n, 2, rand_sync(n, 2, i, base=55)) for i, n in enumerate((130, 190, 200))]
+    want = [oracle_rw(n, k, d) for n, k, d in cs]
+    for w in (1, 3, 4):
+        srw.set_option(f"schedule@{w}", 3)
+    srw.set_option("schedule@2", 2)
+    try:
+        res = srw.solve_batch(cs)
+        assert [(st, (r, wd)) for st, r, wd in res] == [(srw.OK, w) for w in want]
+        c = golden("rand256.json")[0]
+        d = I.random_automaton(c["n"], c["k"], c["seed"], c["attempt"])
+        r, w = srw.solve(c["n"], c["k"], d)
+        assert r == c["r"] and "".join(map(str, w)) == c["word"]
+    finally:
+        for w in (1, 2, 3, 4):
+            srw.set_option(f"schedule@{w}", -1)
 
 
 @pytest.mark.parametrize("tiles", [1, 2, 3, 8, 32])
@@ -522,13 +583,14 @@ def test_random_n256_against_stored_oracle_values():
         assert "".join(map(str, w)) == c["word"]
 
 
-@pytest.mark.parametrize("bucket", [16384, 0])
-def test_random_n450_against_stored_oracle_value(bucket):
+@pytest.mark.parametrize("bucket,xcd", [(16384, 0), (0, 0), (16384, 64)])
+def test_random_n450_against_stored_oracle_value(bucket, xcd):
     """The n = 450, k = 2 automaton of the benchmark: 8-word sets, levels of
     millions of sets, hash tables grown far past 10^7 slots, the chunked meet
     at full size with its inverse levels in buckets (default) and in level
-    order (0).  r and word equal the oracle's stored values
-    (tests/golden/n450.json; about 40 minutes of oracle time)."""
+    order (0), and with per-XCD work queues.  r and word equal the oracle's
+    stored values (tests/golden/n450.json; about 40 minutes of oracle
+    time)."""
     path = os.path.join(GOLDEN, "n450.json")
     if not os.path.exists(path):
         pytest.skip("no stored oracle value for n = 450")
@@ -537,11 +599,13 @@ def test_random_n450_against_stored_oracle_value(bucket):
     d = I.random_automaton(c["n"], c["k"], c["seed"], c["attempt"])
     assert I.first_synchronizing(450, 2, c["seed"], srw.check_sync)[1] == c["attempt"]
     srw.set_option("bucket", bucket)
+    srw.set_option("meet_xcd", xcd)
     try:
-        say("n450 bucket", bucket)
+        say("n450 bucket", bucket, "xcd", xcd)
         assert srw.solve(450, 2, d) == (c["r"], [int(x) for x in c["word"]])
     finally:
         srw.set_option("bucket", 16384)
+        srw.set_option("meet_xcd", 0)
 
 
 def test_random_n256_lds_tile_meet_equals_stored():
@@ -647,14 +711,16 @@ def test_persistent_small_steps_keep_results(persist, small):
         srw.set_option("small_cand", 2048)
 
 
-@pytest.mark.parametrize("bucket,meet", [(0, 0), (1, 2), (64, 0), (1, 0)])
-def test_bucketed_meet_keeps_results(bucket, meet):
+@pytest.mark.parametrize("bucket,meet,xcd", [(0, 0, 0), (1, 2, 0), (64, 0, 0), (1, 0, 0), (1, 2, 1),
+                                              (1, 2, 64), (64, 0, 7)])
+def test_bucketed_meet_keeps_results(bucket, meet, xcd):
     """Inverse levels in buckets by their membership of the forward level's
     most frequent states, met by chunks that scan only the buckets holding
     their common split states: off (0), for every level against every
     forward level sorted into chunks (1 with meet mode 2, so tiny and
     one-bucket levels too), from 64 sets on, and for every level the default
-    schedule sorts.  r and word equal the oracle's, singly and batched."""
+    schedule sorts; work items from one queue or dealt to per-XCD queues in
+    runs of 1, 7 or 64.  r and word equal the oracle's, singly and batched."""
     cs = [(n, 2, I.cerny(n)) for n in (9, 20)]
     cs += [(n, k, rand_sync(n, k, j, base=61)) for j, (n, k) in
            enumerate([(64, 2), (150, 2), (200, 3), (129, 2), (40, 4), (255, 2), (90, 3)])]
@@ -663,15 +729,17 @@ def test_bucketed_meet_keeps_results(bucket, meet):
     want = [oracle_rw(n, k, d) for n, k, d in cs]
     srw.set_option("bucket", bucket)
     srw.set_option("meet", meet)
+    srw.set_option("meet_xcd", xcd)
     try:
         for (n, k, d), w in zip(cs, want):
-            say("bucketed meet", bucket, meet, n, k)
+            say("bucketed meet", bucket, meet, xcd, n, k)
             assert srw.solve(n, k, d) == w, (n, k)
         res = srw.solve_batch(cs)
         assert [(st, (r, wd)) for st, r, wd in res] == [(srw.OK, w) for w in want]
     finally:
         srw.set_option("bucket", 16384)
         srw.set_option("meet", 0)
+        srw.set_option("meet_xcd", 0)
 
 
 @pytest.mark.parametrize("ysort", [0, 1])

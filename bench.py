@@ -439,6 +439,63 @@ def serve_bench(args, srw):
     }
 
 
+def beam_bench(args, srw):
+    """Beam-search upper bounds (srw_beam_batch) of 64 seeded random n = 450,
+    k = 2 automata (the first is the default workload's), width ceil(n ln n)
+    as in the paper's large-n runs (Section 3); beside it the oracle's beam
+    search of the first automata, single-threaded."""
+    import math
+    import torch
+    from oracle import oracle as O
+    n, k, count = 450, 2, 64
+    width = int(math.ceil(n * math.log(n)))
+    probs = []
+    for i in range(count):
+        d, _ = I.first_synchronizing(n, k, I.member_seed(I.BASE_SEED, i), srw.check_sync)
+        probs.append((n, k, d, width))
+    # the oracle's beam, on as many automata as fit the CPU budget
+    cpu, t_cpu, same = 0, 0.0, 0
+    want = []
+    while cpu < count and t_cpu < args.cpu_budget / 4:
+        t = time.perf_counter()
+        R, w, _ = O.beam(n, k, probs[cpu][2], width)
+        t_cpu += time.perf_counter() - t
+        want.append((R, w))
+        cpu += 1
+    res = srw.beam_batch(probs)                   # warmup
+    for _ in range(args.warmup):
+        res = srw.beam_batch(probs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = srw.beam_batch(probs)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    for (R, w), (st, Rg, wg) in zip(want, res):
+        exp = (srw.OK, R, list(w)) if R is not None else (srw.ENOBOUND, -1, None)
+        if (st, Rg, wg) != exp:
+            raise SystemExit(f"beam result {(st, Rg)} differs from the oracle's R={R}")
+        same += 1
+    Rs = [R for st, R, _ in res if st == srw.OK]
+    stored = stored_oracle_values()
+    r0 = stored.get(np.asarray(probs[0][2], dtype=np.int32).tobytes())
+    return {
+        "metric": "beam-search upper bounds/s (1 GPU)", "value": count / dt, "unit": "automata/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "beam-n450k2x64", "automata": count, "width": width,
+                   "sizes": f"{count} x random n={n} k={k} (uniform delta, seeded SplitMix64, first "
+                            "synchronizing draw)", "path": "srw_beam_batch"},
+        "R_min": min(Rs) if Rs else None, "R_max": max(Rs) if Rs else None,
+        "R_first": res[0][1], "r_first_exact": r0[0] if r0 else None,
+        "oracle_checked": f"{same} of {count} (R and word) equal the oracle's beam search",
+        "cpu_baseline": {"value": cpu / t_cpu if t_cpu else None, "unit": "automata/s", "cores": 1,
+                         "kind": "oracle", "sample": f"the first {cpu} automata, orc_beam, one core",
+                         "cpu": host_cpu()},
+    }
+
+
 def stored_oracle_values():
     """(r, word) the oracle stored under tests/golden for seeded random
     automata, keyed by the bytes of the transition table (rebuilt from each
@@ -576,6 +633,12 @@ def main():
         sys.exit(2)
 
     from paper_2207_05495_amd import srw
+    if args.workload == "beam-n450k2x64":
+        import torch
+        torch.cuda.set_device(0)
+        srw.use_torch(0)
+        print(json.dumps(beam_bench(args, srw)))
+        return
     if args.workload == "serve-mix":
         import torch
         torch.cuda.set_device(0)

@@ -55,6 +55,7 @@ extern "C" {
 #define SRW_EDEVICE (-6)       /* HIP error or no usable GPU; srw_last_error() has the text */
 #define SRW_ETIMEOUT (-7)      /* srw_server_poll: nothing completed in time; a solve: its deadline passed */
 #define SRW_EINTERNAL (-8)     /* internal check failed (e.g. the word did not verify) */
+#define SRW_ENOBOUND (-9)      /* srw_beam: a cut level had no new set before Q was reached */
 
 /* Solve one automaton.  r: out, the reset threshold.  word: out, may be NULL
  * (r only); otherwise room for word_cap letters.  On SRW_EWORDCAP *r is set. */
@@ -271,6 +272,28 @@ int srw_reset_stats(void);
  * a*|previous level|+i; 0xFFFFFFFF on level 0). */
 int srw_last_levels(int32_t side, int32_t *nlev, int64_t *nrows,
                     int64_t *off, uint64_t *rows, uint32_t *par);
+
+/* Upper bound on the reset threshold by beam search (CutOff-IBFS, cited in
+ * Section 1.3.2; its beam size is the subject of Section 2.1.3): the
+ * inverse side of the search of srw_solve alone, from the singletons, with
+ * every new level cut to its `width` sets of largest cardinality (ties: the
+ * least key, i.e. the lexicographically least word).  Sets cut from a level
+ * stay visited.  *R is the first depth whose kept level holds Q, so R >= r;
+ * `word` (if not NULL, word_cap >= R) gets a reset word of length R, the one
+ * of the first such set, checked on the host.  With a width at least the
+ * size of every level this is the exact search: R = r and the word is the
+ * one srw_solve returns.  One block of the GPU runs each automaton from
+ * start to end.  Statuses as srw_solve, plus SRW_ENOBOUND when a level ends
+ * up empty before Q is reached (the cut can lead into a dead end); "budget"
+ * and "deadline_ms" of srw_set_option apply. */
+int srw_beam(int32_t n, int32_t k, const int32_t *delta, int64_t width, int32_t *R,
+             uint8_t *word, int64_t word_cap);
+/* srw_beam of `count` automata at once (arrays as in srw_solve_batch, plus
+ * width[i] per automaton); the return value is SRW_OK or an error of the
+ * call itself, each automaton's status is in status[i]. */
+int srw_beam_batch(int32_t count, const int32_t *n, const int32_t *k, const int64_t *delta_off,
+                   const int32_t *delta, const int64_t *width, int32_t *R, int32_t *status,
+                   const int64_t *word_off, uint8_t *words, const int64_t *word_cap);
 
 /* The side of every step of the last srw_solve run with "keep_levels" on,
  * in order (0 forward, 1 inverse): *steps = their count; with sides != NULL

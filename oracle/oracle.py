@@ -74,6 +74,8 @@ def bind(path):
         L.orc_bidir_reduced.argtypes = L.orc_bidir.argtypes
         L.orc_bidir_history.argtypes = L.orc_bidir.argtypes
         L.orc_bidir_reduce.argtypes = L.orc_bidir.argtypes + [ctypes.c_int]
+        L.orc_beam.argtypes = [ctypes.c_int, ctypes.c_int, i32p, ctypes.c_int64, ctypes.c_int,
+                               i32p, u8p, ctypes.c_int64, i64p]
         L.orc_levels.argtypes = [ctypes.c_void_p, ctypes.c_int, i32p, i64p, i64p,
                                  u64p, i64p]
         L.orc_free.argtypes = [ctypes.c_void_p]
@@ -230,6 +232,26 @@ def bidir_steps(n, k, delta, max_steps, meet=MEET_MARK):
     if rc not in (OK, ELIMIT):
         raise OracleError(rc, "bidir_steps")
     return rc == OK, dict(zip(STAT_NAMES, (int(x) for x in stats)))
+
+
+BEAM_STATS = ("steps", "kept", "cut", "widest")
+
+
+def beam(n, k, delta, width, max_steps=1 << 20):
+    """Beam search upper bound (orc_beam): returns (R, word, info), or
+    (None, None, info) when the cut led into a dead end."""
+    d = _delta(delta)
+    R = ctypes.c_int32(-1)
+    cap = 1 << 20
+    word = np.zeros(cap, dtype=np.uint8)
+    stats = np.zeros(len(BEAM_STATS), dtype=np.int64)
+    rc = lib().orc_beam(n, k, _ptr(d, ctypes.c_int32), int(width), int(max_steps), ctypes.byref(R),
+                        _ptr(word, ctypes.c_uint8), cap, _ptr(stats, ctypes.c_int64))
+    info = dict(zip(BEAM_STATS, (int(x) for x in stats)))
+    if rc == ELIMIT:
+        return None, None, info
+    rr, ww = _result(rc, "beam", R, word)
+    return rr, ww, info
 
 
 def levels_after(n, k, delta, sched):

@@ -32,6 +32,11 @@
  *   orc_bidir_reduce      either reduction by flags, with the drops found
  *                         by all pairs or by Alg. 2; pinned by equality of
  *                         the two and the invariants above
+ *   orc_beam              beam search (CutOff-IBFS, cited in Section 1.3.2
+ *                         and tuned in Section 2.1.3): the inverse side of
+ *                         the plain search with every level cut to its
+ *                         largest sets; an upper bound R >= r and a reset
+ *                         word of length R
  *   orc_bidir             plain bidirectional BFS (Alg. 1 with only the
  *                         duplicate removal kept): forward images from Q,
  *                         inverse preimages from the singletons, meet test
@@ -883,6 +888,129 @@ int orc_bidir(int n, int k, const int32_t *delta, int meet_mode,
               uint8_t *sides_out, int64_t *stats_out, void **handle_out) {
     return bidir_impl(n, k, delta, meet_mode, sched, sched_len, max_steps, r, word, word_cap,
                       sides_out, stats_out, handle_out, 0);
+}
+
+/* ------------- beam search: CutOff-IBFS (Section 1.3.2, 2.1.3) ---------- */
+
+/* Keeps the `beam` sets of largest cardinality of the newest level (ties:
+ * the earlier place in the level, i.e. the least key); the sets cut stay
+ * visited (ghost rows) and leave the level, whose kept sets keep key
+ * order.  Returns how many sets were cut, or a negative ORC_ code. */
+static int64_t side_cut(Side *s, int64_t beam, int n) {
+    const int W = s->W, L = s->nlev - 1;
+    const int64_t m = level_size(s, L), base = s->off[L];
+    if (m <= beam) return 0;
+    int64_t *count = calloc((size_t)n + 1, sizeof(int64_t));
+    unsigned char *drop = malloc((size_t)m);
+    if (!count || !drop) { free(count); free(drop); return ORC_ENOMEM; }
+    for (int64_t i = 0; i < m; i++) count[popcount_set(level_row(s, L, i), W)]++;
+    /* the least cardinality that is kept, and how many of it */
+    int cstar = n;
+    int64_t above = 0;
+    while (above + count[cstar] < beam) above += count[cstar--];
+    int64_t quota = beam - above, cut = 0;
+    for (int64_t i = 0; i < m; i++) {
+        const int c = popcount_set(level_row(s, L, i), W);
+        drop[i] = !(c > cstar || (c == cstar && quota > 0));
+        if (c == cstar && !drop[i]) quota--;
+        cut += drop[i];
+    }
+    free(count);
+    if (s->nghost + cut > s->ghost_cap) {
+        int64_t cap = 2 * (s->nghost + cut) + 16;
+        u64 *g = realloc(s->ghost, (size_t)cap * W * sizeof(u64));
+        if (!g) { free(drop); return ORC_ENOMEM; }
+        s->ghost = g;
+        s->ghost_cap = cap;
+    }
+    int64_t pos = base;
+    for (int64_t i = 0; i < m; i++) {
+        if (drop[i]) {
+            memcpy(s->ghost + (s->nghost++) * W, level_row(s, L, i), sizeof(u64) * W);
+            continue;
+        }
+        if (pos != base + i) {
+            memmove(s->rows + pos * W, s->rows + (base + i) * W, sizeof(u64) * W);
+            s->par[pos] = s->par[base + i];
+        }
+        pos++;
+    }
+    free(drop);
+    g_W = W;
+    qsort(s->ghost, (size_t)s->nghost, sizeof(u64) * W, cmp_ghost);
+    s->nrows = pos;
+    s->off[L + 1] = pos;
+    for (int64_t t = 0; t < s->nrows; t++) s->sorted[t] = t;
+    g_rows = s->rows;
+    qsort(s->sorted, (size_t)s->nrows, sizeof(int64_t), cmp_cand);
+    return cut;
+}
+
+/* Beam search for an upper bound R >= r: the inverse BFS of Alg. 1 from the
+ * singletons (preimages, letter-major keys, duplicates as in the plain
+ * search), every new level cut to its `beam` largest sets (side_cut), until
+ * a level holds Q.  R is that depth and the word traced from the first such
+ * set (least key) is a reset word of length R.  Which sets the cut keeps is
+ * not fixed by the paper (it cites the method): the largest, as a set
+ * closer to Q in size.  With a beam at least as large as every level, this
+ * is the plain search run on the inverse side only, so R = r and the word
+ * is the lex-least one.  stats_out (4 entries, may be NULL): steps, sets
+ * kept, sets cut, largest level after the cut.  ORC_ELIMIT: a level became
+ * empty (the cut can lead into a dead end) or max_steps passed. */
+int orc_beam(int n, int k, const int32_t *delta, int64_t beam, int max_steps,
+             int32_t *R, uint8_t *word, int64_t word_cap, int64_t *stats_out) {
+    int rc = check_input(n, k, delta);
+    if (rc) return rc;
+    if (beam < 1 || !R) return ORC_EINVAL;
+    rc = orc_is_synchronizing(n, k, delta);
+    if (rc < 0) return rc;
+    if (rc == 0) return ORC_ENOTSYNC;
+    int64_t st[4] = {0, 0, 0, 0};
+    if (n == 1) {
+        *R = 0;
+        if (stats_out) memcpy(stats_out, st, sizeof st);
+        return ORC_OK;
+    }
+    const int W = nwords(n);
+    u64 *init = calloc((size_t)n * W, sizeof(u64));
+    if (!init) return ORC_ENOMEM;
+    for (int q = 0; q < n; q++) setbit(init + (int64_t)q * W, q);
+    Side B;
+    rc = side_init(&B, W, init, n);
+    free(init);
+    int out = ORC_ELIMIT;
+    if (!rc) {
+        const int64_t cut0 = side_cut(&B, beam, n);   /* level 0 too, if n > beam */
+        if (cut0 < 0) out = (int)cut0;
+        else st[2] += cut0;
+    } else {
+        out = rc;
+    }
+    for (int step = 1; !rc && out == ORC_ELIMIT && step <= max_steps; step++) {
+        rc = step_inverse(&B, n, k, delta);
+        if (rc) { out = rc; break; }
+        const int L = B.nlev - 1;
+        if (level_size(&B, L) == 0) break;          /* dead end */
+        const int64_t cut = side_cut(&B, beam, n);
+        if (cut < 0) { out = (int)cut; break; }
+        st[0] = step;
+        st[1] += level_size(&B, L);
+        st[2] += cut;
+        if (level_size(&B, L) > st[3]) st[3] = level_size(&B, L);
+        for (int64_t j = 0; j < level_size(&B, L); j++) {
+            if (popcount_set(level_row(&B, L, j), W) != n) continue;
+            *R = step;
+            out = ORC_OK;
+            if (word) {
+                if (word_cap < step) out = ORC_EWORDCAP;
+                else trace_inverse(&B, L, j, word);
+            }
+            break;
+        }
+    }
+    side_free(&B);
+    if (stats_out) memcpy(stats_out, st, sizeof st);
+    return out;
 }
 
 /* orc_bidir with every new level self-reduced (side_reduce) */

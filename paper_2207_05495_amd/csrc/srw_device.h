@@ -259,6 +259,38 @@ struct TransposeDesc {
     u64 *YT, *YTt, *Ysig;
 };
 
+// Beam search (CutOff-IBFS) of one automaton, run by one block from start
+// to end (k_beam): inverse steps from the singletons, every new level cut to
+// its `beam` largest sets.  Every distinct set generated is stored (it stays
+// visited); level L holds rows lev[3L] .. lev[3L]+lev[3L+1]-1 (the kept sets,
+// in key order), then its cut sets up to lev[3L+2].
+struct BeamState;
+struct BeamDesc {
+    int32_t n, k, W, max_lev;  // max_lev: levels the lev array holds (the step limit + 1)
+    const uint16_t *delta;     // delta[a*n + q]
+    int64_t beam;              // sets kept per level
+    u64 *rows;                 // stored sets, rows_cap of them
+    u32 *par;                  // key of each stored set (0xFFFFFFFF on level 0)
+    int64_t rows_cap;
+    u64 *tab;                  // visited hash set, at least 2 * rows_cap slots, cleared
+    u64 tab_mask;
+    u64 *cand;                 // candidates of a step, cand_cap >= k * beam (and >= n)
+    u32 *cslot;
+    int64_t cand_cap;
+    int64_t *lev;              // 3 * max_lev entries
+    uint8_t *word;             // max_lev - 1 letters
+    int64_t max_ticks;         // stop after this many wall_clock64 ticks (0: no limit)
+    BeamState *st;
+};
+struct BeamState {
+    int32_t status;            // 1 Q reached, 2 a level became empty, 3 rows or levels ran out, 4 deadline
+    int32_t R;                 // with status 1: the depth of Q (the word is in BeamDesc::word)
+    int32_t nlev;              // levels stored (level 0 included)
+    int32_t pad;
+    int64_t nrows;             // sets stored
+    int64_t candidates, kept, cut;   // over the steps run
+};
+
 struct TraceDesc {
     const u32 *par_f;
     const int64_t *off_f;      // level offsets of the forward side

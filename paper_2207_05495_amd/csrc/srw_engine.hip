@@ -47,6 +47,7 @@ hipError_t launch_rehash(const RehashDesc *, const int64_t *, int, int64_t, hipS
 hipError_t launch_fill(u64 *, int64_t, u64, hipStream_t);
 hipError_t launch_clear_tables(const RehashDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_trace(const TraceDesc *, int, hipStream_t);
+hipError_t launch_beam(const BeamDesc *, int, int, hipStream_t);
 hipError_t launch_sort(const SortDesc *, const int64_t *const[3], const int64_t[3], int, hipStream_t);
 
 // ------------------------------------------------------------------ errors
@@ -1335,8 +1336,159 @@ class Engine {
     }
     hipStream_t stream() const { return stream_; }
 
+    // Beam searches (k_beam), a block per automaton, in groups whose buffers
+    // fit the budget.  A search that runs out of rows, candidates or levels
+    // is run again with four times the room, up to kBeamTries times.
+    struct BeamJob {
+        int n = 0, k = 0;
+        const int32_t *delta = nullptr;
+        int64_t width = 0;
+        int64_t index = -1;
+        int status = 1;            // 1: not run yet
+        int32_t R = -1;
+        std::vector<uint8_t> word;
+        int64_t rows_cap = 0, max_lev = 0;
+        int64_t stats[3] = {0, 0, 0};   // candidates, kept, cut
+    };
+    static constexpr int kBeamTries = 4;
+    // rows and candidates of one search at most: its hash table then stays
+    // below 2^31 slots (slot positions are 32-bit)
+    static constexpr int64_t kBeamMaxRows = (int64_t)1 << 28;
+    static constexpr int kBeamGroup = 256;
+
+    void beam(std::vector<BeamJob *> &jobs) {
+        HIPCHK(hipSetDevice(device_));
+        for (BeamJob *j : jobs) {
+            const int64_t wk = std::min<int64_t>(j->width, (int64_t)1 << 24);
+            j->rows_cap = std::min<int64_t>(std::max<int64_t>(65536, 32 * (int64_t)j->k * wk + j->n),
+                                            (int64_t)1 << 22);
+            j->max_lev = std::min<int64_t>((int64_t)j->n * j->n + 2, 4096);
+        }
+        for (int attempt = 0; attempt < kBeamTries; ++attempt) {
+            std::vector<BeamJob *> todo;
+            for (BeamJob *j : jobs)
+                if (j->status == 1) todo.push_back(j);
+            if (todo.empty()) break;
+            std::stable_sort(todo.begin(), todo.end(), [](BeamJob *a, BeamJob *b) {
+                return (a->n + 63) / 64 < (b->n + 63) / 64;
+            });
+            for (size_t i0 = 0; i0 < todo.size(); i0 += kBeamGroup) {
+                std::vector<BeamJob *> grp(todo.begin() + i0,
+                                           todo.begin() + std::min(todo.size(), i0 + kBeamGroup));
+                beam_group(grp);
+            }
+            for (BeamJob *j : todo)
+                if (j->status == 1) {          // out of room: more of it next time
+                    j->rows_cap = std::min<int64_t>(4 * j->rows_cap, kBeamMaxRows);
+                    j->max_lev = std::min<int64_t>(4 * j->max_lev, (int64_t)1 << 20);
+                }
+        }
+        for (BeamJob *j : jobs)
+            if (j->status == 1) j->status = SRW_ENOMEM;
+    }
+
   private:
     static size_t align8(size_t x) { return (x + 7) & ~(size_t)7; }
+
+    // one group of beam searches: buffers, one launch per set width, results
+    void beam_group(std::vector<BeamJob *> &grp) {
+        const int cnt = (int)grp.size();
+        std::vector<BeamDesc> D(cnt);
+        std::vector<void *> blocks;
+        auto A = [&](size_t bytes) -> void * {
+            void *q = pool_->alloc(bytes);
+            if (q) blocks.push_back(q);
+            return q;
+        };
+        char *dst = (char *)A(sizeof(BeamState) * (size_t)cnt);
+        BeamDesc *dd = (BeamDesc *)A(sizeof(BeamDesc) * (size_t)cnt);
+        // every transition table of the group in one upload
+        std::vector<int64_t> doff(cnt + 1, 0);
+        for (int i = 0; i < cnt; ++i) doff[i + 1] = doff[i] + (int64_t)grp[i]->n * grp[i]->k;
+        std::vector<uint16_t> d16((size_t)doff[cnt]);
+        for (int i = 0; i < cnt; ++i)
+            for (int64_t t = 0; t < doff[i + 1] - doff[i]; ++t) d16[(size_t)(doff[i] + t)] = (uint16_t)grp[i]->delta[t];
+        uint16_t *dl = (uint16_t *)A(d16.size() * 2);
+        bool ok = dst && dd && dl;
+        for (int i = 0; i < cnt && ok; ++i) {
+            BeamJob *j = grp[i];
+            const int W = (j->n + 63) / 64;
+            BeamDesc &b = D[i];
+            memset(&b, 0, sizeof b);
+            b.n = j->n;
+            b.k = j->k;
+            b.W = W;
+            b.max_lev = (int32_t)j->max_lev;
+            b.beam = j->width;
+            b.rows_cap = j->rows_cap;
+            b.cand_cap = std::min<int64_t>(kBeamMaxRows, std::max<int64_t>(
+                j->n, (int64_t)j->k * std::min<int64_t>(j->width, j->rows_cap)));
+            int64_t slots = 1;
+            while (slots < 2 * (b.rows_cap + b.cand_cap)) slots <<= 1;
+            b.tab_mask = (u64)(slots - 1);
+            b.rows = (u64 *)A((size_t)b.rows_cap * W * 8);
+            b.par = (u32 *)A((size_t)b.rows_cap * 4);
+            b.tab = (u64 *)A((size_t)slots * 8);
+            b.cand = (u64 *)A((size_t)b.cand_cap * W * 8);
+            b.cslot = (u32 *)A((size_t)b.cand_cap * 4);
+            b.lev = (int64_t *)A((size_t)j->max_lev * 3 * 8);
+            b.word = (uint8_t *)A((size_t)j->max_lev);
+            b.st = (BeamState *)(dst + sizeof(BeamState) * (size_t)i);
+            if (opt.deadline_ms > 0) b.max_ticks = std::max<int64_t>(1, (int64_t)(opt.deadline_ms * wall_khz_));
+            ok = b.rows && b.par && b.tab && b.cand && b.cslot && b.lev && b.word;
+            if (!ok) break;
+            b.delta = dl + doff[i];
+            HIPCHK(launch_fill(b.tab, slots, kEmpty, stream_));
+        }
+        if (!ok) {
+            // no room for the whole group: halve it (one automaton that does
+            // not fit ends with SRW_ENOMEM)
+            HIPCHK(hipStreamSynchronize(stream_));
+            for (void *q : blocks) pool_->free(q);
+            if (cnt == 1) {
+                grp[0]->status = SRW_ENOMEM;
+                return;
+            }
+            std::vector<BeamJob *> a(grp.begin(), grp.begin() + cnt / 2), b(grp.begin() + cnt / 2, grp.end());
+            beam_group(a);
+            beam_group(b);
+            return;
+        }
+        HIPCHK(hipMemcpyAsync(dl, d16.data(), d16.size() * 2, hipMemcpyHostToDevice, stream_));
+        HIPCHK(hipMemcpyAsync(dd, D.data(), sizeof(BeamDesc) * (size_t)cnt, hipMemcpyHostToDevice, stream_));
+        for (int i0 = 0; i0 < cnt;) {
+            int i1 = i0;
+            const int W = D[i0].W;
+            while (i1 < cnt && D[i1].W == W) ++i1;
+            HIPCHK(launch_beam(dd + i0, i1 - i0, W, stream_));
+            i0 = i1;
+        }
+        std::vector<BeamState> S(cnt);
+        HIPCHK(hipMemcpyAsync(S.data(), dst, sizeof(BeamState) * (size_t)cnt, hipMemcpyDeviceToHost, stream_));
+        HIPCHK(hipStreamSynchronize(stream_));
+        for (int i = 0; i < cnt; ++i) {
+            BeamJob *j = grp[i];
+            const BeamState &t = S[i];
+            j->stats[0] = t.candidates;
+            j->stats[1] = t.kept;
+            j->stats[2] = t.cut;
+            if (t.status == 1) {
+                j->R = t.R;
+                j->word.resize((size_t)t.R);
+                if (t.R > 0)
+                    HIPCHK(hipMemcpy(j->word.data(), D[i].word, (size_t)t.R, hipMemcpyDeviceToHost));
+                j->status = verify_word(j->n, j->k, j->delta, j->word.data(), t.R) ? SRW_OK : SRW_EINTERNAL;
+                if (j->status != SRW_OK) t_err = "beam word does not reset the automaton";
+            } else if (t.status == 2) {
+                j->status = SRW_ENOBOUND;
+            } else if (t.status == 4) {
+                j->status = SRW_ETIMEOUT;
+            } else {
+                j->status = 1;                   // out of room: again, larger
+            }
+        }
+        for (void *q : blocks) pool_->free(q);
+    }
 
     // the automata of this engine start with k_run_small (it keeps the side
     // rule of schedule 0 and the LDS-tile meet of one-block steps)
@@ -2090,6 +2242,68 @@ int srw_solve_batch(int32_t count, const int32_t *n, const int32_t *k, const int
         }
     }
     return SRW_OK;
+}
+
+int srw_beam_batch(int32_t count, const int32_t *n, const int32_t *k, const int64_t *delta_off,
+                   const int32_t *delta, const int64_t *width, int32_t *R, int32_t *status,
+                   const int64_t *word_off, uint8_t *words, const int64_t *word_cap) {
+    if (count < 0 || (count > 0 && (!n || !k || !delta_off || !delta || !width || !R || !status)))
+        return set_error(SRW_EINVAL, "null argument");
+    if (words && (!word_off || !word_cap)) return set_error(SRW_EINVAL, "words without offsets");
+    Context &x = ctx();
+    std::lock_guard<std::mutex> g(x.mu);
+    std::vector<Engine::BeamJob> jobs((size_t)std::max(count, 0));
+    std::vector<Engine::BeamJob *> work;
+    for (int32_t i = 0; i < count; ++i) {
+        R[i] = -1;
+        const int32_t *d = delta + delta_off[i];
+        int rc = check_input(n[i], k[i], d);
+        if (!rc && width[i] < 1) rc = SRW_EINVAL;
+        if (rc) { status[i] = rc; continue; }
+        if (!is_synchronizing(n[i], k[i], d)) { status[i] = SRW_ENOTSYNC; continue; }
+        if (n[i] == 1) { status[i] = SRW_OK; R[i] = 0; continue; }
+        Engine::BeamJob &j = jobs[(size_t)i];
+        j.n = n[i];
+        j.k = k[i];
+        j.delta = d;
+        j.width = width[i];
+        j.index = i;
+        work.push_back(&j);
+    }
+    if (!work.empty()) {
+        try {
+            engine_locked(x)->beam(work);
+        } catch (const HipFailure &f) {
+            const bool oom = f.e == hipErrorOutOfMemory;
+            for (Engine::BeamJob *j : work)
+                if (j->status == 1) j->status = oom ? SRW_ENOMEM : SRW_EDEVICE;
+            x.eng.reset();
+            if (!oom) {
+                for (Engine::BeamJob *j : work) status[j->index] = j->status;
+                return device_error(f);
+            }
+        }
+    }
+    for (Engine::BeamJob *j : work) {
+        const int i = (int)j->index;
+        status[i] = j->status;
+        R[i] = j->status == SRW_OK ? j->R : -1;
+        if (j->status == SRW_OK && words) {
+            if (word_cap[i] < j->R) status[i] = SRW_EWORDCAP;
+            else memcpy(words + word_off[i], j->word.data(), (size_t)j->R);
+        }
+    }
+    return SRW_OK;
+}
+
+int srw_beam(int32_t n, int32_t k, const int32_t *delta, int64_t width, int32_t *R, uint8_t *word,
+             int64_t word_cap) {
+    if (!R) return set_error(SRW_EINVAL, "R is NULL");
+    const int64_t off = 0;
+    int32_t st = SRW_OK;
+    int rc = srw_beam_batch(1, &n, &k, &off, delta, &width, R, &st, word ? &off : nullptr, word,
+                            word ? &word_cap : nullptr);
+    return rc ? rc : st;
 }
 
 int srw_solve(int32_t n, int32_t k, const int32_t *delta, int32_t *r, uint8_t *word, int64_t word_cap) {

@@ -793,20 +793,26 @@ __device__ u32 meet_chunk_core(const CONST_AS StepDesc &d, int64_t c, int64_t gi
             for (int w = 0; w < W; ++w) slice[64 * w + lane] = d.YTt[tt * 64 * W + 64 * w + lane];
             wave_sync_lds();
             if (done) continue;
+            // the states of each X, by 32-bit halves, two columns a round
+            // (the second repeats the first when the half has one left); a
+            // lane stops once M is empty, the wave once every lane has
             u64 M = mc;
-            bool alive = true;
 #pragma unroll
-            for (int w = 0; w < W; ++w) {
-                if (!alive) break;
-                u64 b = x[w];
+            for (int h = 0; h < 2 * W; ++h) {
+                u32 b = M ? (u32)(x[h >> 1] >> (32 * (h & 1))) : 0u;
+                const int base = 32 * h;
                 while (b) {
-                    const int q = 64 * w + lowest_bit(b);
+                    const int q0 = base + (int)__builtin_ctz(b);
                     b &= b - 1;
-                    M &= slice[q];
-                    if (M == 0) { alive = false; break; }
+                    const int q1 = b ? base + (int)__builtin_ctz(b) : q0;
+                    if (CNT) nops += q1 != q0 ? 4 : 2;
+                    b &= b - 1;                   // (stays 0 at 0)
+                    M &= slice[q0] & slice[q1];
+                    if (M == 0) b = 0;
                 }
-                if (CNT) nops += 2 * (u32)(__popcll(x[w]) - __popcll(b));
+                if (__ballot(M != 0) == 0) break;
             }
+            const bool alive = M != 0;
             if (alive) {
                 if (!Yidx) {
                     atomicMin(d.res + 1, ((u64)orig << 32) | (u64)(tt * 64 + lowest_bit(M)));
@@ -1533,6 +1539,214 @@ __global__ void __launch_bounds__(kBS) k_run_small(const RunDesc *descs, u64 *op
     }
 }
 
+// ---------------------------------------------------------- beam search
+
+__device__ __forceinline__ u32 set_card(const u64 *row, int W) {
+    u32 c = 0;
+    for (int w = 0; w < W; ++w) c += (u32)__popcll(row[w]);
+    return c;
+}
+
+// One block runs the whole beam search of one automaton (BeamDesc).  Each
+// step makes candidates -- at depth 0 the singletons (key q), later the
+// preimages of the kept sets of the current level under every letter (key
+// a * m + i, letter-major, as on the inverse side of the plain search) --
+// and removes duplicates in the automaton's hash set with the same device
+// functions as the plain search (least key among equal candidates; sets
+// stored before, kept or cut, and empty sets dropped).  Then the cut: with
+// U new sets and U > beam, c* is the cardinality of the beam-th largest;
+// the sets above c* are kept, and those at c* in key order until the beam
+// is full.  Kept sets are stored first, in key order, then the cut ones,
+// and their hash slots are pointed at the stored rows.  The search stops at
+// the first level that keeps Q (the full set) and traces the word back
+// through the keys, at an empty level, when rows or levels run out, or at
+// the deadline.
+template <int W>
+__device__ void beam_w(const CONST_AS BeamDesc &b, StepDesc &sd, u64 *lds, u32 *wsum, u32 *hist) {
+    __shared__ int64_t s_nrows, s_start, s_m, s_U, s_K;
+    __shared__ int s_nlev, s_go, s_depth;
+    __shared__ u32 s_cstar, s_quota, s_qbest;
+    BeamState *st = b.st;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = b.n;
+    const u64 t_start = wall_clock64();
+    if (tid == 0) {
+        s_nrows = 0;
+        s_nlev = 0;
+        s_start = 0;
+        s_m = 0;
+        s_depth = 0;
+        st->status = 0;
+        st->R = -1;
+        st->candidates = st->kept = st->cut = 0;
+        sd.n = n;
+        sd.k = b.k;
+        sd.W = W;
+        sd.dir = 1;
+        sd.delta = b.delta;
+        sd.cand = b.cand;
+        sd.cslot = b.cslot;
+        sd.tab = b.tab;
+        sd.tab_mask = b.tab_mask;
+        sd.vis_rows = b.rows;
+    }
+    __syncthreads();
+    for (;;) {
+        // candidates of this depth (they must fit the candidate buffer)
+        if (tid == 0) {
+            sd.m = s_m;
+            sd.par_rows = b.rows + s_start * W;
+            sd.C = s_depth == 0 ? (int64_t)n : s_m * b.k;
+            s_go = sd.C <= b.cand_cap;
+            if (!s_go) st->status = 3;
+        }
+        __syncthreads();
+        if (!s_go) break;
+        const int64_t C = sd.C;
+        if (s_depth == 0) {
+            for (int64_t g = tid; g < C; g += kBS)
+                for (int w = 0; w < W; ++w)
+                    b.cand[g * W + w] = (w == (int)(g >> 6)) ? 1ull << (g & 63) : 0ull;
+        } else {
+            const int64_t nb = (C + kBS - 1) / kBS;
+            for (int64_t lb = 0; lb < nb; ++lb) expand_w<W>(sd, lb, lds);
+        }
+        __syncthreads();
+        {
+            const int64_t nb = (C + kBS - 1) / kBS;
+            for (int64_t lb = 0; lb < nb; ++lb) insert_w<W>(sd, lb);
+        }
+        for (int c = tid; c <= n; c += kBS) hist[c] = 0;
+        __syncthreads();
+        // cardinalities of the new sets
+        for (int64_t g = tid; g < C; g += kBS)
+            if (is_winner(sd, g)) atomicAdd(&hist[set_card(b.cand + g * W, W)], 1u);
+        __syncthreads();
+        if (tid == 0) {
+            int64_t U = 0;
+            for (int c = 0; c <= n; ++c) U += hist[c];
+            s_U = U;
+            s_qbest = 0xFFFFFFFFu;
+            if (U > b.beam) {
+                int64_t above = 0;
+                int c = n;
+                while (above + hist[c] < b.beam) above += hist[c--];
+                s_cstar = (u32)c;
+                s_quota = (u32)(b.beam - above);
+                s_K = b.beam;
+            } else {
+                s_cstar = 0;
+                s_quota = 0xFFFFFFFFu;
+                s_K = U;
+            }
+            int status = 0;
+            if (U == 0) status = 2;
+            else if (s_nrows + U > b.rows_cap || s_nlev + 1 >= b.max_lev) status = 3;
+            else if (b.max_ticks > 0 && (int64_t)(wall_clock64() - t_start) > b.max_ticks) status = 4;
+            s_go = status == 0;
+            if (status) st->status = status;
+            st->candidates += C;
+        }
+        __syncthreads();
+        if (!s_go) break;
+        // keep or cut every new set, in key order; store kept sets first
+        const bool all = s_U <= b.beam;
+        const u32 cstar = s_cstar, quota = s_quota;
+        const int64_t base = s_nrows, K = s_K;
+        u32 kept_run = 0, cut_run = 0, tie_run = 0;
+        for (int64_t g0 = 0; g0 < C; g0 += kBS) {
+            const int64_t g = g0 + tid;
+            const bool f = g < C && is_winner(sd, g);
+            const u32 c = f ? set_card(b.cand + g * W, W) : 0u;
+            const bool tie = f && !all && c == cstar;
+            const u64 tmask = __ballot(tie);
+            if (lane == 0) wsum[wave] = (u32)__popcll(tmask);
+            __syncthreads();
+            u32 tpre = 0, ttot = 0;
+#pragma unroll
+            for (int w = 0; w < kBS / 64; ++w) {
+                if (w < wave) tpre += wsum[w];
+                ttot += wsum[w];
+            }
+            const bool keep = f && (all || c > cstar || (tie && tie_run + tpre + lanes_below(tmask) < quota));
+            const bool cutf = f && !keep;
+            const u64 kmask = __ballot(keep), cmask = __ballot(cutf);
+            __syncthreads();                       // wsum is read
+            if (lane == 0) {
+                wsum[wave] = (u32)__popcll(kmask);
+                wsum[kBS / 64 + wave] = (u32)__popcll(cmask);
+            }
+            __syncthreads();
+            u32 kpre = 0, ktot = 0, cpre = 0, ctot = 0;
+#pragma unroll
+            for (int w = 0; w < kBS / 64; ++w) {
+                if (w < wave) { kpre += wsum[w]; cpre += wsum[kBS / 64 + w]; }
+                ktot += wsum[w];
+                ctot += wsum[kBS / 64 + w];
+            }
+            if (f) {
+                const u32 kp = kept_run + kpre + lanes_below(kmask);
+                const u32 cp = cut_run + cpre + lanes_below(cmask);
+                const int64_t row = keep ? base + kp : base + K + cp;
+#pragma unroll
+                for (int w = 0; w < W; ++w) b.rows[row * W + w] = b.cand[g * W + w];
+                b.par[row] = (u32)g;
+                const u32 sl = b.cslot[g];
+                const u64 e = b.tab[sl];
+                b.tab[sl] = (e & 0xFFFFFFFF00000000ull) | (u64)(u32)row;
+                if (keep && (int)c == n) atomicMin(&s_qbest, kp);
+            }
+            kept_run += ktot;
+            cut_run += ctot;
+            tie_run += ttot;
+            __syncthreads();
+        }
+        if (tid == 0) {
+            const int L = s_nlev;
+            b.lev[3 * L] = base;
+            b.lev[3 * L + 1] = K;
+            b.lev[3 * L + 2] = base + s_U;
+            st->kept += K;
+            st->cut += s_U - K;
+            s_start = base;
+            s_m = K;
+            s_nrows = base + s_U;
+            s_nlev = L + 1;
+            if (s_qbest != 0xFFFFFFFFu) {
+                // Q at depth L: the letters back through the keys
+                int64_t j = s_qbest;
+                for (int dd = L; dd > 0; --dd) {
+                    const u32 g = b.par[b.lev[3 * dd] + j];
+                    const int64_t m = b.lev[3 * (dd - 1) + 1];
+                    b.word[L - dd] = (uint8_t)(g / m);
+                    j = (int64_t)(g % m);
+                }
+                st->R = L;
+                st->status = 1;
+                s_go = 0;
+            }
+            s_depth = s_depth + 1;
+        }
+        __syncthreads();
+        if (!s_go) break;
+    }
+    if (tid == 0) {
+        st->nlev = s_nlev;
+        st->nrows = s_nrows;
+    }
+}
+
+// one block per automaton; one launch per set width W (all its automata)
+template <int W>
+__global__ void __launch_bounds__(kBS) k_beam(const BeamDesc *descs) {
+    __shared__ u64 lds[kMaxW * kBS];       // expansion rows
+    __shared__ u32 wsum[2 * (kBS / 64)];
+    __shared__ u32 hist[kMaxW * 64 + 1];
+    __shared__ StepDesc sd;
+    const CONST_AS BeamDesc &b = cref(descs + blockIdx.x);
+    beam_w<W>(b, sd, lds, wsum, hist);
+}
+
 // ------------------------------------------------- sort of forward levels
 
 // zero the state histogram and the key bins
@@ -1768,6 +1982,12 @@ hipError_t launch_copy(const CopyDesc *d, const int64_t *pre, int nseg, int64_t 
 hipError_t launch_run_small(const RunDesc *d, int count, int W, u64 *ops, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     SRW_SWITCH_W(W, hipLaunchKernelGGL(k_run_small<W>, dim3((unsigned)count), dim3(kBS), 0, st, d, ops));
+    return launch_checked();
+}
+// count automata, all with W words per set
+hipError_t launch_beam(const BeamDesc *d, int count, int W, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    SRW_SWITCH_W(W, hipLaunchKernelGGL(k_beam<W>, dim3((unsigned)count), dim3(kBS), 0, st, d));
     return launch_checked();
 }
 hipError_t launch_step_small(const StepDesc *d, const int32_t *segs, int count, u64 *ops, hipStream_t st) {

@@ -18,13 +18,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsrw.so")
 
 OK = 0
-EINVAL, ENOTSYNC, EUNSUPPORTED, ENOMEM, EWORDCAP, EDEVICE, ETIMEOUT, EINTERNAL = (
-    -1, -2, -3, -4, -5, -6, -7, -8)
+EINVAL, ENOTSYNC, EUNSUPPORTED, ENOMEM, EWORDCAP, EDEVICE, ETIMEOUT, EINTERNAL, ENOBOUND = (
+    -1, -2, -3, -4, -5, -6, -7, -8, -9)
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOTSYNC", -3: "EUNSUPPORTED", -4: "ENOMEM",
-                -5: "EWORDCAP", -6: "EDEVICE", -7: "ETIMEOUT", -8: "EINTERNAL"}
+                -5: "EWORDCAP", -6: "EDEVICE", -7: "ETIMEOUT", -8: "EINTERNAL", -9: "ENOBOUND"}
 
 # every symbol include/srw.h declares
-EXPORTS = ("srw_solve", "srw_solve_batch", "srw_solve_noalloc", "srw_check_sync", "srw_verify",
+EXPORTS = ("srw_solve", "srw_solve_batch", "srw_solve_noalloc", "srw_beam", "srw_beam_batch",
+           "srw_check_sync", "srw_verify",
            "srw_server_create", "srw_server_submit", "srw_server_poll",
            "srw_server_pending", "srw_server_destroy", "srw_set_allocator",
            "srw_set_stream", "srw_set_option", "srw_get_stats", "srw_reset_stats",
@@ -112,6 +113,10 @@ def load(path: str = LIB_PATH):
     L.srw_solve_noalloc.argtypes = L.srw_solve.argtypes
     L.srw_solve_batch.argtypes = [ctypes.c_int32, i32p, i32p, i64p, i32p, i32p, i32p,
                                   i64p, u8p, i64p]
+    L.srw_beam.argtypes = [ctypes.c_int32, ctypes.c_int32, i32p, ctypes.c_int64, i32p, u8p,
+                           ctypes.c_int64]
+    L.srw_beam_batch.argtypes = [ctypes.c_int32, i32p, i32p, i64p, i32p, i64p, i32p, i32p,
+                                 i64p, u8p, i64p]
     L.srw_check_sync.argtypes = [ctypes.c_int32, ctypes.c_int32, i32p]
     L.srw_verify.argtypes = [ctypes.c_int32, ctypes.c_int32, i32p, u8p, ctypes.c_int64]
     L.srw_server_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(Config)]
@@ -302,6 +307,51 @@ def solve_batch(problems, want_words=True):
             w = [int(x) for x in words[woff[i]: woff[i] + r[i]]]
         out.append((int(st[i]), int(r[i]), w))
     return out
+
+
+def beam_batch(problems, want_words=True):
+    """problems: list of (n, k, delta, width).  Beam-search upper bounds
+    (srw_beam_batch): a list of (status, R, word)."""
+    cnt = len(problems)
+    ns = np.array([p[0] for p in problems], dtype=np.int32)
+    ks = np.array([p[1] for p in problems], dtype=np.int32)
+    ws = np.array([p[3] for p in problems], dtype=np.int64)
+    sizes = np.array([p[0] * p[1] for p in problems], dtype=np.int64)
+    doff = np.zeros(cnt, dtype=np.int64)
+    if cnt:
+        doff[1:] = np.cumsum(sizes)[:-1]
+    delta = np.ascontiguousarray(np.concatenate([_delta(p[2]) for p in problems])
+                                 if cnt else np.zeros(1, np.int32))
+    R = np.full(cnt, -1, dtype=np.int32)
+    st = np.zeros(cnt, dtype=np.int32)
+    caps = np.array([1 << 16 for _ in problems], dtype=np.int64)
+    woff = np.arange(cnt, dtype=np.int64) * (1 << 16)
+    words = np.zeros(max(1, cnt << 16), dtype=np.uint8) if want_words else np.zeros(1, np.uint8)
+    rc = load().srw_beam_batch(cnt, _ptr(ns, ctypes.c_int32), _ptr(ks, ctypes.c_int32),
+                               _ptr(doff, ctypes.c_int64), _ptr(delta, ctypes.c_int32),
+                               _ptr(ws, ctypes.c_int64), _ptr(R, ctypes.c_int32),
+                               _ptr(st, ctypes.c_int32),
+                               _ptr(woff, ctypes.c_int64) if want_words else None,
+                               _ptr(words, ctypes.c_uint8) if want_words else None,
+                               _ptr(caps, ctypes.c_int64) if want_words else None)
+    if rc:
+        raise SrwError(rc, "beam_batch")
+    out = []
+    for i in range(cnt):
+        w = None
+        if want_words and st[i] == OK:
+            w = [int(x) for x in words[woff[i]: woff[i] + R[i]]]
+        out.append((int(st[i]), int(R[i]), w))
+    return out
+
+
+def beam(n, k, delta, width):
+    """Beam-search upper bound of one automaton: (R, word); raises on any
+    status but SRW_OK."""
+    st, R, w = beam_batch([(n, k, delta, width)])[0]
+    if st != OK:
+        raise SrwError(st, "beam")
+    return R, w
 
 
 def get_stats() -> dict:

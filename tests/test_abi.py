@@ -123,6 +123,20 @@ def test_noalloc_host_checks_come_first():
     assert srw.solve_noalloc(1, 2, [0, 0]) == (0, [])
 
 
+def test_beam_host_checks_come_first():
+    """srw_beam_batch answers bad input, non-synchronizing input and n = 1
+    on the host, per automaton; a search that needs the GPU gets
+    SRW_EDEVICE here (no GPU)."""
+    res = srw.beam_batch([(3, 1, [0, 1, 5], 4), (3, 2, [1, 2, 0, 0, 2, 1], 4), (1, 2, [0, 0], 4),
+                          (4, 2, I.cerny(4), 0)])
+    assert [x[0] for x in res] == [srw.EINVAL, srw.ENOTSYNC, srw.OK, srw.EINVAL]
+    assert res[2] == (srw.OK, 0, [])
+    if not gpu_present():
+        with pytest.raises(srw.SrwError) as e:
+            srw.beam_batch([(4, 2, I.cerny(4), 4)])
+        assert e.value.code == srw.EDEVICE
+
+
 def test_estimator_inputs_generator_is_deterministic():
     a = I.random_automaton(100, 3, 12345, 2)
     b = I.random_automaton(100, 3, 12345, 2)

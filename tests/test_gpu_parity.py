@@ -853,3 +853,49 @@ def test_server_deadline_then_recovery():
                 break
     assert got[7]["status"] == srw.OK
     assert (got[7]["r"], got[7]["word"]) == (39 ** 2, I.cerny_word(40))
+
+
+# ------------------------------------------------------ beam search (upper bound)
+
+def beam_cases():
+    cs = []
+    for i, (n, k) in enumerate([(8, 2), (20, 2), (33, 3), (64, 2), (65, 3), (100, 2), (130, 2),
+                                (200, 3), (300, 2), (450, 2)]):
+        d, _ = I.first_synchronizing(n, k, I.member_seed(I.BASE_SEED ^ 0xBEA, i), O.is_synchronizing)
+        cs.append((n, k, d))
+    return cs
+
+
+def test_beam_matches_the_oracle():
+    """srw_beam_batch against the oracle's beam search (orc_beam): the same
+    R and word, or both ending at an empty level, over widths from 1 to
+    n log n, set widths 1..8, in one batch."""
+    import math
+    probs, want = [], []
+    for n, k, d in beam_cases():
+        for width in sorted({1, 4, 16, 64, int(n * math.log(n)) + 1}):
+            R, w, _ = O.beam(n, k, d, width)
+            probs.append((n, k, d, width))
+            want.append((srw.OK, R, list(w)) if R is not None else (srw.ENOBOUND, -1, None))
+    say("beam batch", len(probs))
+    got = srw.beam_batch(probs)
+    for p, g, w in zip(probs, got, want):
+        assert g == w, (p[0], p[1], p[3])
+
+
+def test_unbounded_beam_is_exact():
+    """A width above every level size makes the beam search the plain
+    inverse search: R = r and the word srw_solve returns (and the oracle)."""
+    for n, k, d in beam_cases()[:6] + [(n, 2, I.cerny(n)) for n in (5, 17, 40)]:
+        say("beam exact", n, k)
+        want = oracle_rw(n, k, d)
+        assert srw.beam(n, k, d, 1 << 40) == want, (n, k)
+
+
+def test_beam_edges():
+    st = srw.beam_batch([(1, 2, np.zeros(2, np.int32), 3), (4, 2, np.array([0, 1, 2, 3, 0, 1, 2, 3], np.int32), 8),
+                         (3, 1, np.array([1, 2, 0], np.int32), 2), (9, 2, I.cerny(9), 0)])
+    assert st[0] == (srw.OK, 0, [])
+    assert st[1][0] == srw.ENOTSYNC and st[2][0] == srw.ENOTSYNC
+    assert st[3][0] == srw.EINVAL
+    assert srw.beam_batch([]) == []

@@ -256,6 +256,9 @@ typedef struct srw_stats {
                                   (full row tests), 5 tiles tested column by column,
                                   6 tiles scanned; 7 launches of the meet against an
                                   inverse level in buckets (counted always) */
+    int64_t meet_b_launches_w[8];/* of those bucketed meet launches, per set width */
+    double meet_b_ms_w[8];     /* their own time, with "profile" 1 or 2 */
+    int64_t meet_b_ops_w[8];   /* their share of meet_ops_w, with "profile" 1 */
 } srw_stats;
 /* kernel classes: 0 expand (and whole one-block steps), 1 insert, 2 count+scan+compact, 3 meet
  * preparation (transpose of inverse levels, bucket sort of forward levels),

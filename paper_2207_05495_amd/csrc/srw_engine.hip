@@ -523,6 +523,7 @@ class Engine {
         wall_khz_ = khz > 0 ? (double)khz : 1e5;
         for (int c = 0; c < 16; ++c) HIPCHK(hipEventCreate(&ev_[c]));
         for (int c = 0; c < 2 * kMaxW; ++c) HIPCHK(hipEventCreate(&ev_meet_[c]));
+        for (int c = 0; c < 2 * kMaxW; ++c) HIPCHK(hipEventCreate(&ev_meetb_[c]));
         memset(&stats_, 0, sizeof stats_);
     }
     ~Engine() {
@@ -532,6 +533,7 @@ class Engine {
         pool_.reset();
         for (int c = 0; c < 16; ++c) (void)hipEventDestroy(ev_[c]);
         for (int c = 0; c < 2 * kMaxW; ++c) (void)hipEventDestroy(ev_meet_[c]);
+        for (int c = 0; c < 2 * kMaxW; ++c) (void)hipEventDestroy(ev_meetb_[c]);
         if (own_stream_) (void)hipStreamDestroy(own_stream_);
     }
 
@@ -546,9 +548,12 @@ class Engine {
             HIPCHK(hipMemcpyAsync(h, d_ops_, (kOpsWords + kMstatWords) * sizeof(u64), hipMemcpyDeviceToHost, stream_));
             HIPCHK(hipStreamSynchronize(stream_));
             for (int w = 0; w < kMaxW; ++w) {
-                out.meet_ops_w[w] = 0;
-                for (int sl = 0; sl < kOpsSlots; ++sl)
-                    out.meet_ops_w[w] += (int64_t)h[((int64_t)w * kOpsSlots + sl) * kOpsStride];
+                out.meet_ops_w[w] = out.meet_b_ops_w[w] = 0;
+                for (int sl = 0; sl < kOpsSlots; ++sl) {
+                    const u64 *c = h + ((int64_t)w * kOpsSlots + sl) * kOpsStride;
+                    out.meet_b_ops_w[w] += (int64_t)c[1];
+                    out.meet_ops_w[w] += (int64_t)(c[0] + c[1]);
+                }
             }
             for (int c = 0; c < kMstatCounters - 1; ++c) {   // [7] is counted on the host
                 out.meet_work[c] = 0;
@@ -1094,9 +1099,17 @@ class Engine {
                 HIPCHK(launch_meet(dD, dpm, s0, s1, W, pm[s1] - pm[s0], opt.meet_grid, ys, ops, stream_));
             }
             if (bk_items > 0) {
+                // its own events and, in the counting build, its own word of
+                // each counter slot
+                if (opt.profile) {
+                    HIPCHK(hipEventRecord(ev_meetb_[2 * (W - 1)], stream_));
+                    meetb_used_[W - 1] = true;
+                }
                 HIPCHK(launch_meet_b(dD, s0, s1, W, std::min<int64_t>(ceil_div(bk_items, kBS / 64), kMeetQueueGrid),
-                                     ops, stream_));
+                                     ops ? ops + 1 : nullptr, stream_));
+                if (opt.profile) HIPCHK(hipEventRecord(ev_meetb_[2 * (W - 1) + 1], stream_));
                 stats_.meet_work[7]++;
+                stats_.meet_b_launches_w[W - 1]++;
             }
             if (opt.profile) HIPCHK(hipEventRecord(ev_meet_[2 * (W - 1) + 1], stream_));
             stats_.meet_launches_w[W - 1]++;
@@ -1975,6 +1988,14 @@ class Engine {
             stats_.meet_ms_w[w] += ms;
             meet_used_[w] = false;
         }
+        for (int w = 0; w < kMaxW; ++w) {
+            if (!meetb_used_[w]) continue;
+            float ms = 0;
+            HIPCHK(hipEventSynchronize(ev_meetb_[2 * w + 1]));
+            HIPCHK(hipEventElapsedTime(&ms, ev_meetb_[2 * w], ev_meetb_[2 * w + 1]));
+            stats_.meet_b_ms_w[w] += ms;
+            meetb_used_[w] = false;
+        }
     }
 
     int device_;
@@ -1982,8 +2003,9 @@ class Engine {
     Backing backing_;
     hipStream_t stream_ = nullptr, own_stream_ = nullptr;
     std::unique_ptr<Pool> pool_;
-    hipEvent_t ev_[16], ev_meet_[2 * kMaxW];
+    hipEvent_t ev_[16], ev_meet_[2 * kMaxW], ev_meetb_[2 * kMaxW];
     bool meet_used_[kMaxW] = {};
+    bool meetb_used_[kMaxW] = {};
     bool prof_used_[8] = {};
     Pinned pin_delta_, pin_step_, pin_res_, pin_trace_, pin_init_, pin_misc_, pin_clear_, pin_copy_, pin_run_;
     std::vector<CopyDesc> pend_copy_;

@@ -793,26 +793,20 @@ __device__ u32 meet_chunk_core(const CONST_AS StepDesc &d, int64_t c, int64_t gi
             for (int w = 0; w < W; ++w) slice[64 * w + lane] = d.YTt[tt * 64 * W + 64 * w + lane];
             wave_sync_lds();
             if (done) continue;
-            // the states of each X, by 32-bit halves, two columns a round
-            // (the second repeats the first when the half has one left); a
-            // lane stops once M is empty, the wave once every lane has
             u64 M = mc;
+            bool alive = true;
 #pragma unroll
-            for (int h = 0; h < 2 * W; ++h) {
-                u32 b = M ? (u32)(x[h >> 1] >> (32 * (h & 1))) : 0u;
-                const int base = 32 * h;
+            for (int w = 0; w < W; ++w) {
+                if (!alive) break;
+                u64 b = x[w];
                 while (b) {
-                    const int q0 = base + (int)__builtin_ctz(b);
+                    const int q = 64 * w + lowest_bit(b);
                     b &= b - 1;
-                    const int q1 = b ? base + (int)__builtin_ctz(b) : q0;
-                    if (CNT) nops += q1 != q0 ? 4 : 2;
-                    b &= b - 1;                   // (stays 0 at 0)
-                    M &= slice[q0] & slice[q1];
-                    if (M == 0) b = 0;
+                    M &= slice[q];
+                    if (M == 0) { alive = false; break; }
                 }
-                if (__ballot(M != 0) == 0) break;
+                if (CNT) nops += 2 * (u32)(__popcll(x[w]) - __popcll(b));
             }
-            const bool alive = M != 0;
             if (alive) {
                 if (!Yidx) {
                     atomicMin(d.res + 1, ((u64)orig << 32) | (u64)(tt * 64 + lowest_bit(M)));

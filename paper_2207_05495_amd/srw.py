@@ -50,11 +50,13 @@ class Stats(ctypes.Structure):
                 ("bytes_compact", ctypes.c_int64), ("peak_device_bytes", ctypes.c_int64),
                 ("meet_launches_w", ctypes.c_int64 * 8), ("meet_ms_w", ctypes.c_double * 8),
                 ("pair_words_w", ctypes.c_int64 * 8), ("meet_ops_w", ctypes.c_int64 * 8),
-                ("host_ms", ctypes.c_double * 4), ("meet_work", ctypes.c_int64 * 8)]
+                ("host_ms", ctypes.c_double * 4), ("meet_work", ctypes.c_int64 * 8),
+                ("meet_b_launches_w", ctypes.c_int64 * 8), ("meet_b_ms_w", ctypes.c_double * 8),
+                ("meet_b_ops_w", ctypes.c_int64 * 8)]
 
     def as_dict(self):
         arrays = ("launches", "ms", "meet_launches_w", "meet_ms_w", "pair_words_w", "meet_ops_w", "host_ms",
-                  "meet_work")
+                  "meet_work", "meet_b_launches_w", "meet_b_ms_w", "meet_b_ops_w")
         d = {f: getattr(self, f) for f, _ in self._fields_ if f not in arrays}
         d["launches"] = dict(zip(KERNEL_CLASSES, list(self.launches)))
         d["ms"] = dict(zip(KERNEL_CLASSES, list(self.ms)))
@@ -63,7 +65,9 @@ class Stats(ctypes.Structure):
                                    "signature_passes", "column_tiles", "tiles", "bucketed_launches"),
                                   list(self.meet_work)))
         d["meet_w"] = {w + 1: {"launches": self.meet_launches_w[w], "ms": self.meet_ms_w[w],
-                               "pair_words": self.pair_words_w[w], "ops": self.meet_ops_w[w]}
+                               "pair_words": self.pair_words_w[w], "ops": self.meet_ops_w[w],
+                               "b_launches": self.meet_b_launches_w[w], "b_ms": self.meet_b_ms_w[w],
+                               "b_ops": self.meet_b_ops_w[w]}
                        for w in range(8) if self.meet_launches_w[w]}
         return d
 

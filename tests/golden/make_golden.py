@@ -18,6 +18,10 @@ so a test can rebuild the exact automaton.
                                                    # 300 of the batch, at most 900 s of
                                                    # oracle time each (the rest recorded
                                                    # as unpinned)
+    python tests/golden/make_golden.py serve5 5 900 --resume
+                                                   # only the entries of the stored set
+                                                   # recorded as unpinned, with the new
+                                                   # budget; the others are kept
 """
 
 import json
@@ -104,20 +108,44 @@ def main():
     if sys.argv[1:2] == ["--one"]:
         print(json.dumps(solve_one(tuple(int(x) for x in sys.argv[2:5]))), flush=True)
         return
-    which = sys.argv[1] if len(sys.argv) > 1 else "rand256"
-    procs = int(sys.argv[2]) if len(sys.argv) > 2 else 6
-    budget = float(sys.argv[3]) if len(sys.argv) > 3 else None
+    resume = "--resume" in sys.argv
+    args = [a for a in sys.argv[1:] if a != "--resume"]
+    which = args[0] if args else "rand256"
+    procs = int(args[1]) if len(args) > 1 else 6
+    budget = float(args[2]) if len(args) > 2 else None
+    path = os.path.join(HERE, f"{which}.json")
     js = jobs(which)
+    old = {}
+    if resume:
+        with open(path) as f:
+            old = {(c["n"], c["k"], c["seed"]): c for c in json.load(f)["cases"]}
+        todo = [j for j in js if "unpinned" in old.get(j, {"unpinned": 1})]
+    else:
+        todo = js
+    got = {}
+
+    def write():
+        res = [got[j] if j in got else old[j] for j in js if j in got or j in old]
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump({"generator": "paper_2207_05495_amd.inputs (SplitMix64, first synchronizing attempt)",
+                       "oracle": "oracle/srw_oracle.c orc_bidir, Alg. 2 meet",
+                       "cases": res}, f, indent=1)
+        os.replace(tmp, path)
+        return res
+
+    # results are written as they come (a long run can be stopped and resumed)
     with Pool(procs) as p:
         if budget is None:
-            res = p.map(solve_one, js, chunksize=1)
+            it = p.imap_unordered(solve_one, todo, chunksize=1)
         else:
-            res = p.map(solve_bounded, [j + (budget,) for j in js], chunksize=1)
-    path = os.path.join(HERE, f"{which}.json")
-    with open(path, "w") as f:
-        json.dump({"generator": "paper_2207_05495_amd.inputs (SplitMix64, first synchronizing attempt)",
-                   "oracle": "oracle/srw_oracle.c orc_bidir, Alg. 2 meet",
-                   "cases": res}, f, indent=1)
+            it = p.imap_unordered(solve_bounded, [j + (budget,) for j in todo], chunksize=1)
+        for c in it:
+            got[(c["n"], c["k"], c["seed"])] = c
+            if resume:
+                write()
+            print(c["n"], c["k"], c.get("r"), c.get("oracle_s", c.get("unpinned")), flush=True)
+    res = write()
     print(path, [(c["n"], c["k"], c.get("r"), c.get("oracle_s")) for c in res])
 
 

@@ -56,6 +56,20 @@ def test_roofline_of_the_meet_uses_the_widest_time_width(monkeypatch):
     assert r["brute_force_lane_ops_per_launch"] == pytest.approx(1e12)
 
 
+def test_roofline_of_the_bucketed_meet_uses_its_own_launches(monkeypatch):
+    monkeypatch.setattr(bench, "measured_traffic", lambda w, k: None)
+    # width 8: 32 meet launches of which 25 bucketed, 90% of the time
+    stats = {"meet_w": {8: {"ms": 800.0, "launches": 32, "ops": 0, "pair_words": 3.2e13,
+                            "b_launches": 25, "b_ms": 750.0, "b_ops": 0}}}
+    counted = {8: {"ms": 900.0, "launches": 32, "ops": 1.3e12, "pair_words": 3.2e13,
+                   "b_launches": 25, "b_ms": 850.0, "b_ops": 1.25e12}}
+    r = bench.roofline(stats, cls_stats({"meet": 900.0}, {"meet": 32}, meet_w=counted), "wl")
+    assert r["kernel"] == "k_meet_b<8, false>" and r["launches"] == 25
+    assert r["per_launch_ms"] == pytest.approx(30.0)
+    # 5e10 lane-ops per launch in 30 ms
+    assert r["achieved"] == pytest.approx(5e10 / 0.03 / 1e12)
+
+
 def test_roofline_of_an_hbm_class():
     c = cls_stats({"expand": 10.0, "meet": 1.0}, {"expand": 5, "meet": 3}, bytes_expand=4e10)
     r = bench.roofline({"meet_w": {}}, c, "wl")

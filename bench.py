@@ -385,6 +385,12 @@ def serve_bench(args, srw):
                 got += len(s.poll(100000))
                 progress(f"capacity pass: {got}/{m} done")
             cap = got / (time.perf_counter() - t)
+        # the closed server's memory goes back to PyTorch's cache; hand it to
+        # the driver so that the next server's budget (a share of the free
+        # device memory) is not cut by it
+        import torch
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
         rate = 0.7 * cap
         print(f"capacity ~{cap:.2f}/s; arrival rate {rate:.2f}/s", file=sys.stderr, flush=True)
     gaps = rng.exponential(1.0 / rate, size=len(reqs))

@@ -415,6 +415,8 @@ def serve_bench(args, srw):
             progress(f"all submitted, completed {len(done)}/{len(reqs)}")
         elapsed = time.perf_counter() - t0
         pending = s.pending()
+        print(f"closing the server with {pending} requests pending (each lane ends its running step)",
+              file=sys.stderr, flush=True)
     ok = [x for x in done.values() if x["status"] == srw.OK]
     lat = np.array([x["latency_ms"] for x in ok]) if ok else np.zeros(1)
     per = {}

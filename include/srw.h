@@ -192,6 +192,8 @@ int srw_set_stream(void *hip_stream);
  *                 one per XCD, in runs of this many consecutive items, so
  *                 that the chunks scanning one range of tiles share an L2
  *                 (0, the default: one queue)
+ *   "meet_bgrid"  blocks of a bucketed meet launch, which take work items
+ *                 from queues until they are empty (default 4096)
  *   "meet_grid"   meet blocks per launch, grid-striding over the work items
  *                 (0: one block per work item, up to 2^31-1)
  *   "ysort"       new inverse levels of at least this many candidates are
@@ -218,6 +220,13 @@ int srw_set_stream(void *hip_stream);
  *                 (W = ceil(n/64) = 1..8; -1 removes it), e.g. from the
  *                 autotuner's table; it takes precedence over the key's
  *                 value for every width
+ *   "reduce"      1: every new level is self-reduced before the meet test
+ *                 (Alg. 1): a forward set with another set of its level
+ *                 inside it, an inverse set with another one around it, is
+ *                 dropped from the level and stays visited; r is the same,
+ *                 the word may be another shortest one.  Small steps then
+ *                 run per phase (no one-block or one-launch steps).
+ *                 0 (default): no reduction
  *   "deadline_ms" per automaton, from its admission: a solve still running
  *                 after this long ends with SRW_ETIMEOUT (0: no deadline)
  *   "verbose"     1: one line per step of a single solve on stderr
@@ -259,6 +268,7 @@ typedef struct srw_stats {
     int64_t meet_b_launches_w[8];/* of those bucketed meet launches, per set width */
     double meet_b_ms_w[8];     /* their own time, with "profile" 1 or 2 */
     int64_t meet_b_ops_w[8];   /* their share of meet_ops_w, with "profile" 1 */
+    int64_t reduced;           /* sets the self-reduction (option "reduce") dropped */
 } srw_stats;
 /* kernel classes: 0 expand (and whole one-block steps), 1 insert, 2 count+scan+compact, 3 meet
  * preparation (transpose of inverse levels, bucket sort of forward levels),

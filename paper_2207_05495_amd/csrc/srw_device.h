@@ -16,6 +16,8 @@ constexpr int kMaxW = 8;                 // subsets of up to 512 states
 constexpr u64 kEmpty = ~0ull;            // free hash slot
 constexpr u32 kCandBit = 0x80000000u;    // slot ref names a candidate of this step
 constexpr u32 kDrop = 0xFFFFFFFFu;       // candidate dropped (empty or seen before)
+constexpr u32 kGhostBit = 0x40000000u;   // slot ref names a set dropped by a reduction
+                                         // (with StepDesc::ghost set; rows then stay below 2^30)
 constexpr int kBS = 256;                 // threads per block (4 wave64)
 constexpr int kCB = 1024;                // candidates per compaction block
 constexpr int kMeetTileWords = 32;       // LDS budget of the meet: tiles*W <= this
@@ -109,6 +111,14 @@ struct StepDesc {
     u64 *tab;
     u64 tab_mask;              // capacity - 1 (capacity is a power of two)
     const u64 *vis_rows;       // all stored rows of the side (ids < 2^31)
+    // self-reduction of the new level (Alg. 1), when `ghost` is set: its
+    // dropped sets go to ghost rows ghost_base.. and stay visited; mark[i]
+    // flags new set i, red_par holds the kept sets' keys while they move;
+    // res[3] = sets dropped
+    u64 *ghost;
+    int64_t ghost_base;
+    u32 *mark;
+    u32 *red_par;
     // compaction
     u64 *out_rows;             // where the new level starts (vis_rows + base*W)
     u32 *out_par;              // parent key per new row
@@ -245,7 +255,8 @@ struct CopyDesc {
 constexpr int kCopyPerBlock = 4096;      // words per block of k_copy
 
 struct RehashDesc {
-    int32_t W, pad;
+    int32_t W;
+    int32_t ref_or;            // or-ed into every ref (kGhostBit: ghost rows)
     const u64 *rows;           // rows 0..count-1 to insert
     int64_t count;
     u64 *tab;

@@ -48,6 +48,8 @@ hipError_t launch_fill(u64 *, int64_t, u64, hipStream_t);
 hipError_t launch_clear_tables(const RehashDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_trace(const TraceDesc *, int, hipStream_t);
 hipError_t launch_beam(const BeamDesc *, int, int, hipStream_t);
+hipError_t launch_reduce(const StepDesc *, const int64_t *, const int64_t *, int, int64_t, int64_t, u32 *, u32 *,
+                         hipStream_t);
 hipError_t launch_sort(const SortDesc *, const int64_t *const[3], const int64_t[3], int, hipStream_t);
 
 // ------------------------------------------------------------------ errors
@@ -384,6 +386,8 @@ struct SideState {
     int64_t nrows = 0;
     std::vector<int64_t> off;  // level L: rows off[L] .. off[L+1]-1
     u64 popsum = 0;            // sum of the cardinalities of the current level's sets
+    u64 *ghost = nullptr;      // sets dropped by the self-reduction (they stay visited)
+    int64_t ghost_cap = 0, nghost = 0;
     int nlev() const { return (int)off.size() - 1; }
     int64_t cur() const { return off[off.size() - 1] - off[off.size() - 2]; }
     int64_t cur_start() const { return off[off.size() - 2]; }
@@ -412,6 +416,8 @@ struct Problem {
     int64_t cand_cap = 0;     // rows
     u32 *cslot = nullptr;
     int64_t cslot_cap = 0;
+    u32 *mark = nullptr, *red_par = nullptr;   // self-reduction: flags and moved keys, red_cap each
+    int64_t red_cap = 0;
     // the current forward level bucket-sorted for the chunked meet
     u64 *xs_rows = nullptr, *xs_com = nullptr;
     u32 *xs_idx = nullptr, *xs_keys = nullptr, *xs_hist = nullptr, *xs_bins = nullptr;
@@ -465,6 +471,8 @@ struct Options {
     int64_t meet_grid = 0;              // meet blocks per launch (0: one per work item)
     int64_t meet_order = 1;             // chunked meet items: 0 tile-range-major, 1 chunk-major
     int64_t meet_xcd = 0;               // bucketed meet: items dealt to per-XCD queues in runs of this many (0: one queue)
+    int64_t meet_bgrid = 4096;          // bucketed meet: blocks per launch (they take items from queues)
+    int reduce = 0;                     // 1: self-reduction of every new level (Alg. 1), dropped sets kept visited
     int profile = 0;                    // 1: every kernel class and the meet; 2: the meet only
     bool keep_levels = false;
     bool verbose = false;          // one stderr line per step of a single solve
@@ -856,6 +864,12 @@ class Engine {
             d.tab = s.tab;
             d.tab_mask = (u64)(s.tab_cap - 1);
             d.vis_rows = s.rows;
+            if (opt.reduce) {
+                d.ghost = s.ghost;
+                d.ghost_base = s.nghost;
+                d.mark = p->mark;
+                d.red_par = p->red_par;
+            }
             d.out_rows = s.rows + s.nrows * W;
             d.out_par = s.par + s.nrows;
             d.out_base = s.nrows;
@@ -965,7 +979,7 @@ class Engine {
             // the new inverse level is transposed in level order, unless it
             // goes into buckets (transposed in bucket order there)
             d.ntr_waves = (dir == 1 && !p->yb_now) ? ceil_div(d.C, 64) * W : 0;
-            d.small = d.meet_mode == 0 && d.C <= opt.small(W) && d.nXb * d.nYc <= kSmallMeetBlocks;
+            d.small = d.meet_mode == 0 && d.C <= opt.small(W) && d.nXb * d.nYc <= kSmallMeetBlocks && !opt.reduce;
             if (d.small) {
                 pm[i + 1] = pm[i];
                 small.push_back(i);
@@ -1062,6 +1076,8 @@ class Engine {
         HIPCHK(launch_count(dD, dpc, nseg, pc[nseg], d_cnt_, stream_));
         if (nsmall < nseg) HIPCHK(launch_scan(dD, nseg, d_cnt_, d_off_, stream_));
         HIPCHK(launch_compact(dD, dpc, nseg, pc[nseg], d_off_, stream_));
+        if (opt.reduce)        // the new levels' self-reduction, before the meet sees them
+            HIPCHK(launch_reduce(dD, dpe, dpc, nseg, pe[nseg], pc[nseg], d_cnt_, d_off_, stream_));
         prof_end(2);
         if (pt[nseg] > 0 || nsort > 0 || nyb > 0 || pmp[nseg] > 0) {
             prof_begin(3);
@@ -1105,7 +1121,7 @@ class Engine {
                     HIPCHK(hipEventRecord(ev_meetb_[2 * (W - 1)], stream_));
                     meetb_used_[W - 1] = true;
                 }
-                HIPCHK(launch_meet_b(dD, s0, s1, W, std::min<int64_t>(ceil_div(bk_items, kBS / 64), kMeetQueueGrid),
+                HIPCHK(launch_meet_b(dD, s0, s1, W, std::min<int64_t>(ceil_div(bk_items, kBS / 64), opt.meet_bgrid),
                                      ops ? ops + 1 : nullptr, stream_));
                 if (opt.profile) HIPCHK(hipEventRecord(ev_meetb_[2 * (W - 1) + 1], stream_));
                 stats_.meet_work[7]++;
@@ -1142,6 +1158,8 @@ class Engine {
             s.nrows += U;
             s.off.push_back(s.nrows);
             s.popsum = hres[kResWords * i + 2];
+            s.nghost += (int64_t)hres[kResWords * i + 3];
+            stats_.reduced += (int64_t)hres[kResWords * i + 3];
             p->sides.push_back((uint8_t)dir);
             if (dir == 0) p->xs_valid = p->sort_now;
             if (dir == 1) p->ys_valid = d.ysort != 0;
@@ -1516,9 +1534,9 @@ class Engine {
 
     // (schedule 3 leaves the first, small steps to the runner's side rule)
     bool persist_ok(int W) const {
-        return opt.persist && opt.small(W) > 0 && (opt.sched(W) == 0 || opt.sched(W) == 3) && opt.meet != 2;
+        return opt.persist && opt.small(W) > 0 && (opt.sched(W) == 0 || opt.sched(W) == 3) && opt.meet != 2 &&
+               !opt.reduce;
     }
-    static constexpr int64_t kMeetQueueGrid = 4096;  // blocks of a bucketed meet (they take items from queues)
     static constexpr int64_t kPersistRows = 16384;   // rows per side while k_run_small steps
     static constexpr int64_t kPersistCand = 8192;    // candidates of its largest step
     static constexpr int64_t kPersistLevels = 4096;  // levels per side it can record
@@ -1632,6 +1650,21 @@ class Engine {
             return set_error(SRW_ENOMEM, "list size beyond 2^31");
         void *pp;
         int64_t cap;
+        if (opt.reduce) {
+            // rows and ghosts are named by refs below kGhostBit
+            if (s.nrows + s.nghost + C >= (int64_t)kGhostBit)
+                return set_error(SRW_ENOMEM, "list size beyond 2^30 with reductions");
+            pp = s.ghost; cap = s.ghost_cap;
+            if (!dev_grow(pp, cap, s.nghost + C, (size_t)W * 8, s.nghost))
+                return set_error(SRW_ENOMEM, "device budget (dropped sets)");
+            s.ghost = (u64 *)pp; s.ghost_cap = cap;
+            pp = p->mark; cap = p->red_cap;
+            if (!dev_grow(pp, cap, C, 4, 0)) return set_error(SRW_ENOMEM, "device budget (reduction)");
+            p->mark = (u32 *)pp;
+            pp = p->red_par; cap = p->red_cap;
+            if (!dev_grow(pp, cap, C, 4, 0)) return set_error(SRW_ENOMEM, "device budget (reduction)");
+            p->red_par = (u32 *)pp; p->red_cap = cap;
+        }
         pp = p->cand; cap = p->cand_cap;
         if (!dev_grow(pp, cap, C, (size_t)W * 8, 0)) return set_error(SRW_ENOMEM, "device budget (candidates)");
         p->cand = (u64 *)pp; p->cand_cap = cap;
@@ -1648,9 +1681,9 @@ class Engine {
             s.par = (u32 *)pp;
             s.cap = c1;
         }
-        if (2 * (s.nrows + C) > s.tab_cap) {
+        if (2 * (s.nrows + s.nghost + C) > s.tab_cap) {
             int64_t nc = s.tab_cap;
-            while (2 * (s.nrows + C) > nc) nc <<= 1;
+            while (2 * (s.nrows + s.nghost + C) > nc) nc <<= 1;
             nc = std::max(nc, 2 * s.tab_cap);
             if (nc > ((int64_t)1 << 31)) return set_error(SRW_ENOMEM, "hash table beyond 2^31 slots");
             void *t = pool_->alloc((size_t)nc * 8);
@@ -1660,6 +1693,10 @@ class Engine {
             s.tab_cap = nc;
             grow.push_back(RehashDesc{W, 0, s.rows, s.nrows, s.tab, (u64)(nc - 1)});
             growpre.push_back(growpre.back() + ceil_div(s.nrows, kBS));
+            if (s.nghost > 0) {                  // the dropped sets stay visited
+                grow.push_back(RehashDesc{W, (int32_t)kGhostBit, s.ghost, s.nghost, s.tab, (u64)(nc - 1)});
+                growpre.push_back(growpre.back() + ceil_div(s.nghost, kBS));
+            }
         }
         if (dir == 1) {
             pp = p->colT; cap = p->colT_cap;
@@ -1852,10 +1889,11 @@ class Engine {
                               (const void *)p->ys_idx, (const void *)p->cand, (const void *)p->cslot,
                               (const void *)p->xs_rows, (const void *)p->xs_com, (const void *)p->xs_idx,
                               (const void *)p->xs_keys, (const void *)p->xs_hist, (const void *)p->xs_bins,
-                              (const void *)p->xs_top})
+                              (const void *)p->xs_top, (const void *)p->mark, (const void *)p->red_par})
             b += pool_->size_of(q);
         for (int sd = 0; sd < 2; ++sd)
-            b += pool_->size_of(p->s[sd].rows) + pool_->size_of(p->s[sd].par) + pool_->size_of(p->s[sd].tab);
+            b += pool_->size_of(p->s[sd].rows) + pool_->size_of(p->s[sd].par) + pool_->size_of(p->s[sd].tab) +
+                 pool_->size_of(p->s[sd].ghost);
         return b;
     }
 
@@ -1867,6 +1905,8 @@ class Engine {
             pool_->free(p->s[sd].rows); p->s[sd].rows = nullptr;
             pool_->free(p->s[sd].par); p->s[sd].par = nullptr;
             pool_->free(p->s[sd].tab); p->s[sd].tab = nullptr;
+            pool_->free(p->s[sd].ghost); p->s[sd].ghost = nullptr;
+            p->s[sd].ghost_cap = p->s[sd].nghost = 0;
             p->s[sd].cap = p->s[sd].tab_cap = 0;
         }
         pool_->free(p->colT); p->colT = nullptr; p->colT_cap = 0;
@@ -1889,6 +1929,9 @@ class Engine {
         p->ys_cap = 0;
         p->ys_valid = false;
         pool_->free(p->cand); p->cand = nullptr; p->cand_cap = 0;
+        pool_->free(p->mark); pool_->free(p->red_par);
+        p->mark = p->red_par = nullptr;
+        p->red_cap = 0;
         pool_->free(p->cslot); p->cslot = nullptr; p->cslot_cap = 0;
         for (void *q : {(void *)p->xs_rows, (void *)p->xs_com, (void *)p->xs_idx, (void *)p->xs_keys,
                         (void *)p->xs_hist, (void *)p->xs_bins, (void *)p->xs_top})
@@ -2181,6 +2224,8 @@ int srw_set_option(const char *key, int64_t v) {
     else if (k == "meet_grid") { if (v < 0) return set_error(SRW_EINVAL, "meet_grid"); x.opt.meet_grid = v; }
     else if (k == "meet_order") { if (v < 0 || v > 1) return set_error(SRW_EINVAL, "meet_order"); x.opt.meet_order = v; }
     else if (k == "meet_xcd") { if (v < 0 || v > 65536) return set_error(SRW_EINVAL, "meet_xcd"); x.opt.meet_xcd = v; }
+    else if (k == "meet_bgrid") { if (v < 1 || v > 65536) return set_error(SRW_EINVAL, "meet_bgrid"); x.opt.meet_bgrid = v; }
+    else if (k == "reduce") { if (v < 0 || v > 1) return set_error(SRW_EINVAL, "reduce"); x.opt.reduce = (int)v; }
     else return set_error(SRW_EINVAL, "unknown option " + k);
     if (x.eng) x.eng->opt = x.opt;
     return SRW_OK;

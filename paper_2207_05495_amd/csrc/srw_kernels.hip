@@ -190,7 +190,8 @@ __device__ void insert_w(const D &d, int64_t lb) {
         if ((u32)(cur >> 32) == fp) {
             const u32 ref = (u32)cur;
             const u64 *o = (ref & kCandBit) ? d.cand + (u64)(ref & ~kCandBit) * W
-                                            : d.vis_rows + (u64)ref * W;
+                         : (d.ghost && (ref & kGhostBit)) ? d.ghost + (u64)(ref & ~kGhostBit) * W
+                                                          : d.vis_rows + (u64)ref * W;
             bool eq = true;
 #pragma unroll
             for (int w = 0; w < W; ++w) eq = eq && (o[w] == x[w]);
@@ -284,6 +285,7 @@ __global__ void __launch_bounds__(kBS) k_scan(const StepDesc *descs, int nseg, c
         d.res[0] = running;
         d.res[1] = kEmpty;
         d.res[2] = 0;                      // k_compact adds the cardinalities
+        d.res[3] = 0;                      // sets a reduction drops
     }
 }
 
@@ -328,6 +330,194 @@ __global__ void __launch_bounds__(kBS) k_compact(const StepDesc *descs, const in
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) card += (u32)__shfl_xor((int)card, off, 64);
     if (lane == 0 && card) atomicAdd((unsigned long long *)(d.res + 2), (unsigned long long)card);
+}
+
+// ------------------------------------------------------ self-reduction
+
+// Self-reduction of a new level (Alg. 1), for segments with d.ghost set.
+// Step 1: mark each new set i that has another set of its level inside it
+// (forward: i is not minimal) or around it (inverse: i is not maximal).
+// The sets of a level are distinct, so "another" is the index.  Brute force:
+// 256 sets per block against the level, staged 256 sets at a time in LDS
+// and read as broadcasts.
+template <int W>
+__device__ void red_mark_w(const CONST_AS StepDesc &d, int64_t lb, u64 *lds) {
+    const int64_t U = (int64_t)d.res[0];
+    if (lb * kBS >= U) return;                 // the whole block
+    const int tid = threadIdx.x;
+    const int64_t i = lb * kBS + tid;
+    const bool vi = i < U;
+    u64 x[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) x[w] = vi ? d.out_rows[i * W + w] : 0ull;
+    bool marked = !vi;
+    for (int64_t j0 = 0; j0 < U; j0 += kBS) {
+        __syncthreads();                       // the last tile is read
+        const int64_t j = j0 + tid;
+#pragma unroll
+        for (int w = 0; w < W; ++w) lds[w * kBS + tid] = j < U ? d.out_rows[j * W + w] : 0ull;
+        __syncthreads();
+        const int jn = (int)min((int64_t)kBS, U - j0);
+        for (int t = 0; t < jn && !marked; ++t) {
+            if (j0 + t == i) continue;
+            u64 viol = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const u64 y = lds[w * kBS + t];
+                viol |= d.dir == 0 ? (y & ~x[w]) : (x[w] & ~y);
+            }
+            marked = viol == 0;
+        }
+    }
+    if (vi) d.mark[i] = marked ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(kBS) k_red_mark(const StepDesc *descs, const int64_t *pre, int nseg) {
+    __shared__ u64 lds[kMaxW * kBS];
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const CONST_AS StepDesc &d = cref(descs + s);
+    if (!d.ghost) return;
+    const int64_t lb = (int64_t)blockIdx.x - cref(pre + s);
+    SRW_SWITCH_W(d.W, red_mark_w<W>(d, lb, lds));
+}
+
+// Step 2: kept sets per compaction block (the step's compaction grid)
+__global__ void __launch_bounds__(kBS) k_red_count(const StepDesc *descs, const int64_t *pre, int nseg,
+                                                   u32 *blk_cnt) {
+    __shared__ u32 wsum[kBS / 64];
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const CONST_AS StepDesc &d = cref(descs + s);
+    if (!d.ghost) return;
+    const int64_t lb = (int64_t)blockIdx.x - cref(pre + s);
+    const int64_t U = (int64_t)d.res[0];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    u32 c = 0;
+#pragma unroll
+    for (int t = 0; t < kCB / kBS; ++t) {
+        const int64_t r = lb * kCB + t * kBS + tid;
+        c += (u32)__popcll(__ballot(r < U && d.mark[r] == 0));
+    }
+    if (lane == 0) wsum[wave] = c;
+    __syncthreads();
+    if (tid == 0) {
+        u32 tot = 0;
+        for (int w = 0; w < kBS / 64; ++w) tot += wsum[w];
+        blk_cnt[d.cblk_base + lb] = tot;
+    }
+}
+
+// Step 3, one block per segment: exclusive scan of the kept counts; the
+// level size becomes the kept count, res[3] the dropped one
+__global__ void __launch_bounds__(kBS) k_red_scan(const StepDesc *descs, int nseg, const u32 *blk_cnt,
+                                                  u32 *blk_off) {
+    __shared__ u32 wsum[kBS / 64];
+    const int s = blockIdx.x;
+    if (s >= nseg) return;
+    const CONST_AS StepDesc &d = cref(descs + s);
+    if (!d.ghost) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    u64 running = 0;
+    for (int64_t c0 = 0; c0 < d.ncblk; c0 += kBS) {
+        const int64_t idx = c0 + tid;
+        const u32 v = idx < d.ncblk ? blk_cnt[d.cblk_base + idx] : 0u;
+        u32 incl = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const u32 o = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += o;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        u32 wpre = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < kBS / 64; ++w) {
+            if (w < wave) wpre += wsum[w];
+            tot += wsum[w];
+        }
+        if (idx < d.ncblk) blk_off[d.cblk_base + idx] = (u32)(running + wpre + incl - v);
+        running += tot;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        d.res[3] = d.res[0] - running;
+        d.res[0] = running;
+    }
+}
+
+// Step 4: kept sets (in key order) to the candidate buffer and their keys
+// to red_par, dropped sets to the ghost rows; every moved set's hash slot
+// (found through its key: cslot[g]) names its new place, and a dropped
+// set's cardinality leaves the level's sum
+template <int W>
+__device__ void red_compact_w(const CONST_AS StepDesc &d, int64_t lb, const u32 *blk_off, u32 *wsum) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t U = (int64_t)(d.res[0] + d.res[3]);
+    u32 rank0 = blk_off[d.cblk_base + lb];
+    u64 gone = 0;                              // cardinalities of the dropped sets
+#pragma unroll
+    for (int t = 0; t < kCB / kBS; ++t) {
+        const int64_t r = lb * kCB + t * kBS + tid;
+        const bool v = r < U;
+        const bool keep = v && d.mark[r] == 0;
+        const u64 mask = __ballot(keep);
+        if (lane == 0) wsum[wave] = (u32)__popcll(mask);
+        __syncthreads();
+        u32 wpre = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < kBS / 64; ++w) {
+            if (w < wave) wpre += wsum[w];
+            tot += wsum[w];
+        }
+        if (v) {
+            const u64 rank = rank0 + wpre + lanes_below(mask);     // kept sets before r
+            const u32 g = d.out_par[r];
+            const u32 sl = d.cslot[g];
+            const u64 e = d.tab[sl];
+            if (keep) {
+#pragma unroll
+                for (int w = 0; w < W; ++w) d.cand[rank * W + w] = d.out_rows[r * W + w];
+                d.red_par[rank] = g;
+                d.tab[sl] = (e & 0xFFFFFFFF00000000ull) | (u64)(u32)(d.out_base + (int64_t)rank);
+            } else {
+                const int64_t gr = d.ghost_base + (r - (int64_t)rank);
+                u32 card = 0;
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    const u64 x = d.out_rows[r * W + w];
+                    d.ghost[gr * W + w] = x;
+                    card += (u32)__popcll(x);
+                }
+                d.tab[sl] = (e & 0xFFFFFFFF00000000ull) | (u64)(kGhostBit | (u32)gr);
+                gone += card;
+            }
+        }
+        rank0 += tot;
+        __syncthreads();
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) gone += (u64)__shfl_xor((long long)gone, off, 64);
+    if (lane == 0 && gone) atomicAdd((unsigned long long *)(d.res + 2), (unsigned long long)(0ull - gone));
+}
+
+__global__ void __launch_bounds__(kBS) k_red_compact(const StepDesc *descs, const int64_t *pre, int nseg,
+                                                     const u32 *blk_off) {
+    __shared__ u32 wsum[kBS / 64];
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const CONST_AS StepDesc &d = cref(descs + s);
+    if (!d.ghost) return;
+    const int64_t lb = (int64_t)blockIdx.x - cref(pre + s);
+    SRW_SWITCH_W(d.W, red_compact_w<W>(d, lb, blk_off, wsum));
+}
+
+// Step 5: the kept sets and keys back into the level
+__global__ void __launch_bounds__(kBS) k_red_copy(const StepDesc *descs, const int64_t *pre, int nseg) {
+    const int s = find_seg(pre, nseg, blockIdx.x);
+    const CONST_AS StepDesc &d = cref(descs + s);
+    if (!d.ghost) return;
+    const int64_t r = ((int64_t)blockIdx.x - cref(pre + s)) * kBS + threadIdx.x;
+    if (r >= (int64_t)d.res[0]) return;
+    for (int w = 0; w < d.W; ++w) d.out_rows[r * d.W + w] = d.cand[r * d.W + w];
+    d.out_par[r] = d.red_par[r];
 }
 
 // ------------------------------------------------------------ transpose
@@ -1331,6 +1521,7 @@ __device__ u32 step_small_w(const D &d, u64 *lds, u32 *wsum) {
         d.res[0] = rank0;
         d.res[1] = kEmpty;
         d.res[2] = tc;
+        d.res[3] = 0;
     }
     if (d.ntr_waves > 0) {                 // a new inverse level: transpose it
         const int64_t tiles = ((int64_t)rank0 + 63) / 64;
@@ -1438,6 +1629,7 @@ __device__ u32 run_small_w(const CONST_AS RunDesc &r, StepDesc &sd, u64 *lds, u3
                 d.tab = r.tab[dir];
                 d.tab_mask = r.tab_mask[dir];
                 d.vis_rows = r.rows[dir];
+                d.ghost = nullptr;
                 d.out_rows = r.rows[dir] + nr[dir] * W;
                 d.out_par = r.par[dir] + nr[dir];
                 d.out_base = nr[dir];
@@ -1583,6 +1775,7 @@ __device__ void beam_w(const CONST_AS BeamDesc &b, StepDesc &sd, u64 *lds, u32 *
         sd.tab = b.tab;
         sd.tab_mask = b.tab_mask;
         sd.vis_rows = b.rows;
+        sd.ghost = nullptr;
     }
     __syncthreads();
     for (;;) {
@@ -1898,7 +2091,7 @@ __device__ void rehash_w(const CONST_AS RehashDesc &d, int64_t id) {
 #pragma unroll
     for (int w = 0; w < W; ++w) x[w] = d.rows[id * W + w];
     const u64 h = set_hash<W>(x);
-    const u64 e = (h & 0xFFFFFFFF00000000ull) | (u64)(u32)id;
+    const u64 e = (h & 0xFFFFFFFF00000000ull) | (u64)((u32)id | (u32)d.ref_or);
     u64 pos = h & d.tab_mask;
     for (;;) {
         if (load_slot(&d.tab[pos]) == kEmpty && atomicCAS(&d.tab[pos], kEmpty, e) == kEmpty) return;
@@ -1976,6 +2169,18 @@ hipError_t launch_copy(const CopyDesc *d, const int64_t *pre, int nseg, int64_t 
 hipError_t launch_run_small(const RunDesc *d, int count, int W, u64 *ops, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     SRW_SWITCH_W(W, hipLaunchKernelGGL(k_run_small<W>, dim3((unsigned)count), dim3(kBS), 0, st, d, ops));
+    return launch_checked();
+}
+// pe: block prefix of ceil(C / kBS) per segment (marks, copy); pc: the
+// compaction grid (ceil(C / kCB) per segment)
+hipError_t launch_reduce(const StepDesc *d, const int64_t *pe, const int64_t *pc, int nseg, int64_t be,
+                         int64_t bc, u32 *cnt, u32 *off, hipStream_t st) {
+    if (nseg <= 0) return hipSuccess;
+    if (be > 0) hipLaunchKernelGGL(k_red_mark, dim3((unsigned)be), dim3(kBS), 0, st, d, pe, nseg);
+    if (bc > 0) hipLaunchKernelGGL(k_red_count, dim3((unsigned)bc), dim3(kBS), 0, st, d, pc, nseg, cnt);
+    hipLaunchKernelGGL(k_red_scan, dim3((unsigned)nseg), dim3(kBS), 0, st, d, nseg, cnt, off);
+    if (bc > 0) hipLaunchKernelGGL(k_red_compact, dim3((unsigned)bc), dim3(kBS), 0, st, d, pc, nseg, off);
+    if (be > 0) hipLaunchKernelGGL(k_red_copy, dim3((unsigned)be), dim3(kBS), 0, st, d, pe, nseg);
     return launch_checked();
 }
 // count automata, all with W words per set

@@ -52,7 +52,7 @@ class Stats(ctypes.Structure):
                 ("pair_words_w", ctypes.c_int64 * 8), ("meet_ops_w", ctypes.c_int64 * 8),
                 ("host_ms", ctypes.c_double * 4), ("meet_work", ctypes.c_int64 * 8),
                 ("meet_b_launches_w", ctypes.c_int64 * 8), ("meet_b_ms_w", ctypes.c_double * 8),
-                ("meet_b_ops_w", ctypes.c_int64 * 8)]
+                ("meet_b_ops_w", ctypes.c_int64 * 8), ("reduced", ctypes.c_int64)]
 
     def as_dict(self):
         arrays = ("launches", "ms", "meet_launches_w", "meet_ms_w", "pair_words_w", "meet_ops_w", "host_ms",

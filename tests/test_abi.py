@@ -158,13 +158,14 @@ def test_every_documented_option_is_accepted_and_checked():
     defaults = {"budget": 0, "max_slots": 4096, "profile": 0, "schedule": 0, "sched_seed": 0,
                 "meet": 0, "meet_tiles": 0, "meet_rows": 512, "meet_groups": 16, "meet_order": 1,
                 "meet_grid": 0, "ysort": 0, "small_cand": 2048, "deadline_ms": 0,
-                "verbose": 0, "keep_levels": 0, "persist": 1, "bucket": 16384, "meet_xcd": 0}
+                "verbose": 0, "keep_levels": 0, "persist": 1, "bucket": 16384, "meet_xcd": 0,
+                "meet_bgrid": 4096, "reduce": 0}
     assert set(keys) == set(defaults), set(keys) ^ set(defaults)
     for k in keys:
         srw.set_option(k, defaults[k])
     bad = {"profile": 3, "schedule": 4, "meet": 3, "meet_order": 2, "meet_groups": 0,
            "meet_tiles": 1000, "ysort": -1, "small_cand": -1, "meet_grid": -1, "budget": -5,
-           "persist": 2, "bucket": -1, "meet_xcd": -1}
+           "persist": 2, "bucket": -1, "meet_xcd": -1, "meet_bgrid": 0, "reduce": 2}
     for k, v in bad.items():
         with pytest.raises(srw.SrwError) as e:
             srw.set_option(k, v)

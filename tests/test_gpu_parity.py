@@ -35,7 +35,7 @@ def gpu():
 DEFAULTS = (("schedule", 0), ("meet_tiles", 0), ("keep_levels", 0), ("budget", 0), ("meet", 0),
             ("max_slots", 4096), ("meet_rows", 512), ("meet_groups", 16), ("meet_order", 1),
             ("meet_grid", 0), ("small_cand", 2048), ("ysort", 0), ("deadline_ms", 0),
-            ("verbose", 0), ("persist", 1), ("bucket", 16384), ("meet_xcd", 0))
+            ("verbose", 0), ("persist", 1), ("bucket", 16384), ("meet_xcd", 0), ("meet_bgrid", 4096))
 
 
 def say(*a):
@@ -711,16 +711,18 @@ def test_persistent_small_steps_keep_results(persist, small):
         srw.set_option("small_cand", 2048)
 
 
-@pytest.mark.parametrize("bucket,meet,xcd", [(0, 0, 0), (1, 2, 0), (64, 0, 0), (1, 0, 0), (1, 2, 1),
-                                              (1, 2, 64), (64, 0, 7)])
-def test_bucketed_meet_keeps_results(bucket, meet, xcd):
+@pytest.mark.parametrize("bucket,meet,xcd,bgrid", [(0, 0, 0, 4096), (1, 2, 0, 4096), (64, 0, 0, 4096),
+                                                    (1, 0, 0, 4096), (1, 2, 1, 4096), (1, 2, 64, 4096),
+                                                    (64, 0, 7, 4096), (1, 2, 0, 1), (1, 2, 8, 7)])
+def test_bucketed_meet_keeps_results(bucket, meet, xcd, bgrid):
     """Inverse levels in buckets by their membership of the forward level's
     most frequent states, met by chunks that scan only the buckets holding
     their common split states: off (0), for every level against every
     forward level sorted into chunks (1 with meet mode 2, so tiny and
     one-bucket levels too), from 64 sets on, and for every level the default
     schedule sorts; work items from one queue or dealt to per-XCD queues in
-    runs of 1, 7 or 64.  r and word equal the oracle's, singly and batched."""
+    runs of 1, 7 or 64; a launch of 4096, 7 or a single block taking the
+    items.  r and word equal the oracle's, singly and batched."""
     cs = [(n, 2, I.cerny(n)) for n in (9, 20)]
     cs += [(n, k, rand_sync(n, k, j, base=61)) for j, (n, k) in
            enumerate([(64, 2), (150, 2), (200, 3), (129, 2), (40, 4), (255, 2), (90, 3)])]
@@ -730,9 +732,10 @@ def test_bucketed_meet_keeps_results(bucket, meet, xcd):
     srw.set_option("bucket", bucket)
     srw.set_option("meet", meet)
     srw.set_option("meet_xcd", xcd)
+    srw.set_option("meet_bgrid", bgrid)
     try:
         for (n, k, d), w in zip(cs, want):
-            say("bucketed meet", bucket, meet, xcd, n, k)
+            say("bucketed meet", bucket, meet, xcd, bgrid, n, k)
             assert srw.solve(n, k, d) == w, (n, k)
         res = srw.solve_batch(cs)
         assert [(st, (r, wd)) for st, r, wd in res] == [(srw.OK, w) for w in want]
@@ -740,6 +743,7 @@ def test_bucketed_meet_keeps_results(bucket, meet, xcd):
         srw.set_option("bucket", 16384)
         srw.set_option("meet", 0)
         srw.set_option("meet_xcd", 0)
+        srw.set_option("meet_bgrid", 4096)
 
 
 @pytest.mark.parametrize("ysort", [0, 1])
@@ -808,11 +812,10 @@ def test_mixed_batch_members_against_stored_oracle_values():
 @pytest.mark.parametrize("k", [2, 3])
 def test_mixed_batch_larger_members_against_stored_oracle_values(k):
     """The members with n > 160 among the first 300 of the seeded 4096-member
-    batch that the oracle finished within 300 s each (tests/golden/
-    mix4096big.json: every k = 2 member up to n = 320 but two, the k = 3 ones
-    up to n = 256), solved together in one batch per alphabet size: r and
-    word equal the oracle's stored values.  The others are parity
-    unpinned."""
+    batch that the oracle finished within its time budget (tests/golden/
+    mix4096big.json records the budget of the others), solved together in
+    one batch per alphabet size: r and word equal the oracle's stored
+    values.  The others are parity unpinned."""
     path = os.path.join(GOLDEN, "mix4096big.json")
     if not os.path.exists(path):
         pytest.skip("no stored oracle values for the larger members")
@@ -899,3 +902,48 @@ def test_beam_edges():
     assert st[1][0] == srw.ENOTSYNC and st[2][0] == srw.ENOTSYNC
     assert st[3][0] == srw.EINVAL
     assert srw.beam_batch([]) == []
+
+
+# ------------------------------------------------------ self-reduction on the device
+
+def reduce_cases():
+    cs = []
+    for i, (n, k) in enumerate([(12, 2), (20, 2), (33, 3), (48, 2), (64, 2), (90, 3), (128, 2), (160, 2)]):
+        d, _ = I.first_synchronizing(n, k, I.member_seed(I.BASE_SEED ^ 0x5ED, i), O.is_synchronizing)
+        cs.append((n, k, d))
+    cs += [(n, 2, I.cerny(n)) for n in (6, 13)]
+    return cs
+
+
+def test_self_reduction_matches_the_oracle():
+    """Option reduce: every new level self-reduced on the device (Alg. 1),
+    dropped sets kept visited.  r and word equal the oracle's search with
+    the same reduction (oracle.bidir(reduce=True, keep_dropped=True)), r
+    equals the unreduced r, and every level (sets, order, parent keys)
+    equals the oracle's; singly and in one batch."""
+    cs = reduce_cases()
+    want = []
+    for n, k, d in cs:
+        r, w, info = O.bidir(n, k, d, reduce=True, keep_dropped=True, keep_levels=True)
+        want.append((r, list(w), info["levels"]))
+        assert r == oracle_rw(n, k, d)[0]
+    srw.set_option("reduce", 1)
+    srw.set_option("keep_levels", 1)
+    try:
+        for (n, k, d), (r, w, levels) in zip(cs, want):
+            say("reduce", n, k)
+            assert srw.solve(n, k, d) == (r, w), (n, k)
+            for side in (0, 1):
+                got = srw.last_levels(side, (n + 63) // 64)
+                assert len(got) == len(levels[side]), (n, k, side)
+                for L, ((gr, gp), (er, ep)) in enumerate(zip(got, levels[side])):
+                    assert np.array_equal(gr, er), (n, k, side, L)
+                    if L > 0:
+                        assert np.array_equal(gp.astype(np.int64), ep), (n, k, side, L)
+        srw.set_option("keep_levels", 0)
+        res = srw.solve_batch(cs)
+        assert [(st, (r, wd)) for st, r, wd in res] == [(srw.OK, (r, w)) for r, w, _ in want]
+        assert srw.get_stats()["reduced"] > 0
+    finally:
+        srw.set_option("reduce", 0)
+        srw.set_option("keep_levels", 0)

@@ -223,10 +223,14 @@ int srw_set_stream(void *hip_stream);
  *   "reduce"      1: every new level is self-reduced before the meet test
  *                 (Alg. 1): a forward set with another set of its level
  *                 inside it, an inverse set with another one around it, is
- *                 dropped from the level and stays visited; r is the same,
- *                 the word may be another shortest one.  Small steps then
- *                 run per phase (no one-block or one-launch steps).
- *                 0 (default): no reduction
+ *                 dropped from the level and stays visited; 2: also one
+ *                 with a set of an earlier level of its side inside it
+ *                 (forward) or around it (inverse), the reduction by
+ *                 history.  r is the same, the word may be another
+ *                 shortest one.  Small steps then run per phase (no
+ *                 one-block or one-launch steps).  The marks are found by
+ *                 brute force over the level (and the history), so large
+ *                 levels are slow.  0 (default): no reduction
  *   "deadline_ms" per automaton, from its admission: a solve still running
  *                 after this long ends with SRW_ETIMEOUT (0: no deadline)
  *   "verbose"     1: one line per step of a single solve on stderr

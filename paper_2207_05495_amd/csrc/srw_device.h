@@ -119,6 +119,7 @@ struct StepDesc {
     int64_t ghost_base;
     u32 *mark;
     u32 *red_par;
+    int64_t red_hist;          // 1: also reduce by the side's earlier levels (history)
     // compaction
     u64 *out_rows;             // where the new level starts (vis_rows + base*W)
     u32 *out_par;              // parent key per new row

@@ -472,7 +472,8 @@ struct Options {
     int64_t meet_order = 1;             // chunked meet items: 0 tile-range-major, 1 chunk-major
     int64_t meet_xcd = 0;               // bucketed meet: items dealt to per-XCD queues in runs of this many (0: one queue)
     int64_t meet_bgrid = 4096;          // bucketed meet: blocks per launch (they take items from queues)
-    int reduce = 0;                     // 1: self-reduction of every new level (Alg. 1), dropped sets kept visited
+    int reduce = 0;                     // 1: self-reduction of every new level (Alg. 1), 2: also by history;
+                                        // dropped sets kept visited
     int profile = 0;                    // 1: every kernel class and the meet; 2: the meet only
     bool keep_levels = false;
     bool verbose = false;          // one stderr line per step of a single solve
@@ -869,6 +870,7 @@ class Engine {
                 d.ghost_base = s.nghost;
                 d.mark = p->mark;
                 d.red_par = p->red_par;
+                d.red_hist = opt.reduce == 2;
             }
             d.out_rows = s.rows + s.nrows * W;
             d.out_par = s.par + s.nrows;
@@ -2225,7 +2227,7 @@ int srw_set_option(const char *key, int64_t v) {
     else if (k == "meet_order") { if (v < 0 || v > 1) return set_error(SRW_EINVAL, "meet_order"); x.opt.meet_order = v; }
     else if (k == "meet_xcd") { if (v < 0 || v > 65536) return set_error(SRW_EINVAL, "meet_xcd"); x.opt.meet_xcd = v; }
     else if (k == "meet_bgrid") { if (v < 1 || v > 65536) return set_error(SRW_EINVAL, "meet_bgrid"); x.opt.meet_bgrid = v; }
-    else if (k == "reduce") { if (v < 0 || v > 1) return set_error(SRW_EINVAL, "reduce"); x.opt.reduce = (int)v; }
+    else if (k == "reduce") { if (v < 0 || v > 2) return set_error(SRW_EINVAL, "reduce"); x.opt.reduce = (int)v; }
     else return set_error(SRW_EINVAL, "unknown option " + k);
     if (x.eng) x.eng->opt = x.opt;
     return SRW_OK;

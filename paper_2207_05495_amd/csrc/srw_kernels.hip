@@ -336,10 +336,13 @@ __global__ void __launch_bounds__(kBS) k_compact(const StepDesc *descs, const in
 
 // Self-reduction of a new level (Alg. 1), for segments with d.ghost set.
 // Step 1: mark each new set i that has another set of its level inside it
-// (forward: i is not minimal) or around it (inverse: i is not maximal).
-// The sets of a level are distinct, so "another" is the index.  Brute force:
-// 256 sets per block against the level, staged 256 sets at a time in LDS
-// and read as broadcasts.
+// (forward: i is not minimal) or around it (inverse: i is not maximal), and
+// with d.red_hist also each one with a set of an earlier level of its side
+// inside (forward) or around it (inverse): the reduction by history.  The
+// sets of a level are distinct, so "another" is the index.  Brute force:
+// 256 sets per block against the level (then the earlier levels, the
+// side's stored rows 0 .. out_base-1), staged 256 sets at a time in LDS and
+// read as broadcasts.
 template <int W>
 __device__ void red_mark_w(const CONST_AS StepDesc &d, int64_t lb, u64 *lds) {
     const int64_t U = (int64_t)d.res[0];
@@ -351,22 +354,27 @@ __device__ void red_mark_w(const CONST_AS StepDesc &d, int64_t lb, u64 *lds) {
 #pragma unroll
     for (int w = 0; w < W; ++w) x[w] = vi ? d.out_rows[i * W + w] : 0ull;
     bool marked = !vi;
-    for (int64_t j0 = 0; j0 < U; j0 += kBS) {
-        __syncthreads();                       // the last tile is read
-        const int64_t j = j0 + tid;
+    // pass 0: the level itself; pass 1: the earlier levels (history)
+    for (int pass = 0; pass < (d.red_hist ? 2 : 1); ++pass) {
+        const u64 *src = pass == 0 ? d.out_rows : d.vis_rows;
+        const int64_t cnt = pass == 0 ? U : d.out_base;
+        for (int64_t j0 = 0; j0 < cnt; j0 += kBS) {
+            __syncthreads();                   // the last tile is read
+            const int64_t j = j0 + tid;
 #pragma unroll
-        for (int w = 0; w < W; ++w) lds[w * kBS + tid] = j < U ? d.out_rows[j * W + w] : 0ull;
-        __syncthreads();
-        const int jn = (int)min((int64_t)kBS, U - j0);
-        for (int t = 0; t < jn && !marked; ++t) {
-            if (j0 + t == i) continue;
-            u64 viol = 0;
+            for (int w = 0; w < W; ++w) lds[w * kBS + tid] = j < cnt ? src[j * W + w] : 0ull;
+            __syncthreads();
+            const int jn = (int)min((int64_t)kBS, cnt - j0);
+            for (int t = 0; t < jn && !marked; ++t) {
+                if (pass == 0 && j0 + t == i) continue;
+                u64 viol = 0;
 #pragma unroll
-            for (int w = 0; w < W; ++w) {
-                const u64 y = lds[w * kBS + t];
-                viol |= d.dir == 0 ? (y & ~x[w]) : (x[w] & ~y);
+                for (int w = 0; w < W; ++w) {
+                    const u64 y = lds[w * kBS + t];
+                    viol |= d.dir == 0 ? (y & ~x[w]) : (x[w] & ~y);
+                }
+                marked = viol == 0;
             }
-            marked = viol == 0;
         }
     }
     if (vi) d.mark[i] = marked ? 1u : 0u;

@@ -165,7 +165,7 @@ def test_every_documented_option_is_accepted_and_checked():
         srw.set_option(k, defaults[k])
     bad = {"profile": 3, "schedule": 4, "meet": 3, "meet_order": 2, "meet_groups": 0,
            "meet_tiles": 1000, "ysort": -1, "small_cand": -1, "meet_grid": -1, "budget": -5,
-           "persist": 2, "bucket": -1, "meet_xcd": -1, "meet_bgrid": 0, "reduce": 2}
+           "persist": 2, "bucket": -1, "meet_xcd": -1, "meet_bgrid": 0, "reduce": 3}
     for k, v in bad.items():
         with pytest.raises(srw.SrwError) as e:
             srw.set_option(k, v)

@@ -915,19 +915,22 @@ def reduce_cases():
     return cs
 
 
-def test_self_reduction_matches_the_oracle():
+@pytest.mark.parametrize("mode", [1, 2])
+def test_self_reduction_matches_the_oracle(mode):
     """Option reduce: every new level self-reduced on the device (Alg. 1),
-    dropped sets kept visited.  r and word equal the oracle's search with
-    the same reduction (oracle.bidir(reduce=True, keep_dropped=True)), r
-    equals the unreduced r, and every level (sets, order, parent keys)
-    equals the oracle's; singly and in one batch."""
+    with mode 2 also reduced by the side's earlier levels; dropped sets kept
+    visited.  r and word equal the oracle's search with the same reduction
+    (oracle.bidir(reduce=True or "history", keep_dropped=True)), r equals
+    the unreduced r, and every level (sets, order, parent keys) equals the
+    oracle's; singly and in one batch."""
     cs = reduce_cases()
     want = []
     for n, k, d in cs:
-        r, w, info = O.bidir(n, k, d, reduce=True, keep_dropped=True, keep_levels=True)
+        r, w, info = O.bidir(n, k, d, reduce=True if mode == 1 else "history", keep_dropped=True,
+                             keep_levels=True)
         want.append((r, list(w), info["levels"]))
         assert r == oracle_rw(n, k, d)[0]
-    srw.set_option("reduce", 1)
+    srw.set_option("reduce", mode)
     srw.set_option("keep_levels", 1)
     try:
         for (n, k, d), (r, w, levels) in zip(cs, want):

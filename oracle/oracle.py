@@ -76,6 +76,9 @@ def bind(path):
         L.orc_bidir_reduce.argtypes = L.orc_bidir.argtypes + [ctypes.c_int]
         L.orc_beam.argtypes = [ctypes.c_int, ctypes.c_int, i32p, ctypes.c_int64, ctypes.c_int,
                                i32p, u8p, ctypes.c_int64, i64p]
+        L.orc_pair_dist.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, u8p]
+        L.orc_eppstein.argtypes = [ctypes.c_int, ctypes.c_int, i32p, u8p, ctypes.c_int64,
+                                   i64p, i32p, i32p]
         L.orc_levels.argtypes = [ctypes.c_void_p, ctypes.c_int, i32p, i64p, i64p,
                                  u64p, i64p]
         L.orc_free.argtypes = [ctypes.c_void_p]
@@ -252,6 +255,37 @@ def beam(n, k, delta, width, max_steps=1 << 20):
         return None, None, info
     rr, ww = _result(rc, "beam", R, word)
     return rr, ww, info
+
+
+def pair_dist(n, k, delta):
+    """Shortest merging word length of every pair (orc_pair_dist): returns
+    (dist, next), two n x n arrays; dist -1 where no word merges the pair,
+    next the least letter starting a shortest merging word (255 where
+    dist <= 0)."""
+    d = _delta(delta)
+    dist = np.zeros((n, n), dtype=np.int32)
+    nxt = np.zeros((n, n), dtype=np.uint8)
+    rc = lib().orc_pair_dist(n, k, _ptr(d, ctypes.c_int32), _ptr(dist, ctypes.c_int32),
+                             _ptr(nxt, ctypes.c_uint8))
+    if rc != OK:
+        raise OracleError(rc, "pair_dist")
+    return dist, nxt
+
+
+def eppstein(n, k, delta, cap=1 << 22):
+    """Eppstein's greedy heuristic (orc_eppstein): returns (word, rounds),
+    rounds a list of (p, q, dist) per round."""
+    d = _delta(delta)
+    word = np.zeros(max(cap, 1), dtype=np.uint8)
+    ln = ctypes.c_int64(-1)
+    rounds = np.zeros(3 * max(n, 1), dtype=np.int32)
+    nr = ctypes.c_int32(0)
+    rc = lib().orc_eppstein(n, k, _ptr(d, ctypes.c_int32), _ptr(word, ctypes.c_uint8), len(word),
+                            ctypes.byref(ln), _ptr(rounds, ctypes.c_int32), ctypes.byref(nr))
+    if rc != OK:
+        raise OracleError(rc, "eppstein")
+    rr = [tuple(int(x) for x in rounds[3 * i:3 * i + 3]) for i in range(nr.value)]
+    return [int(x) for x in word[:ln.value]], rr
 
 
 def levels_after(n, k, delta, sched):

@@ -37,6 +37,13 @@
  *                         the plain search with every level cut to its
  *                         largest sets; an upper bound R >= r and a reset
  *                         word of length R
+ *   orc_pair_dist         shortest merging word length of every pair of
+ *                         states, from its recursive definition (the pair
+ *                         test of the Section 2 intro, with lengths)
+ *   orc_eppstein          Eppstein's greedy heuristic (cited in Section
+ *                         1.3.2, the first bound of Section 2.1.3): merge
+ *                         the pair of the current set with the shortest
+ *                         merging word, until one state is left
  *   orc_bidir             plain bidirectional BFS (Alg. 1 with only the
  *                         duplicate removal kept): forward images from Q,
  *                         inverse preimages from the singletons, meet test
@@ -1011,6 +1018,119 @@ int orc_beam(int n, int k, const int32_t *delta, int64_t beam, int max_steps,
     side_free(&B);
     if (stats_out) memcpy(stats_out, st, sizeof st);
     return out;
+}
+
+/* ---------------- Eppstein's greedy heuristic -------------------------- */
+
+/* Shortest merging words of pairs of states: dist[p*n+q] is the least |w|
+ * with delta(p,w) = delta(q,w) (0 when p = q, -1 when no word merges them:
+ * the pair test of the Section 2 intro, with lengths).  Filled from its
+ * recursive definition, dist{p,q} = 1 + min over letters a of
+ * dist{delta(p,a), delta(q,a)}, in rounds d = 1, 2, ...: a pair gets d in
+ * round d when some letter takes it to a pair (or a single state) of
+ * distance d - 1.  next[p*n+q] is the least such letter (255 where
+ * dist <= 0).  Both arrays are n*n and symmetric. */
+int orc_pair_dist(int n, int k, const int32_t *delta, int32_t *dist, uint8_t *next) {
+    int rc = check_input(n, k, delta);
+    if (rc) return rc;
+    if (!dist || !next) return ORC_EINVAL;
+    for (int p = 0; p < n; p++)
+        for (int q = 0; q < n; q++) {
+            dist[(size_t)p * n + q] = p == q ? 0 : -1;
+            next[(size_t)p * n + q] = 255;
+        }
+    for (int d = 1;; d++) {
+        int any = 0;
+        for (int p = 0; p < n; p++)
+            for (int q = p + 1; q < n; q++) {
+                if (dist[(size_t)p * n + q] != -1) continue;
+                for (int a = 0; a < k; a++) {
+                    int pp = delta[(int64_t)a * n + p], qq = delta[(int64_t)a * n + q];
+                    if (dist[(size_t)pp * n + qq] == d - 1) {
+                        dist[(size_t)p * n + q] = dist[(size_t)q * n + p] = d;
+                        next[(size_t)p * n + q] = next[(size_t)q * n + p] = (uint8_t)a;
+                        any = 1;
+                        break;
+                    }
+                }
+            }
+        if (!any) break;
+    }
+    return ORC_OK;
+}
+
+/* Eppstein's greedy heuristic (cited in Section 1.3.2, the first upper
+ * bound of Section 2.1.3).  From S = Q, each round picks the pair {p, q}
+ * of S whose merging word is shortest (ties: least p, then least q),
+ * appends that word (next{p,q}, then next of the image pair, and so on,
+ * dist{p,q} letters) and replaces S with its image under it, until S is a
+ * single state.  The result is a reset word, so its length bounds r from
+ * above.  rounds (3 ints per round: p, q, dist{p,q}; at most n - 1 rounds;
+ * may be NULL) and *nrounds describe the rounds for the tests.  *len is the
+ * whole length even when it exceeds word_cap (then ORC_EWORDCAP and only
+ * the first word_cap letters are written). */
+int orc_eppstein(int n, int k, const int32_t *delta, uint8_t *word, int64_t word_cap,
+                 int64_t *len, int32_t *rounds, int32_t *nrounds) {
+    int rc = check_input(n, k, delta);
+    if (rc) return rc;
+    if (!len) return ORC_EINVAL;
+    rc = orc_is_synchronizing(n, k, delta);
+    if (rc < 0) return rc;
+    if (rc == 0) return ORC_ENOTSYNC;
+    int32_t *dist = malloc(sizeof(int32_t) * (size_t)n * n);
+    uint8_t *next = malloc((size_t)n * n);
+    unsigned char *in = calloc((size_t)n, 1), *img = calloc((size_t)n, 1);
+    if (!dist || !next || !in || !img) {
+        free(dist); free(next); free(in); free(img);
+        return ORC_ENOMEM;
+    }
+    rc = orc_pair_dist(n, k, delta, dist, next);
+    int64_t total = 0;
+    int32_t nr = 0;
+    int size = n;
+    for (int q = 0; q < n; q++) in[q] = 1;
+    while (!rc && size > 1) {
+        if (nr == n - 1) {          /* every round merges a pair: cannot happen */
+            rc = ORC_ELIMIT;
+            break;
+        }
+        int bp = -1, bq = -1, bd = 0;
+        for (int p = 0; p < n; p++) {
+            if (!in[p]) continue;
+            for (int q = p + 1; q < n; q++) {
+                if (!in[q]) continue;
+                const int d = dist[(size_t)p * n + q];
+                if (bp < 0 || d < bd) { bp = p; bq = q; bd = d; }
+            }
+        }
+        if (rounds) {
+            rounds[3 * nr] = bp;
+            rounds[3 * nr + 1] = bq;
+            rounds[3 * nr + 2] = bd;
+        }
+        nr++;
+        int p = bp, q = bq;
+        for (int t = 0; t < bd; t++) {
+            const int a = next[(size_t)p * n + q];
+            if (word && total < word_cap) word[total] = (uint8_t)a;
+            total++;
+            memset(img, 0, (size_t)n);
+            size = 0;
+            for (int s = 0; s < n; s++)
+                if (in[s] && !img[delta[(int64_t)a * n + s]]) {
+                    img[delta[(int64_t)a * n + s]] = 1;
+                    size++;
+                }
+            memcpy(in, img, (size_t)n);
+            p = delta[(int64_t)a * n + p];
+            q = delta[(int64_t)a * n + q];
+        }
+    }
+    free(dist); free(next); free(in); free(img);
+    if (rc) return rc;
+    *len = total;
+    if (nrounds) *nrounds = nr;
+    return total > word_cap && word ? ORC_EWORDCAP : ORC_OK;
 }
 
 /* orc_bidir with every new level self-reduced (side_reduce) */

@@ -187,11 +187,68 @@ def reduction_pins_hold(reduce=True):
     return True
 
 
+# planted mistakes in the Eppstein heuristic
+EPPSTEIN_MUTANTS = {
+    # the diagonal starts at 1: every distance one too long
+    "pair_dist_off_by_one": [("dist[(size_t)p * n + q] = p == q ? 0 : -1;",
+                              "dist[(size_t)p * n + q] = p == q ? 1 : -1;")],
+    # the last letter reaching distance d - 1 instead of the least
+    "pair_dist_last_letter": [("                        any = 1;\n                        break;\n",
+                               "                        any = 1;\n")],
+    # equal distances go to the last pair
+    "greedy_ties_last": [("if (bp < 0 || d < bd) { bp = p; bq = q; bd = d; }",
+                          "if (bp < 0 || d <= bd) { bp = p; bq = q; bd = d; }")],
+    # the pair with the longest merging word
+    "greedy_longest_pair": [("if (bp < 0 || d < bd) { bp = p; bq = q; bd = d; }",
+                             "if (bp < 0 || d > bd) { bp = p; bq = q; bd = d; }")],
+    # only the first letter of each round's word
+    "greedy_one_letter_rounds": [("for (int t = 0; t < bd; t++) {", "for (int t = 0; t < 1; t++) {")],
+    # the pair is not followed through the round's letters
+    "greedy_pair_not_followed": [("            p = delta[(int64_t)a * n + p];\n"
+                                  "            q = delta[(int64_t)a * n + q];\n", "")],
+}
+
+
+def eppstein_pins_hold():
+    from tests.test_eppstein_oracle import check_rounds, enumerated_dist, tiny_cases
+    try:
+        for n, k, d in tiny_cases()[::3]:
+            dist, nxt = O.pair_dist(n, k, d)
+            want, first = enumerated_dist(n, k, d)
+            if not np.array_equal(dist, want):
+                return False
+            for (p, q), w in first.items():
+                if w and nxt[p, q] != w[0]:
+                    return False
+            if not O.is_synchronizing(n, k, d):
+                continue
+            word, rounds = O.eppstein(n, k, d)
+            try:
+                check_rounds(n, k, d, word, rounds, want, first)
+            except AssertionError:
+                return False
+    except O.OracleError:
+        return False
+    return True
+
+
+@pytest.mark.parametrize("name", sorted(EPPSTEIN_MUTANTS))
+def test_eppstein_mutant_is_caught(name, tmp_path):
+    so = build_mutant(name, EPPSTEIN_MUTANTS[name], str(tmp_path))
+    saved = O._lib
+    try:
+        O._lib = O.bind(so)
+        assert not eppstein_pins_hold(), f"planted mistake {name} went unnoticed"
+    finally:
+        O._lib = saved
+
+
 def test_unmutated_oracle_passes():
     assert pins_hold()
     assert reduction_pins_hold()
     assert reduction_pins_hold("history")
     assert alg2_pins_hold()
+    assert eppstein_pins_hold()
 
 
 @pytest.mark.parametrize("name", sorted(REDUCE_MUTANTS))

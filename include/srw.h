@@ -312,6 +312,30 @@ int srw_beam_batch(int32_t count, const int32_t *n, const int32_t *k, const int6
                    const int32_t *delta, const int64_t *width, int32_t *R, int32_t *status,
                    const int64_t *word_off, uint8_t *words, const int64_t *word_cap);
 
+/* Upper bound on the reset threshold by Eppstein's greedy heuristic (cited
+ * in Section 1.3.2 with its O(n^3 + k n^2) time and (n^3-n)/3 length bound;
+ * Section 2.1.3 computes it before the beam search).  From S = Q, each round
+ * takes the pair {p, q} of S whose shortest merging word is shortest (ties:
+ * the least p, then the least q), appends that word and replaces S with its
+ * image, until one state is left.  The merging word of a pair is its
+ * lexicographically least shortest one: the least letter that takes the
+ * pair to a single state or to a pair one step closer, repeated.  *len gets
+ * the length of the whole word (an upper bound on r); `word` (if not NULL)
+ * gets the word when word_cap >= *len, else the status is SRW_EWORDCAP with
+ * *len still written.  Every word is checked on the host.  One block of the
+ * GPU runs each automaton: all pair distances by a breadth-first search
+ * backwards over pairs, then the rounds.  Statuses as srw_solve; "budget"
+ * and "deadline_ms" of srw_set_option apply. */
+int srw_eppstein(int32_t n, int32_t k, const int32_t *delta, int64_t *len, uint8_t *word,
+                 int64_t word_cap);
+/* srw_eppstein of `count` automata at once (arrays as in srw_solve_batch,
+ * len[i] per automaton, -1 unless its status is SRW_OK or SRW_EWORDCAP); the
+ * return value is SRW_OK or an error of the call itself, each automaton's
+ * status is in status[i]. */
+int srw_eppstein_batch(int32_t count, const int32_t *n, const int32_t *k, const int64_t *delta_off,
+                       const int32_t *delta, int64_t *len, int32_t *status,
+                       const int64_t *word_off, uint8_t *words, const int64_t *word_cap);
+
 /* The side of every step of the last srw_solve run with "keep_levels" on,
  * in order (0 forward, 1 inverse): *steps = their count; with sides != NULL
  * also sides[0..*steps) (SRW_EINVAL when cap < *steps).  A test and

@@ -303,6 +303,28 @@ struct BeamState {
     int64_t candidates, kept, cut;   // over the steps run
 };
 
+// Eppstein's greedy heuristic, one block per automaton (k_eppstein).  Pairs
+// {p, q}, p < q, are numbered q(q-1)/2 + p.
+struct EppState {
+    int32_t status;            // 1 done, 4 deadline, 5 a pair of the set cannot be merged
+    int32_t rounds;            // pairs merged
+    int64_t len;               // letters of the whole word (also those beyond word_cap)
+};
+struct EppDesc {
+    int32_t n, k;
+    const uint16_t *delta;     // delta[a*n + q]
+    u32 *dist;                 // n(n-1)/2 shortest merging lengths (0: not reached)
+    uint8_t *next;             // n(n-1)/2 first letters of the lex-least shortest merging words
+    u32 *queue;                // 2 * n(n-1)/2: two BFS frontiers of pair numbers
+    uint16_t *inv;             // k*n: states of each inverse list, letter by letter
+    u32 *inv_off;              // k*(n+1): list a, t is inv[inv_off[a*(n+1)+t] .. inv_off[a*(n+1)+t+1])
+    u32 *inv_cur;              // k*n fill cursors
+    uint8_t *word;             // word_cap letters
+    int64_t word_cap;
+    int64_t max_ticks;         // stop after this many wall_clock64 ticks (0: no limit)
+    EppState *st;
+};
+
 struct TraceDesc {
     const u32 *par_f;
     const int64_t *off_f;      // level offsets of the forward side

@@ -48,6 +48,7 @@ hipError_t launch_fill(u64 *, int64_t, u64, hipStream_t);
 hipError_t launch_clear_tables(const RehashDesc *, const int64_t *, int, int64_t, hipStream_t);
 hipError_t launch_trace(const TraceDesc *, int, hipStream_t);
 hipError_t launch_beam(const BeamDesc *, int, int, hipStream_t);
+hipError_t launch_eppstein(const EppDesc *, int, hipStream_t);
 hipError_t launch_reduce(const StepDesc *, const int64_t *, const int64_t *, int, int64_t, int64_t, u32 *, u32 *,
                          hipStream_t);
 hipError_t launch_sort(const SortDesc *, const int64_t *const[3], const int64_t[3], int, hipStream_t);
@@ -1420,8 +1421,120 @@ class Engine {
             if (j->status == 1) j->status = SRW_ENOMEM;
     }
 
+    // Eppstein's heuristic (k_eppstein), a block per automaton, in groups
+    // whose buffers fit the budget.  The word buffer starts at a guess; a
+    // longer word (its length is always returned) is computed again with
+    // room for all of it, so that every word is checked on the host.
+    struct EppJob {
+        int n = 0, k = 0;
+        const int32_t *delta = nullptr;
+        int64_t index = -1;
+        int status = 1;            // 1: not done yet
+        int64_t len = -1, dcap = 0;
+        int32_t rounds = 0;
+        std::vector<uint8_t> word;
+    };
+    void eppstein(std::vector<EppJob *> &jobs) {
+        HIPCHK(hipSetDevice(device_));
+        for (EppJob *j : jobs) j->dcap = std::max<int64_t>(4096, 64 * (int64_t)j->n);
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            std::vector<EppJob *> todo;
+            for (EppJob *j : jobs)
+                if (j->status == 1) todo.push_back(j);
+            for (size_t i0 = 0; i0 < todo.size(); i0 += kBeamGroup) {
+                std::vector<EppJob *> grp(todo.begin() + i0,
+                                          todo.begin() + std::min(todo.size(), i0 + kBeamGroup));
+                eppstein_group(grp);
+            }
+            for (EppJob *j : todo)
+                if (j->status == 1) j->dcap = j->len;     // the whole word next time
+        }
+        for (EppJob *j : jobs)
+            if (j->status == 1) j->status = SRW_EINTERNAL;
+    }
+
   private:
     static size_t align8(size_t x) { return (x + 7) & ~(size_t)7; }
+
+    void eppstein_group(std::vector<EppJob *> &grp) {
+        const int cnt = (int)grp.size();
+        std::vector<EppDesc> D(cnt);
+        std::vector<size_t> at(cnt + 1, 0);
+        size_t head = align8(sizeof(EppState) * (size_t)cnt) + align8(sizeof(EppDesc) * (size_t)cnt);
+        std::vector<int64_t> doff(cnt + 1, 0);
+        for (int i = 0; i < cnt; ++i) doff[i + 1] = doff[i] + (int64_t)grp[i]->n * grp[i]->k;
+        head += align8((size_t)doff[cnt] * 2);
+        at[0] = head;
+        for (int i = 0; i < cnt; ++i) {
+            const size_t n = (size_t)grp[i]->n, k = (size_t)grp[i]->k, P = n * (n - 1) / 2;
+            at[i + 1] = at[i] + align8(4 * P) + align8(P) + align8(8 * P) + align8(2 * k * n) +
+                        align8(4 * k * (n + 1)) + align8(4 * k * n) + align8((size_t)grp[i]->dcap);
+        }
+        char *base = (char *)pool_->alloc(at[cnt]);
+        if (!base) {
+            if (cnt == 1) {
+                grp[0]->status = SRW_ENOMEM;
+                return;
+            }
+            std::vector<EppJob *> a(grp.begin(), grp.begin() + cnt / 2), b(grp.begin() + cnt / 2, grp.end());
+            eppstein_group(a);
+            eppstein_group(b);
+            return;
+        }
+        EppState *dst = (EppState *)base;
+        EppDesc *dd = (EppDesc *)(base + align8(sizeof(EppState) * (size_t)cnt));
+        uint16_t *dl = (uint16_t *)((char *)dd + align8(sizeof(EppDesc) * (size_t)cnt));
+        std::vector<uint16_t> d16((size_t)doff[cnt]);
+        for (int i = 0; i < cnt; ++i)
+            for (int64_t t = 0; t < doff[i + 1] - doff[i]; ++t) d16[(size_t)(doff[i] + t)] = (uint16_t)grp[i]->delta[t];
+        for (int i = 0; i < cnt; ++i) {
+            EppJob *j = grp[i];
+            const size_t n = (size_t)j->n, k = (size_t)j->k, P = n * (n - 1) / 2;
+            EppDesc &e = D[i];
+            memset(&e, 0, sizeof e);
+            char *c = base + at[i];
+            e.n = j->n;
+            e.k = j->k;
+            e.delta = dl + doff[i];
+            e.dist = (u32 *)c;            c += align8(4 * P);
+            e.next = (uint8_t *)c;        c += align8(P);
+            e.queue = (u32 *)c;           c += align8(8 * P);
+            e.inv = (uint16_t *)c;        c += align8(2 * k * n);
+            e.inv_off = (u32 *)c;         c += align8(4 * k * (n + 1));
+            e.inv_cur = (u32 *)c;         c += align8(4 * k * n);
+            e.word = (uint8_t *)c;
+            e.word_cap = j->dcap;
+            if (opt.deadline_ms > 0) e.max_ticks = std::max<int64_t>(1, (int64_t)(opt.deadline_ms * wall_khz_));
+            e.st = dst + i;
+        }
+        HIPCHK(hipMemcpyAsync(dl, d16.data(), d16.size() * 2, hipMemcpyHostToDevice, stream_));
+        HIPCHK(hipMemcpyAsync(dd, D.data(), sizeof(EppDesc) * (size_t)cnt, hipMemcpyHostToDevice, stream_));
+        HIPCHK(launch_eppstein(dd, cnt, stream_));
+        std::vector<EppState> S(cnt);
+        HIPCHK(hipMemcpyAsync(S.data(), dst, sizeof(EppState) * (size_t)cnt, hipMemcpyDeviceToHost, stream_));
+        HIPCHK(hipStreamSynchronize(stream_));
+        for (int i = 0; i < cnt; ++i) {
+            EppJob *j = grp[i];
+            const EppState &t = S[i];
+            j->rounds = t.rounds;
+            if (t.status == 4) {
+                j->status = SRW_ETIMEOUT;
+            } else if (t.status != 1) {
+                j->status = SRW_EINTERNAL;
+                t_err = "Eppstein: a pair of the current set has no merging word";
+            } else if (t.len > j->dcap) {
+                j->len = t.len;                    // again, with room for all of it
+            } else {
+                j->len = t.len;
+                j->word.resize((size_t)t.len);
+                if (t.len > 0)
+                    HIPCHK(hipMemcpy(j->word.data(), D[i].word, (size_t)t.len, hipMemcpyDeviceToHost));
+                j->status = verify_word(j->n, j->k, j->delta, j->word.data(), t.len) ? SRW_OK : SRW_EINTERNAL;
+                if (j->status != SRW_OK) t_err = "Eppstein word does not reset the automaton";
+            }
+        }
+        pool_->free(base);
+    }
 
     // one group of beam searches: buffers, one launch per set width, results
     void beam_group(std::vector<BeamJob *> &grp) {
@@ -2367,6 +2480,65 @@ int srw_beam_batch(int32_t count, const int32_t *n, const int32_t *k, const int6
         }
     }
     return SRW_OK;
+}
+
+int srw_eppstein_batch(int32_t count, const int32_t *n, const int32_t *k, const int64_t *delta_off,
+                       const int32_t *delta, int64_t *len, int32_t *status, const int64_t *word_off,
+                       uint8_t *words, const int64_t *word_cap) {
+    if (count < 0 || (count > 0 && (!n || !k || !delta_off || !delta || !len || !status)))
+        return set_error(SRW_EINVAL, "null argument");
+    if (words && (!word_off || !word_cap)) return set_error(SRW_EINVAL, "words without offsets");
+    Context &x = ctx();
+    std::lock_guard<std::mutex> g(x.mu);
+    std::vector<Engine::EppJob> jobs((size_t)std::max(count, 0));
+    std::vector<Engine::EppJob *> work;
+    for (int32_t i = 0; i < count; ++i) {
+        len[i] = -1;
+        const int32_t *d = delta + delta_off[i];
+        int rc = check_input(n[i], k[i], d);
+        if (rc) { status[i] = rc; continue; }
+        if (!is_synchronizing(n[i], k[i], d)) { status[i] = SRW_ENOTSYNC; continue; }
+        if (n[i] == 1) { status[i] = SRW_OK; len[i] = 0; continue; }
+        Engine::EppJob &j = jobs[(size_t)i];
+        j.n = n[i];
+        j.k = k[i];
+        j.delta = d;
+        j.index = i;
+        work.push_back(&j);
+    }
+    if (!work.empty()) {
+        try {
+            engine_locked(x)->eppstein(work);
+        } catch (const HipFailure &f) {
+            const bool oom = f.e == hipErrorOutOfMemory;
+            for (Engine::EppJob *j : work)
+                if (j->status == 1) j->status = oom ? SRW_ENOMEM : SRW_EDEVICE;
+            x.eng.reset();
+            if (!oom) {
+                for (Engine::EppJob *j : work) status[j->index] = j->status;
+                return device_error(f);
+            }
+        }
+    }
+    for (Engine::EppJob *j : work) {
+        const int i = (int)j->index;
+        status[i] = j->status;
+        len[i] = j->status == SRW_OK ? j->len : -1;
+        if (j->status == SRW_OK && words) {
+            if (word_cap[i] < j->len) status[i] = SRW_EWORDCAP;
+            else memcpy(words + word_off[i], j->word.data(), (size_t)j->len);
+        }
+    }
+    return SRW_OK;
+}
+
+int srw_eppstein(int32_t n, int32_t k, const int32_t *delta, int64_t *len, uint8_t *word, int64_t word_cap) {
+    if (!len) return set_error(SRW_EINVAL, "len is NULL");
+    const int64_t off = 0;
+    int32_t st = SRW_OK;
+    int rc = srw_eppstein_batch(1, &n, &k, &off, delta, len, &st, word ? &off : nullptr, word,
+                                word ? &word_cap : nullptr);
+    return rc ? rc : st;
 }
 
 int srw_beam(int32_t n, int32_t k, const int32_t *delta, int64_t width, int32_t *R, uint8_t *word,

@@ -1942,6 +1942,243 @@ __global__ void __launch_bounds__(kBS) k_beam(const BeamDesc *descs) {
     beam_w<W>(b, sd, lds, wsum, hist);
 }
 
+// ------------------------------------------------- Eppstein's heuristic
+//
+// One block per automaton.  First the shortest merging length of every pair
+// of states: a breadth-first search over pairs backwards from the pairs some
+// letter merges, a pair {x, y} reaching distance d + 1 from {p, q} at
+// distance d when delta(x, a) = p and delta(y, a) = q for a letter a (so the
+// preimage lists of each letter are built first).  The distance of a pair is
+// claimed once by compare-and-swap; the frontier order does not matter.
+// Then each pair's first letter: the least letter taking it to a single
+// state (distance 1) or to a pair one shorter.  Then the greedy rounds on
+// the current set S (flags and a sorted list in LDS): the least (distance,
+// p, q) over the pairs of S, a block-wide minimum; one thread walks the pair
+// through its first letters, writing the round's word, in chunks that the
+// other threads then apply to the states of S; S is rebuilt from the images.
+constexpr int kEB = 512;                 // threads per Eppstein block (n <= 512 states, one each)
+constexpr int kEppSeg = 2048;            // letters of a round applied at once
+constexpr int kEppLdsDelta = 16384;      // k*n entries of delta staged in LDS when they fit
+
+__device__ __forceinline__ u32 pair_no(u32 p, u32 q) {     // p < q
+    return q * (q - 1) / 2 + p;
+}
+__device__ __forceinline__ void pair_of(u32 idx, u32 &p, u32 &q) {
+    u32 j = (u32)((1.0f + sqrtf(1.0f + 8.0f * (float)idx)) * 0.5f);
+    while (j > 1 && j * (j - 1) / 2 > idx) --j;
+    while ((j + 1) * j / 2 <= idx) ++j;
+    q = j;
+    p = idx - j * (j - 1) / 2;
+}
+
+__global__ void __launch_bounds__(kEB) k_eppstein(const EppDesc *descs) {
+    __shared__ uint16_t s_delta[kEppLdsDelta];
+    __shared__ uint8_t s_in[kMaxW * 64];
+    __shared__ uint16_t s_list[kMaxW * 64];
+    __shared__ uint8_t s_seg[kEppSeg];
+    __shared__ u64 s_wmin[kEB / 64];
+    __shared__ u32 s_wcnt[kEB / 64];
+    __shared__ u32 s_qlen[2];
+    __shared__ u32 s_p, s_q;
+    __shared__ int s_m, s_stop;
+    const CONST_AS EppDesc &e = cref(descs + blockIdx.x);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = e.n, k = e.k;
+    const u32 P = (u32)n * (u32)(n - 1) / 2;
+    const u64 t_start = wall_clock64();
+    const bool lds_delta = (int64_t)n * k <= kEppLdsDelta;
+    const uint16_t *D = lds_delta ? s_delta : e.delta;
+    const int K1 = n + 1;
+    if (lds_delta)
+        for (int t = tid; t < n * k; t += kEB) s_delta[t] = e.delta[t];
+    // preimage lists: counts, offsets (one thread per letter), fill
+    for (int t = tid; t < k * K1; t += kEB) e.inv_off[t] = 0;
+    for (u32 t = tid; t < P; t += kEB) e.dist[t] = 0;
+    if (tid == 0) {
+        s_qlen[0] = 0;
+        s_stop = 0;
+    }
+    __syncthreads();
+    for (int t = tid; t < k * n; t += kEB) {
+        const int a = t / n;
+        atomicAdd(&e.inv_off[a * K1 + D[t] + 1], 1u);
+    }
+    __syncthreads();
+    for (int a = tid; a < k; a += kEB) {
+        u32 acc = (u32)(a * n);            // letter a's lists fill inv[a*n .. a*n + n)
+        for (int t = 0; t <= n; ++t) {
+            acc += e.inv_off[a * K1 + t];
+            e.inv_off[a * K1 + t] = acc;
+        }
+    }
+    __syncthreads();
+    for (int t = tid; t < k * n; t += kEB) {
+        const int a = t / n, x = t - a * n;
+        e.inv_cur[t] = e.inv_off[a * K1 + x];
+    }
+    __syncthreads();
+    for (int t = tid; t < k * n; t += kEB) {
+        const int a = t / n, x = t - a * n;
+        const u32 pos = atomicAdd(&e.inv_cur[a * n + D[t]], 1u);
+        e.inv[pos] = (uint16_t)x;
+    }
+    // distance 1: pairs some letter merges
+    for (u32 idx = tid; idx < P; idx += kEB) {
+        u32 p, q;
+        pair_of(idx, p, q);
+        for (int a = 0; a < k; ++a)
+            if (D[a * n + p] == D[a * n + q]) {
+                e.dist[idx] = 1;
+                e.queue[atomicAdd(&s_qlen[0], 1u)] = idx;
+                break;
+            }
+    }
+    __syncthreads();
+    // the search over pairs, a level per round
+    int cur = 0;
+    for (u32 d = 1;; ++d) {
+        const u32 len = s_qlen[cur];
+        if (len == 0 || s_stop) break;
+        if (tid == 0) s_qlen[cur ^ 1] = 0;
+        __syncthreads();
+        const u32 *in = e.queue + (size_t)cur * P;
+        u32 *out = e.queue + (size_t)(cur ^ 1) * P;
+        for (u32 i = tid; i < len; i += kEB) {
+            u32 p, q;
+            pair_of(in[i], p, q);
+            for (int a = 0; a < k; ++a) {
+                const u32 pb = e.inv_off[a * K1 + p], pe = e.inv_off[a * K1 + p + 1];
+                const u32 qb = e.inv_off[a * K1 + q], qe = e.inv_off[a * K1 + q + 1];
+                for (u32 u = pb; u < pe; ++u) {
+                    const u32 x = e.inv[u];
+                    for (u32 v = qb; v < qe; ++v) {
+                        const u32 y = e.inv[v];
+                        const u32 j = x < y ? pair_no(x, y) : pair_no(y, x);
+                        if (atomicCAS(&e.dist[j], 0u, d + 1) == 0u) out[atomicAdd(&s_qlen[cur ^ 1], 1u)] = j;
+                    }
+                }
+            }
+        }
+        if (tid == 0 && e.max_ticks > 0 && (int64_t)(wall_clock64() - t_start) > e.max_ticks) s_stop = 4;
+        __syncthreads();
+        cur ^= 1;
+    }
+    // first letters
+    for (u32 idx = tid; idx < P && !s_stop; idx += kEB) {
+        u32 p, q;
+        pair_of(idx, p, q);
+        const u32 d = e.dist[idx];
+        uint8_t nx = 255;
+        for (int a = 0; d && a < k; ++a) {
+            const u32 pp = D[a * n + p], qq = D[a * n + q];
+            const bool ok = pp == qq ? d == 1
+                                     : e.dist[pp < qq ? pair_no(pp, qq) : pair_no(qq, pp)] + 1 == d && d > 1;
+            if (ok) {
+                nx = (uint8_t)a;
+                break;
+            }
+        }
+        e.next[idx] = nx;
+    }
+    // the greedy rounds
+    if (tid < n) {
+        s_in[tid] = 1;
+        s_list[tid] = (uint16_t)tid;
+    }
+    if (tid == 0) s_m = n;
+    __syncthreads();
+    int64_t total = 0;
+    int rounds = 0;
+    while (s_m > 1 && !s_stop) {
+        const u32 m = (u32)s_m;
+        const u32 np = m * (m - 1) / 2;
+        u64 best = ~0ull;
+        for (u32 idx = tid; idx < np; idx += kEB) {
+            u32 i, j;
+            pair_of(idx, i, j);
+            const u32 p = s_list[i], q = s_list[j];
+            const u32 d = e.dist[pair_no(p, q)];
+            const u64 key = ((u64)(d ? d : 0xFFFFFFFFu) << 20) | ((u64)p << 10) | q;
+            best = key < best ? key : best;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const u64 other = __shfl_xor(best, o, 64);
+            best = other < best ? other : best;
+        }
+        if (lane == 0) s_wmin[wave] = best;
+        __syncthreads();
+        best = s_wmin[0];
+        for (int w = 1; w < kEB / 64; ++w) best = s_wmin[w] < best ? s_wmin[w] : best;
+        const u32 bd = (u32)(best >> 20);
+        if (bd == 0xFFFFFFFFu) {
+            if (tid == 0) s_stop = 5;
+            __syncthreads();
+            break;
+        }
+        if (tid == 0) {
+            s_p = (u32)(best >> 10) & 1023u;
+            s_q = (u32)best & 1023u;
+        }
+        u32 s = tid < (int)m ? s_list[tid] : 0;
+        for (u32 done = 0; done < bd; done += kEppSeg) {
+            const u32 c = bd - done < (u32)kEppSeg ? bd - done : (u32)kEppSeg;
+            __syncthreads();
+            if (tid == 0) {
+                u32 p = s_p, q = s_q;
+                for (u32 t = 0; t < c; ++t) {
+                    // each letter shortens the pair's distance by one, so the
+                    // pair stays a pair with a first letter until the last one
+                    const uint8_t a = p < q ? e.next[pair_no(p, q)] : (uint8_t)255;
+                    if (a >= k) {
+                        s_stop = 5;
+                        break;
+                    }
+                    s_seg[t] = a;
+                    const int64_t at = total + done + t;
+                    if (at < e.word_cap) e.word[at] = a;
+                    const u32 pp = D[a * n + p], qq = D[a * n + q];
+                    p = pp < qq ? pp : qq;
+                    q = pp < qq ? qq : pp;
+                }
+                s_p = p;
+                s_q = q;
+            }
+            __syncthreads();
+            if (s_stop) break;
+            if (tid < (int)m)
+                for (u32 t = 0; t < c; ++t) s = D[s_seg[t] * n + s];
+        }
+        total += bd;
+        ++rounds;
+        __syncthreads();
+        if (tid < n) s_in[tid] = 0;
+        __syncthreads();
+        if (tid < (int)m) s_in[s] = 1;
+        __syncthreads();
+        const bool f = tid < n && s_in[tid];
+        const u64 bal = __ballot(f);
+        if (lane == 0) s_wcnt[wave] = (u32)__popcll(bal);
+        __syncthreads();
+        u32 off = 0, all = 0;
+        for (int w = 0; w < kEB / 64; ++w) {
+            off += w < wave ? s_wcnt[w] : 0;
+            all += s_wcnt[w];
+        }
+        if (f) s_list[off + (u32)__popcll(bal & ((1ull << lane) - 1))] = (uint16_t)tid;
+        // every round merges its pair, so n - 1 rounds leave one state
+        if (tid == 0 && all > 1 && rounds >= n - 1) s_stop = 5;
+        if (tid == 0 && e.max_ticks > 0 && (int64_t)(wall_clock64() - t_start) > e.max_ticks) s_stop = 4;
+        __syncthreads();
+        if (tid == 0) s_m = (int)all;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        e.st->status = s_stop ? s_stop : 1;
+        e.st->rounds = rounds;
+        e.st->len = total;
+    }
+}
+
 // ------------------------------------------------- sort of forward levels
 
 // zero the state histogram and the key bins
@@ -2195,6 +2432,12 @@ hipError_t launch_reduce(const StepDesc *d, const int64_t *pe, const int64_t *pc
 hipError_t launch_beam(const BeamDesc *d, int count, int W, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     SRW_SWITCH_W(W, hipLaunchKernelGGL(k_beam<W>, dim3((unsigned)count), dim3(kBS), 0, st, d));
+    return launch_checked();
+}
+// count automata, a block each
+hipError_t launch_eppstein(const EppDesc *d, int count, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_eppstein, dim3((unsigned)count), dim3(kEB), 0, st, d);
     return launch_checked();
 }
 hipError_t launch_step_small(const StepDesc *d, const int32_t *segs, int count, u64 *ops, hipStream_t st) {

@@ -137,6 +137,19 @@ def test_beam_host_checks_come_first():
         assert e.value.code == srw.EDEVICE
 
 
+def test_eppstein_host_checks_come_first():
+    """srw_eppstein_batch answers bad input, non-synchronizing input and
+    n = 1 on the host, per automaton; a run that needs the GPU gets
+    SRW_EDEVICE here (no GPU)."""
+    res = srw.eppstein_batch([(3, 1, [0, 1, 5]), (3, 2, [1, 2, 0, 0, 2, 1]), (1, 2, [0, 0])])
+    assert [x[0] for x in res] == [srw.EINVAL, srw.ENOTSYNC, srw.OK]
+    assert res[2] == (srw.OK, 0, [])
+    if not gpu_present():
+        with pytest.raises(srw.SrwError) as e:
+            srw.eppstein_batch([(4, 2, I.cerny(4))])
+        assert e.value.code == srw.EDEVICE
+
+
 def test_estimator_inputs_generator_is_deterministic():
     a = I.random_automaton(100, 3, 12345, 2)
     b = I.random_automaton(100, 3, 12345, 2)

@@ -904,6 +904,51 @@ def test_beam_edges():
     assert srw.beam_batch([]) == []
 
 
+# ------------------------------------------------------ Eppstein's heuristic
+
+def eppstein_cases():
+    cs = []
+    for i, (n, k) in enumerate([(2, 1), (2, 3), (3, 2), (5, 2), (8, 4), (16, 2), (33, 3), (64, 2),
+                                (65, 5), (100, 2), (200, 3), (300, 2), (450, 2), (512, 2), (512, 40),
+                                (40, 255)]):
+        d, _ = I.first_synchronizing(n, k, I.member_seed(I.BASE_SEED ^ 0xE99, i), O.is_synchronizing)
+        cs.append((n, k, d))
+    # Černý automata: pair distances up to n(n-1)/2, rounds longer than the
+    # kernel's letter chunk from n = 72 on
+    cs += [(n, 2, I.cerny(n)) for n in (2, 3, 7, 20, 80)]
+    return cs
+
+
+def test_eppstein_matches_the_oracle():
+    """srw_eppstein_batch against the oracle's Eppstein heuristic
+    (orc_eppstein): the same word, letter for letter, over n = 2 .. 512,
+    k = 1 .. 255 (transition tables in LDS and in global memory), and Černý
+    automata with rounds of up to 3,160 letters; in one batch and singly."""
+    cs = eppstein_cases()
+    want = [O.eppstein(n, k, d)[0] for n, k, d in cs]
+    say("eppstein batch", len(cs))
+    got = srw.eppstein_batch(cs)
+    for (n, k, _), g, w in zip(cs, got, want):
+        assert g == (srw.OK, len(w), w), (n, k)
+    for (n, k, d), w in list(zip(cs, want))[-4:]:
+        say("eppstein single", n, k)
+        assert srw.eppstein(n, k, d) == w
+
+
+def test_eppstein_edges():
+    """n = 1, non-synchronizing automata, bad input, a word longer than its
+    buffer (SRW_EWORDCAP with the length), an empty batch."""
+    st = srw.eppstein_batch([(1, 2, np.zeros(2, np.int32)), (4, 2, np.array([0, 1, 2, 3, 0, 1, 2, 3], np.int32)),
+                             (3, 1, np.array([1, 2, 0], np.int32)), (3, 1, np.array([1, 2, 7], np.int32))])
+    assert st[0] == (srw.OK, 0, [])
+    assert st[1][0] == srw.ENOTSYNC and st[2][0] == srw.ENOTSYNC
+    assert st[3][0] == srw.EINVAL
+    assert srw.eppstein_batch([]) == []
+    w = O.eppstein(20, 2, I.cerny(20))[0]
+    st = srw.eppstein_batch([(20, 2, I.cerny(20))], word_cap=100)
+    assert st[0][0] == srw.EWORDCAP and st[0][1] == len(w) > 100
+
+
 # ------------------------------------------------------ self-reduction on the device
 
 def reduce_cases():

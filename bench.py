@@ -511,6 +511,111 @@ def beam_bench(args, srw):
     }
 
 
+def eppstein_bench(args, srw):
+    """Eppstein upper bounds (srw_eppstein_batch) of 1,024 seeded random
+    n = 450, k = 2 automata (the first 64 are those of the beam workload);
+    beside it the oracle's Eppstein heuristic on the first automata,
+    single-threaded, and a check of every word against it."""
+    import torch
+    from oracle import oracle as O
+    n, k, count = 450, 2, 1024
+    probs = []
+    for i in range(count):
+        d, _ = I.first_synchronizing(n, k, I.member_seed(I.BASE_SEED, i), srw.check_sync)
+        probs.append((n, k, d))
+    cpu, t_cpu = 0, 0.0
+    want = []
+    while cpu < count and t_cpu < args.cpu_budget:
+        t = time.perf_counter()
+        want.append(O.eppstein(n, k, probs[cpu][2])[0])
+        t_cpu += time.perf_counter() - t
+        cpu += 1
+    res = srw.eppstein_batch(probs, word_cap=4096)        # warmup
+    for _ in range(args.warmup):
+        res = srw.eppstein_batch(probs, word_cap=4096)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = srw.eppstein_batch(probs, word_cap=4096)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    for i, (w, (st, ln, wg)) in enumerate(zip(want, res)):
+        if (st, ln, wg) != (srw.OK, len(w), w):
+            raise SystemExit(f"Eppstein result {i} ({st}, {ln}) differs from the oracle's ({len(w)})")
+    lens = [ln for _, ln, _ in res]
+    stored = stored_oracle_values()
+    r0 = stored.get(np.asarray(probs[0][2], dtype=np.int32).tobytes())
+    return {
+        "metric": "Eppstein upper bounds/s (1 GPU)", "value": count / dt, "unit": "automata/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "eppstein-n450k2x1024", "automata": count,
+                   "sizes": f"{count} x random n={n} k={k} (uniform delta, seeded SplitMix64, first "
+                            "synchronizing draw)", "path": "srw_eppstein_batch"},
+        "len_min": min(lens), "len_max": max(lens), "len_mean": float(np.mean(lens)),
+        "len_first": lens[0], "r_first_exact": r0[0] if r0 else None,
+        "oracle_checked": f"{cpu} of {count} words equal the oracle's",
+        "cpu_baseline": {"value": cpu / t_cpu if t_cpu else None, "unit": "automata/s", "cores": 1,
+                         "kind": "oracle", "sample": f"the first {cpu} automata, orc_eppstein, one core",
+                         "cpu": host_cpu()},
+    }
+
+
+def bound_bench(args, srw):
+    """The upper bound of Section 2.1.3 (srw_bound_batch: Eppstein, the beam
+    of width n, the beam of the adaptive width) of 64 seeded random n = 450,
+    k = 2 automata (those of the beam workload); beside it the oracle's
+    composition of the same three on the first automata, single-threaded."""
+    import torch
+    from oracle import bounds as Bd
+    n, k, count = 450, 2, 64
+    probs = []
+    for i in range(count):
+        d, _ = I.first_synchronizing(n, k, I.member_seed(I.BASE_SEED, i), srw.check_sync)
+        probs.append((n, k, d))
+    cpu, t_cpu = 0, 0.0
+    want = []
+    while cpu < count and t_cpu < args.cpu_budget / 2:
+        t = time.perf_counter()
+        want.append(Bd.upper_bound(n, k, probs[cpu][2]))
+        t_cpu += time.perf_counter() - t
+        cpu += 1
+    res = srw.bound_batch(probs)                   # warmup
+    for _ in range(args.warmup):
+        res = srw.bound_batch(probs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = srw.bound_batch(probs)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    for i, ((R, w, w1, _), (st, Rg, wg, word)) in enumerate(zip(want, res)):
+        if (st, Rg, wg, word) != (srw.OK, R, w1, w):
+            raise SystemExit(f"bound {i}: ({st}, {Rg}, {wg}) differs from the oracle's ({R}, {w1})")
+    Rs = [R for st, R, _, _ in res if st == srw.OK]
+    widths = [wd for st, _, wd, _ in res if st == srw.OK]
+    stored = stored_oracle_values()
+    r0 = stored.get(np.asarray(probs[0][2], dtype=np.int32).tobytes())
+    return {
+        "metric": "upper bounds (Eppstein + adaptive beam)/s (1 GPU)", "value": count / dt,
+        "unit": "automata/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "bound-n450k2x64", "automata": count,
+                   "sizes": f"{count} x random n={n} k={k} (uniform delta, seeded SplitMix64, first "
+                            "synchronizing draw)", "path": "srw_bound_batch"},
+        "R_min": min(Rs), "R_max": max(Rs), "R_mean": float(np.mean(Rs)),
+        "width_min": min(widths), "width_max": max(widths),
+        "R_first": res[0][1], "r_first_exact": r0[0] if r0 else None,
+        "oracle_checked": f"{cpu} of {count} (R, width and word) equal the oracle's",
+        "cpu_baseline": {"value": cpu / t_cpu if t_cpu else None, "unit": "automata/s", "cores": 1,
+                         "kind": "oracle", "sample": f"the first {cpu} automata, oracle/bounds.py "
+                                                     "(orc_eppstein, orc_beam_sizes), one core",
+                         "cpu": host_cpu()},
+    }
+
+
 def stored_oracle_values():
     """(r, word) the oracle stored under tests/golden for seeded random
     automata, keyed by the bytes of the transition table (rebuilt from each
@@ -654,6 +759,18 @@ def main():
         torch.cuda.set_device(0)
         srw.use_torch(0)
         print(json.dumps(beam_bench(args, srw)))
+        return
+    if args.workload == "bound-n450k2x64":
+        import torch
+        torch.cuda.set_device(0)
+        srw.use_torch(0)
+        print(json.dumps(bound_bench(args, srw)))
+        return
+    if args.workload == "eppstein-n450k2x1024":
+        import torch
+        torch.cuda.set_device(0)
+        srw.use_torch(0)
+        print(json.dumps(eppstein_bench(args, srw)))
         return
     if args.workload == "serve-mix":
         import torch

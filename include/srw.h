@@ -324,8 +324,10 @@ int srw_beam_batch(int32_t count, const int32_t *n, const int32_t *k, const int6
  * gets the word when word_cap >= *len, else the status is SRW_EWORDCAP with
  * *len still written.  Every word is checked on the host.  One block of the
  * GPU runs each automaton: all pair distances by a breadth-first search
- * backwards over pairs, then the rounds.  Statuses as srw_solve; "budget"
- * and "deadline_ms" of srw_set_option apply. */
+ * backwards over pairs, then the rounds.  Statuses as srw_solve, except that
+ * a non-synchronizing automaton is found on the device (a pair of the
+ * current set that no word merges: SRW_ENOTSYNC), not by a host check first;
+ * "budget" and "deadline_ms" of srw_set_option apply. */
 int srw_eppstein(int32_t n, int32_t k, const int32_t *delta, int64_t *len, uint8_t *word,
                  int64_t word_cap);
 /* srw_eppstein of `count` automata at once (arrays as in srw_solve_batch,
@@ -335,6 +337,32 @@ int srw_eppstein(int32_t n, int32_t k, const int32_t *delta, int64_t *len, uint8
 int srw_eppstein_batch(int32_t count, const int32_t *n, const int32_t *k, const int64_t *delta_off,
                        const int32_t *delta, int64_t *len, int32_t *status,
                        const int64_t *word_off, uint8_t *words, const int64_t *word_cap);
+
+/* The upper bound of Section 2.1.3: Eppstein's heuristic (srw_eppstein),
+ * then the beam search (srw_beam) with the small beam w0 = n, then the beam
+ * search with a beam size chosen so that it costs a small fraction of the
+ * exact search (the paper states this policy in words only; the reading
+ * here):
+ *   - B = the least bound so far;
+ *   - the exact search's cost C = 2 * (U(0) + ... + U(ceil(B/2))) sets,
+ *     U(d) the first beam's level sizes before their cut up to its first
+ *     level c larger than w0 (these are the exact search's levels), and
+ *     U(c) * g^(d-c) beyond, g = U(c) / U(c-1);
+ *   - width = ceil(C / (16 B)) (a beam of width w keeps about w * B sets),
+ *     clamped to [w0, 2^20]; w0 when the first beam cut no level (it was
+ *     the exact search).
+ * *R is the least of the (up to) three bounds and `word` (if not NULL,
+ * word_cap >= *R) the word of the first source reaching it, in the order
+ * Eppstein, first beam, second beam; *width is the chosen beam size.
+ * Statuses as srw_eppstein (a beam ending at an empty level is no error
+ * here: its bound is left out). */
+int srw_bound(int32_t n, int32_t k, const int32_t *delta, int32_t *R, int64_t *width,
+              uint8_t *word, int64_t word_cap);
+/* srw_bound of `count` automata at once (arrays as in srw_solve_batch, plus
+ * width[i]); each automaton's status is in status[i]. */
+int srw_bound_batch(int32_t count, const int32_t *n, const int32_t *k, const int64_t *delta_off,
+                    const int32_t *delta, int32_t *R, int64_t *width, int32_t *status,
+                    const int64_t *word_off, uint8_t *words, const int64_t *word_cap);
 
 /* The side of every step of the last srw_solve run with "keep_levels" on,
  * in order (0 forward, 1 inverse): *steps = their count; with sides != NULL

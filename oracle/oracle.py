@@ -76,6 +76,8 @@ def bind(path):
         L.orc_bidir_reduce.argtypes = L.orc_bidir.argtypes + [ctypes.c_int]
         L.orc_beam.argtypes = [ctypes.c_int, ctypes.c_int, i32p, ctypes.c_int64, ctypes.c_int,
                                i32p, u8p, ctypes.c_int64, i64p]
+        L.orc_beam_sizes.argtypes = [ctypes.c_int, ctypes.c_int, i32p, ctypes.c_int64, ctypes.c_int,
+                                     i32p, u8p, ctypes.c_int64, i64p, ctypes.c_int, i32p]
         L.orc_pair_dist.argtypes = [ctypes.c_int, ctypes.c_int, i32p, i32p, u8p]
         L.orc_eppstein.argtypes = [ctypes.c_int, ctypes.c_int, i32p, u8p, ctypes.c_int64,
                                    i64p, i32p, i32p]
@@ -286,6 +288,25 @@ def eppstein(n, k, delta, cap=1 << 22):
         raise OracleError(rc, "eppstein")
     rr = [tuple(int(x) for x in rounds[3 * i:3 * i + 3]) for i in range(nr.value)]
     return [int(x) for x in word[:ln.value]], rr
+
+
+def beam_sizes(n, k, delta, width, max_steps=1 << 20):
+    """orc_beam_sizes: (R, word, sizes), sizes[L] the new sets of depth L
+    before the cut (sizes[0] = n); R and word None at a dead end."""
+    d = _delta(delta)
+    R = ctypes.c_int32(-1)
+    cap = 1 << 20
+    word = np.zeros(cap, dtype=np.uint8)
+    sizes = np.zeros(1 << 16, dtype=np.int64)
+    ns = ctypes.c_int32(0)
+    rc = lib().orc_beam_sizes(n, k, _ptr(d, ctypes.c_int32), int(width), int(max_steps), ctypes.byref(R),
+                              _ptr(word, ctypes.c_uint8), cap, _ptr(sizes, ctypes.c_int64), len(sizes),
+                              ctypes.byref(ns))
+    sz = [int(x) for x in sizes[:ns.value]]
+    if rc == ELIMIT:
+        return None, None, sz
+    rr, ww = _result(rc, "beam_sizes", R, word)
+    return rr, ww, sz
 
 
 def levels_after(n, k, delta, sched):

@@ -964,8 +964,9 @@ static int64_t side_cut(Side *s, int64_t beam, int n) {
  * is the lex-least one.  stats_out (4 entries, may be NULL): steps, sets
  * kept, sets cut, largest level after the cut.  ORC_ELIMIT: a level became
  * empty (the cut can lead into a dead end) or max_steps passed. */
-int orc_beam(int n, int k, const int32_t *delta, int64_t beam, int max_steps,
-             int32_t *R, uint8_t *word, int64_t word_cap, int64_t *stats_out) {
+static int beam_run(int n, int k, const int32_t *delta, int64_t beam, int max_steps,
+                    int32_t *R, uint8_t *word, int64_t word_cap, int64_t *stats_out,
+                    int64_t *sizes, int sizes_cap, int *nsizes) {
     int rc = check_input(n, k, delta);
     if (rc) return rc;
     if (beam < 1 || !R) return ORC_EINVAL;
@@ -986,6 +987,8 @@ int orc_beam(int n, int k, const int32_t *delta, int64_t beam, int max_steps,
     rc = side_init(&B, W, init, n);
     free(init);
     int out = ORC_ELIMIT;
+    int ns = 0;
+    if (sizes && sizes_cap > 0) sizes[ns++] = n;
     if (!rc) {
         const int64_t cut0 = side_cut(&B, beam, n);   /* level 0 too, if n > beam */
         if (cut0 < 0) out = (int)cut0;
@@ -998,8 +1001,10 @@ int orc_beam(int n, int k, const int32_t *delta, int64_t beam, int max_steps,
         if (rc) { out = rc; break; }
         const int L = B.nlev - 1;
         if (level_size(&B, L) == 0) break;          /* dead end */
+        const int64_t U = level_size(&B, L);
         const int64_t cut = side_cut(&B, beam, n);
         if (cut < 0) { out = (int)cut; break; }
+        if (sizes && ns < sizes_cap) sizes[ns++] = U;
         st[0] = step;
         st[1] += level_size(&B, L);
         st[2] += cut;
@@ -1017,7 +1022,22 @@ int orc_beam(int n, int k, const int32_t *delta, int64_t beam, int max_steps,
     }
     side_free(&B);
     if (stats_out) memcpy(stats_out, st, sizeof st);
+    if (nsizes) *nsizes = ns;
     return out;
+}
+
+int orc_beam(int n, int k, const int32_t *delta, int64_t beam, int max_steps,
+             int32_t *R, uint8_t *word, int64_t word_cap, int64_t *stats_out) {
+    return beam_run(n, k, delta, beam, max_steps, R, word, word_cap, stats_out, NULL, 0, NULL);
+}
+
+/* orc_beam that also writes the size of every level before its cut:
+ * sizes[0] = n (the singletons), sizes[L] = the new sets of depth L, for
+ * the levels made (at most sizes_cap), *nsizes of them. */
+int orc_beam_sizes(int n, int k, const int32_t *delta, int64_t beam, int max_steps,
+                   int32_t *R, uint8_t *word, int64_t word_cap, int64_t *sizes, int sizes_cap,
+                   int *nsizes) {
+    return beam_run(n, k, delta, beam, max_steps, R, word, word_cap, NULL, sizes, sizes_cap, nsizes);
 }
 
 /* ---------------- Eppstein's greedy heuristic -------------------------- */

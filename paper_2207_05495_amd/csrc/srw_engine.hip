@@ -96,6 +96,7 @@ static int check_input(int32_t n, int32_t k, const int32_t *delta) {
 // search in the pair automaton from the diagonal, O(k n^2).
 static bool is_synchronizing(int n, int k, const int32_t *delta) {
     if (n == 1) return true;
+    // preimage lists of every letter
     std::vector<int> start((size_t)k * (n + 1), 0), list((size_t)k * n);
     for (int a = 0; a < k; ++a) {
         int *st = &start[(size_t)a * (n + 1)];
@@ -104,33 +105,75 @@ static bool is_synchronizing(int n, int k, const int32_t *delta) {
         std::vector<int> fillp(st, st + n);
         for (int q = 0; q < n; ++q) list[(size_t)a * n + fillp[delta[(size_t)a * n + q]]++] = q;
     }
-    std::vector<uint8_t> merged((size_t)n * n, 0);
+    // unordered pairs {p, q}, p < q, that some word merges: a search
+    // backwards from the single states, a pair {x, y} joining when a letter
+    // takes it to a merged pair or a single state
+    std::vector<uint64_t> merged(((size_t)n * n + 63) / 64, 0);   // bit p*n + q
     std::vector<int32_t> queue;
-    queue.reserve((size_t)n * 2);
+    queue.reserve((size_t)n * (n + 1));
     for (int p = 0; p < n; ++p) {
-        merged[(size_t)p * n + p] = 1;
         queue.push_back(p);
         queue.push_back(p);
     }
-    int64_t count = n;
-    for (size_t h = 0; h < queue.size(); h += 2) {
+    int64_t count = 0;
+    const int64_t want = (int64_t)n * (n - 1) / 2;
+    for (size_t h = 0; h < queue.size() && count < want; h += 2) {
         const int s = queue[h], t = queue[h + 1];
         for (int a = 0; a < k; ++a) {
             const int *st = &start[(size_t)a * (n + 1)];
             const int *ls = &list[(size_t)a * n];
             for (int x = st[s]; x < st[s + 1]; ++x)
-                for (int y = st[t]; y < st[t + 1]; ++y) {
-                    const int p = ls[x], q = ls[y];
-                    if (!merged[(size_t)p * n + q]) {
-                        merged[(size_t)p * n + q] = merged[(size_t)q * n + p] = 1;
-                        count += 2;
+                for (int y = s == t ? x + 1 : st[t]; y < st[t + 1]; ++y) {
+                    const int p = std::min(ls[x], ls[y]), q = std::max(ls[x], ls[y]);
+                    const size_t bit = (size_t)p * n + q;
+                    uint64_t &m = merged[bit >> 6];
+                    if (!(m >> (bit & 63) & 1)) {
+                        m |= 1ull << (bit & 63);
+                        ++count;
                         queue.push_back(p);
                         queue.push_back(q);
                     }
                 }
         }
     }
-    return count == (int64_t)n * n;
+    return count == want;
+}
+
+// check_input and is_synchronizing of every automaton of a batch, on up to
+// 16 host threads: rc[i] = 0, an input error or SRW_ENOTSYNC
+// fn(i) for i in [0, count) on up to 16 host threads (one when `work`, a
+// rough operation count, is small)
+template <class F>
+static void parallel_for(int64_t count, int64_t work, F &&fn) {
+    const int hw = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const int nt = (int)std::min<int64_t>(std::min<int64_t>(hw, count), std::max<int64_t>(1, work / 200000));
+    if (nt <= 1) {
+        for (int64_t i = 0; i < count; ++i) fn(i);
+        return;
+    }
+    std::atomic<int64_t> next{0};
+    std::vector<std::thread> th;
+    for (int t = 0; t < nt; ++t)
+        th.emplace_back([&] {
+            for (int64_t i; (i = next.fetch_add(1)) < count;) fn(i);
+        });
+    for (auto &x : th) x.join();
+}
+
+// (without `sync`, check_input only)
+static void host_checks(int32_t count, const int32_t *n, const int32_t *k, const int64_t *delta_off,
+                        const int32_t *delta, std::vector<int> &rc, bool sync = true) {
+    rc.assign((size_t)std::max(count, 0), 0);
+    auto one = [&](int32_t i) {
+        const int32_t *d = delta + delta_off[i];
+        int c = check_input(n[i], k[i], d);
+        if (!c && sync && !is_synchronizing(n[i], k[i], d)) c = SRW_ENOTSYNC;
+        rc[(size_t)i] = c;
+    };
+    int64_t work = 0;
+    if (sync)
+        for (int32_t i = 0; i < count; ++i) work += (int64_t)n[i] * n[i] * std::max(1, k[i]);
+    parallel_for(count, work, [&](int64_t i) { one((int32_t)i); });
 }
 
 static bool verify_word(int n, int k, const int32_t *delta, const uint8_t *w, int64_t len) {
@@ -1383,6 +1426,8 @@ class Engine {
         std::vector<uint8_t> word;
         int64_t rows_cap = 0, max_lev = 0;
         int64_t stats[3] = {0, 0, 0};   // candidates, kept, cut
+        bool want_sizes = false;
+        std::vector<int64_t> sizes;     // with want_sizes: new sets of each level before its cut
     };
     static constexpr int kBeamTries = 4;
     // rows and candidates of one search at most: its hash table then stays
@@ -1434,16 +1479,17 @@ class Engine {
         int32_t rounds = 0;
         std::vector<uint8_t> word;
     };
+    static constexpr int kEppGroup = 2048;    // blocks of one launch (about 1.7 MB each at n = 512)
     void eppstein(std::vector<EppJob *> &jobs) {
         HIPCHK(hipSetDevice(device_));
-        for (EppJob *j : jobs) j->dcap = std::max<int64_t>(4096, 64 * (int64_t)j->n);
+        for (EppJob *j : jobs) j->dcap = 4 * (int64_t)j->n + 64;
         for (int attempt = 0; attempt < 2; ++attempt) {
             std::vector<EppJob *> todo;
             for (EppJob *j : jobs)
                 if (j->status == 1) todo.push_back(j);
-            for (size_t i0 = 0; i0 < todo.size(); i0 += kBeamGroup) {
+            for (size_t i0 = 0; i0 < todo.size(); i0 += kEppGroup) {
                 std::vector<EppJob *> grp(todo.begin() + i0,
-                                          todo.begin() + std::min(todo.size(), i0 + kBeamGroup));
+                                          todo.begin() + std::min(todo.size(), i0 + kEppGroup));
                 eppstein_group(grp);
             }
             for (EppJob *j : todo)
@@ -1460,7 +1506,12 @@ class Engine {
         const int cnt = (int)grp.size();
         std::vector<EppDesc> D(cnt);
         std::vector<size_t> at(cnt + 1, 0);
-        size_t head = align8(sizeof(EppState) * (size_t)cnt) + align8(sizeof(EppDesc) * (size_t)cnt);
+        // [states | words | descriptors | tables | per-automaton buffers]:
+        // states and words come back in one copy
+        std::vector<size_t> woff(cnt + 1, 0);
+        for (int i = 0; i < cnt; ++i) woff[i + 1] = woff[i] + (size_t)grp[i]->dcap;
+        const size_t wbase = align8(sizeof(EppState) * (size_t)cnt);
+        size_t head = wbase + align8(woff[cnt]) + align8(sizeof(EppDesc) * (size_t)cnt);
         std::vector<int64_t> doff(cnt + 1, 0);
         for (int i = 0; i < cnt; ++i) doff[i + 1] = doff[i] + (int64_t)grp[i]->n * grp[i]->k;
         head += align8((size_t)doff[cnt] * 2);
@@ -1468,7 +1519,7 @@ class Engine {
         for (int i = 0; i < cnt; ++i) {
             const size_t n = (size_t)grp[i]->n, k = (size_t)grp[i]->k, P = n * (n - 1) / 2;
             at[i + 1] = at[i] + align8(4 * P) + align8(P) + align8(8 * P) + align8(2 * k * n) +
-                        align8(4 * k * (n + 1)) + align8(4 * k * n) + align8((size_t)grp[i]->dcap);
+                        align8(4 * k * (n + 1)) + align8(4 * k * n);
         }
         char *base = (char *)pool_->alloc(at[cnt]);
         if (!base) {
@@ -1482,7 +1533,8 @@ class Engine {
             return;
         }
         EppState *dst = (EppState *)base;
-        EppDesc *dd = (EppDesc *)(base + align8(sizeof(EppState) * (size_t)cnt));
+        uint8_t *dwords = (uint8_t *)(base + wbase);
+        EppDesc *dd = (EppDesc *)(base + wbase + align8(woff[cnt]));
         uint16_t *dl = (uint16_t *)((char *)dd + align8(sizeof(EppDesc) * (size_t)cnt));
         std::vector<uint16_t> d16((size_t)doff[cnt]);
         for (int i = 0; i < cnt; ++i)
@@ -1501,8 +1553,8 @@ class Engine {
             e.queue = (u32 *)c;           c += align8(8 * P);
             e.inv = (uint16_t *)c;        c += align8(2 * k * n);
             e.inv_off = (u32 *)c;         c += align8(4 * k * (n + 1));
-            e.inv_cur = (u32 *)c;         c += align8(4 * k * n);
-            e.word = (uint8_t *)c;
+            e.inv_cur = (u32 *)c;
+            e.word = dwords + woff[i];
             e.word_cap = j->dcap;
             if (opt.deadline_ms > 0) e.max_ticks = std::max<int64_t>(1, (int64_t)(opt.deadline_ms * wall_khz_));
             e.st = dst + i;
@@ -1510,30 +1562,44 @@ class Engine {
         HIPCHK(hipMemcpyAsync(dl, d16.data(), d16.size() * 2, hipMemcpyHostToDevice, stream_));
         HIPCHK(hipMemcpyAsync(dd, D.data(), sizeof(EppDesc) * (size_t)cnt, hipMemcpyHostToDevice, stream_));
         HIPCHK(launch_eppstein(dd, cnt, stream_));
-        std::vector<EppState> S(cnt);
-        HIPCHK(hipMemcpyAsync(S.data(), dst, sizeof(EppState) * (size_t)cnt, hipMemcpyDeviceToHost, stream_));
+        std::vector<char> back(wbase + woff[cnt]);
+        HIPCHK(hipMemcpyAsync(back.data(), base, back.size(), hipMemcpyDeviceToHost, stream_));
         HIPCHK(hipStreamSynchronize(stream_));
+        const EppState *S = (const EppState *)back.data();
+        std::vector<char> check(cnt, 0);
+        int64_t vwork = 0;
         for (int i = 0; i < cnt; ++i) {
             EppJob *j = grp[i];
             const EppState &t = S[i];
             j->rounds = t.rounds;
             if (t.status == 4) {
                 j->status = SRW_ETIMEOUT;
+            } else if (t.status == 5) {
+                // a pair of the current set that no word merges: the
+                // automaton is not synchronizing (the pair test of the
+                // search over pairs)
+                j->status = SRW_ENOTSYNC;
             } else if (t.status != 1) {
                 j->status = SRW_EINTERNAL;
-                t_err = "Eppstein: a pair of the current set has no merging word";
+                t_err = "Eppstein: unexpected kernel status";
             } else if (t.len > j->dcap) {
                 j->len = t.len;                    // again, with room for all of it
             } else {
                 j->len = t.len;
-                j->word.resize((size_t)t.len);
-                if (t.len > 0)
-                    HIPCHK(hipMemcpy(j->word.data(), D[i].word, (size_t)t.len, hipMemcpyDeviceToHost));
-                j->status = verify_word(j->n, j->k, j->delta, j->word.data(), t.len) ? SRW_OK : SRW_EINTERNAL;
-                if (j->status != SRW_OK) t_err = "Eppstein word does not reset the automaton";
+                j->word.assign(back.data() + wbase + woff[i], back.data() + wbase + woff[i] + t.len);
+                check[i] = 1;
+                vwork += t.len * j->n;
             }
         }
         pool_->free(base);
+        // every word is checked on the host, on host threads
+        parallel_for(cnt, vwork, [&](int64_t i) {
+            if (!check[(size_t)i]) return;
+            EppJob *j = grp[(size_t)i];
+            j->status = verify_word(j->n, j->k, j->delta, j->word.data(), j->len) ? SRW_OK : SRW_EINTERNAL;
+        });
+        for (int i = 0; i < cnt; ++i)
+            if (check[i] && grp[i]->status != SRW_OK) t_err = "Eppstein word does not reset the automaton";
     }
 
     // one group of beam searches: buffers, one launch per set width, results
@@ -1618,6 +1684,12 @@ class Engine {
             j->stats[0] = t.candidates;
             j->stats[1] = t.kept;
             j->stats[2] = t.cut;
+            if (j->want_sizes && (t.status == 1 || t.status == 2) && t.nlev > 0) {
+                std::vector<int64_t> lev((size_t)t.nlev * 3);
+                HIPCHK(hipMemcpy(lev.data(), D[i].lev, lev.size() * 8, hipMemcpyDeviceToHost));
+                j->sizes.resize((size_t)t.nlev);
+                for (int L = 0; L < t.nlev; ++L) j->sizes[(size_t)L] = lev[3 * (size_t)L + 2] - lev[3 * (size_t)L];
+            }
             if (t.status == 1) {
                 j->R = t.R;
                 j->word.resize((size_t)t.R);
@@ -2382,14 +2454,15 @@ int srw_solve_batch(int32_t count, const int32_t *n, const int32_t *k, const int
     if (words && (!word_off || !word_cap)) return set_error(SRW_EINVAL, "words without offsets");
     Context &x = ctx();
     std::lock_guard<std::mutex> g(x.mu);
+    std::vector<int> hc;
+    host_checks(count, n, k, delta_off, delta, hc);
     std::vector<std::unique_ptr<Problem>> own;
     std::vector<Problem *> work;
     for (int32_t i = 0; i < count; ++i) {
         r[i] = -1;
         const int32_t *d = delta + delta_off[i];
-        int rc = check_input(n[i], k[i], d);
+        int rc = hc[(size_t)i];
         if (rc) { status[i] = rc; continue; }
-        if (!is_synchronizing(n[i], k[i], d)) { status[i] = SRW_ENOTSYNC; continue; }
         if (n[i] == 1) { status[i] = SRW_OK; r[i] = 0; continue; }
         Problem *p = make_problem(n[i], k[i], d);
         p->index = i;
@@ -2438,15 +2511,16 @@ int srw_beam_batch(int32_t count, const int32_t *n, const int32_t *k, const int6
     if (words && (!word_off || !word_cap)) return set_error(SRW_EINVAL, "words without offsets");
     Context &x = ctx();
     std::lock_guard<std::mutex> g(x.mu);
+    std::vector<int> hc;
+    host_checks(count, n, k, delta_off, delta, hc);
     std::vector<Engine::BeamJob> jobs((size_t)std::max(count, 0));
     std::vector<Engine::BeamJob *> work;
     for (int32_t i = 0; i < count; ++i) {
         R[i] = -1;
         const int32_t *d = delta + delta_off[i];
-        int rc = check_input(n[i], k[i], d);
+        int rc = hc[(size_t)i];
         if (!rc && width[i] < 1) rc = SRW_EINVAL;
         if (rc) { status[i] = rc; continue; }
-        if (!is_synchronizing(n[i], k[i], d)) { status[i] = SRW_ENOTSYNC; continue; }
         if (n[i] == 1) { status[i] = SRW_OK; R[i] = 0; continue; }
         Engine::BeamJob &j = jobs[(size_t)i];
         j.n = n[i];
@@ -2490,14 +2564,15 @@ int srw_eppstein_batch(int32_t count, const int32_t *n, const int32_t *k, const 
     if (words && (!word_off || !word_cap)) return set_error(SRW_EINVAL, "words without offsets");
     Context &x = ctx();
     std::lock_guard<std::mutex> g(x.mu);
+    std::vector<int> hc;
+    host_checks(count, n, k, delta_off, delta, hc, false);   // non-synchronizing: found on the device
     std::vector<Engine::EppJob> jobs((size_t)std::max(count, 0));
     std::vector<Engine::EppJob *> work;
     for (int32_t i = 0; i < count; ++i) {
         len[i] = -1;
         const int32_t *d = delta + delta_off[i];
-        int rc = check_input(n[i], k[i], d);
+        int rc = hc[(size_t)i];
         if (rc) { status[i] = rc; continue; }
-        if (!is_synchronizing(n[i], k[i], d)) { status[i] = SRW_ENOTSYNC; continue; }
         if (n[i] == 1) { status[i] = SRW_OK; len[i] = 0; continue; }
         Engine::EppJob &j = jobs[(size_t)i];
         j.n = n[i];
@@ -2530,6 +2605,139 @@ int srw_eppstein_batch(int32_t count, const int32_t *n, const int32_t *k, const 
         }
     }
     return SRW_OK;
+}
+
+namespace {
+// The beam size of the second beam search of srw_bound: the exact search's
+// cost estimated from the first beam's level sizes (exact up to the first
+// level larger than w0, growing by that level's ratio to the one before
+// beyond it), over both sides to depth ceil(B/2); the beam takes 1/16 of it
+// at about width * B sets.  w0 when the first beam cut no level.
+constexpr int kBoundFraction = 16;
+constexpr int64_t kBoundMaxWidth = (int64_t)1 << 20;
+int64_t bound_width(const std::vector<int64_t> &sizes, int64_t w0, int64_t B) {
+    size_t c = 0;
+    while (c < sizes.size() && sizes[c] <= w0) ++c;
+    if (c == sizes.size() || c == 0) return w0;
+    const double g = (double)sizes[c] / (double)sizes[c - 1];
+    const int64_t h = (B + 1) / 2;
+    double total = 0.0, u = 0.0;
+    for (int64_t d = 0; d <= h; ++d) {
+        u = (size_t)d <= c ? (double)sizes[(size_t)d] : u * g;
+        total += u;
+        if (total > 1e30) break;
+    }
+    const double w = std::ceil(2.0 * total / ((double)kBoundFraction * (double)B));
+    if (w >= (double)kBoundMaxWidth) return kBoundMaxWidth;
+    return std::max<int64_t>(w0, (int64_t)w);
+}
+}  // namespace
+
+int srw_bound_batch(int32_t count, const int32_t *n, const int32_t *k, const int64_t *delta_off,
+                    const int32_t *delta, int32_t *R, int64_t *width, int32_t *status,
+                    const int64_t *word_off, uint8_t *words, const int64_t *word_cap) {
+    if (count < 0 || (count > 0 && (!n || !k || !delta_off || !delta || !R || !width || !status)))
+        return set_error(SRW_EINVAL, "null argument");
+    if (words && (!word_off || !word_cap)) return set_error(SRW_EINVAL, "words without offsets");
+    Context &x = ctx();
+    std::lock_guard<std::mutex> g(x.mu);
+    std::vector<int> hc;
+    host_checks(count, n, k, delta_off, delta, hc, false);   // non-synchronizing: found on the device
+    const size_t cn = (size_t)std::max(count, 0);
+    std::vector<Engine::EppJob> ej(cn);
+    std::vector<Engine::BeamJob> b0(cn), b1(cn);
+    std::vector<Engine::EppJob *> ework;
+    std::vector<Engine::BeamJob *> w0work, w1work;
+    for (int32_t i = 0; i < count; ++i) {
+        R[i] = -1;
+        width[i] = 0;
+        const int32_t *d = delta + delta_off[i];
+        int rc = hc[(size_t)i];
+        if (rc) { status[i] = rc; continue; }
+        if (n[i] == 1) { status[i] = SRW_OK; R[i] = 0; width[i] = 1; continue; }
+        status[i] = 1;
+        ej[(size_t)i].n = b0[(size_t)i].n = n[i];
+        ej[(size_t)i].k = b0[(size_t)i].k = k[i];
+        ej[(size_t)i].delta = b0[(size_t)i].delta = d;
+        ej[(size_t)i].index = b0[(size_t)i].index = i;
+        b0[(size_t)i].width = n[i];
+        b0[(size_t)i].want_sizes = true;
+        ework.push_back(&ej[(size_t)i]);
+        w0work.push_back(&b0[(size_t)i]);
+    }
+    try {
+        if (!ework.empty()) {
+            Engine *eng = engine_locked(x);
+            eng->eppstein(ework);
+            std::vector<Engine::BeamJob *> run0;
+            for (Engine::BeamJob *j : w0work)
+                if (ej[(size_t)j->index].status == SRW_OK) run0.push_back(j);
+            eng->beam(run0);
+            for (Engine::BeamJob *j : w0work) {
+                const size_t i = (size_t)j->index;
+                const Engine::EppJob &e = ej[i];
+                if (e.status != SRW_OK && e.status != SRW_EWORDCAP) { status[i] = e.status; continue; }
+                if (j->status != SRW_OK && j->status != SRW_ENOBOUND) { status[i] = j->status; continue; }
+                int64_t B = e.len;
+                if (j->status == SRW_OK) B = std::min<int64_t>(B, j->R);
+                width[i] = bound_width(j->sizes, j->width, B);
+                if (width[i] > j->width) {
+                    Engine::BeamJob &s = b1[i];
+                    s.n = j->n;
+                    s.k = j->k;
+                    s.delta = j->delta;
+                    s.index = j->index;
+                    s.width = width[i];
+                    w1work.push_back(&s);
+                }
+            }
+            if (!w1work.empty()) eng->beam(w1work);
+        }
+    } catch (const HipFailure &f) {
+        x.eng.reset();
+        if (f.e != hipErrorOutOfMemory) {
+            for (int32_t i = 0; i < count; ++i)
+                if (status[i] == 1) status[i] = SRW_EDEVICE;
+            return device_error(f);
+        }
+        for (int32_t i = 0; i < count; ++i)
+            if (status[i] == 1) status[i] = SRW_ENOMEM;
+        return SRW_OK;
+    }
+    for (Engine::EppJob *e : ework) {
+        const size_t i = (size_t)e->index;
+        if (status[i] != 1) continue;
+        // the least bound; ties to Eppstein, then the first beam, then the second
+        const std::vector<uint8_t> *best = &e->word;
+        int64_t len = e->len;
+        for (const Engine::BeamJob *j : {&b0[i], &b1[i]})
+            if (j->status == SRW_OK && j->R < len) {
+                len = j->R;
+                best = &j->word;
+            }
+        if (b1[i].index >= 0 && b1[i].status != SRW_OK && b1[i].status != SRW_ENOBOUND) {
+            status[i] = b1[i].status;
+            continue;
+        }
+        R[i] = (int32_t)len;
+        status[i] = SRW_OK;
+        if (words) {
+            if (word_cap[i] < len) status[i] = SRW_EWORDCAP;
+            else if ((int64_t)best->size() == len) memcpy(words + word_off[i], best->data(), (size_t)len);
+            else status[i] = SRW_EWORDCAP;
+        }
+    }
+    return SRW_OK;
+}
+
+int srw_bound(int32_t n, int32_t k, const int32_t *delta, int32_t *R, int64_t *width, uint8_t *word,
+              int64_t word_cap) {
+    if (!R || !width) return set_error(SRW_EINVAL, "R or width is NULL");
+    const int64_t off = 0;
+    int32_t st = SRW_OK;
+    int rc = srw_bound_batch(1, &n, &k, &off, delta, R, width, &st, word ? &off : nullptr, word,
+                             word ? &word_cap : nullptr);
+    return rc ? rc : st;
 }
 
 int srw_eppstein(int32_t n, int32_t k, const int32_t *delta, int64_t *len, uint8_t *word, int64_t word_cap) {

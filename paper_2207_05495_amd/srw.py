@@ -25,7 +25,7 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOTSYNC", -3: "EUNSUPPORTED", -4: "
 
 # every symbol include/srw.h declares
 EXPORTS = ("srw_solve", "srw_solve_batch", "srw_solve_noalloc", "srw_beam", "srw_beam_batch",
-           "srw_eppstein", "srw_eppstein_batch",
+           "srw_eppstein", "srw_eppstein_batch", "srw_bound", "srw_bound_batch",
            "srw_check_sync", "srw_verify",
            "srw_server_create", "srw_server_submit", "srw_server_poll",
            "srw_server_pending", "srw_server_destroy", "srw_set_allocator",
@@ -120,6 +120,9 @@ def load(path: str = LIB_PATH):
                                   i64p, u8p, i64p]
     L.srw_beam.argtypes = [ctypes.c_int32, ctypes.c_int32, i32p, ctypes.c_int64, i32p, u8p,
                            ctypes.c_int64]
+    L.srw_bound.argtypes = [ctypes.c_int32, ctypes.c_int32, i32p, i32p, i64p, u8p, ctypes.c_int64]
+    L.srw_bound_batch.argtypes = [ctypes.c_int32, i32p, i32p, i64p, i32p, i32p, i64p, i32p,
+                                  i64p, u8p, i64p]
     L.srw_eppstein.argtypes = [ctypes.c_int32, ctypes.c_int32, i32p, i64p, u8p, ctypes.c_int64]
     L.srw_eppstein_batch.argtypes = [ctypes.c_int32, i32p, i32p, i64p, i32p, i64p, i32p,
                                      i64p, u8p, i64p]
@@ -403,6 +406,42 @@ def eppstein(n, k, delta):
     if st != OK:
         raise SrwError(st, "eppstein")
     return w
+
+
+def bound_batch(problems, want_words=True, word_cap=1 << 16):
+    """problems: list of (n, k, delta).  Upper bounds of Section 2.1.3
+    (srw_bound_batch): a list of (status, R, width, word)."""
+    cnt = len(problems)
+    ns = np.array([p[0] for p in problems], dtype=np.int32)
+    ks = np.array([p[1] for p in problems], dtype=np.int32)
+    sizes = np.array([p[0] * p[1] for p in problems], dtype=np.int64)
+    doff = np.zeros(cnt, dtype=np.int64)
+    if cnt:
+        doff[1:] = np.cumsum(sizes)[:-1]
+    delta = np.ascontiguousarray(np.concatenate([_delta(p[2]) for p in problems])
+                                 if cnt else np.zeros(1, np.int32))
+    R = np.full(cnt, -1, dtype=np.int32)
+    wd = np.zeros(cnt, dtype=np.int64)
+    st = np.zeros(cnt, dtype=np.int32)
+    caps = np.full(cnt, word_cap, dtype=np.int64)
+    woff = np.arange(cnt, dtype=np.int64) * word_cap
+    words = np.zeros(max(1, cnt * word_cap), dtype=np.uint8) if want_words else np.zeros(1, np.uint8)
+    rc = load().srw_bound_batch(cnt, _ptr(ns, ctypes.c_int32), _ptr(ks, ctypes.c_int32),
+                                _ptr(doff, ctypes.c_int64), _ptr(delta, ctypes.c_int32),
+                                _ptr(R, ctypes.c_int32), _ptr(wd, ctypes.c_int64),
+                                _ptr(st, ctypes.c_int32),
+                                _ptr(woff, ctypes.c_int64) if want_words else None,
+                                _ptr(words, ctypes.c_uint8) if want_words else None,
+                                _ptr(caps, ctypes.c_int64) if want_words else None)
+    if rc:
+        raise SrwError(rc, "bound_batch")
+    out = []
+    for i in range(cnt):
+        w = None
+        if want_words and st[i] == OK:
+            w = [int(x) for x in words[woff[i]: woff[i] + R[i]]]
+        out.append((int(st[i]), int(R[i]), int(wd[i]), w))
+    return out
 
 
 def get_stats() -> dict:

@@ -138,16 +138,22 @@ def test_beam_host_checks_come_first():
 
 
 def test_eppstein_host_checks_come_first():
-    """srw_eppstein_batch answers bad input, non-synchronizing input and
-    n = 1 on the host, per automaton; a run that needs the GPU gets
+    """srw_eppstein_batch and srw_bound_batch answer bad input and n = 1 on
+    the host, per automaton (a non-synchronizing automaton is found by the
+    search over pairs on the device); a run that needs the GPU gets
     SRW_EDEVICE here (no GPU)."""
-    res = srw.eppstein_batch([(3, 1, [0, 1, 5]), (3, 2, [1, 2, 0, 0, 2, 1]), (1, 2, [0, 0])])
-    assert [x[0] for x in res] == [srw.EINVAL, srw.ENOTSYNC, srw.OK]
-    assert res[2] == (srw.OK, 0, [])
+    res = srw.eppstein_batch([(3, 1, [0, 1, 5]), (1, 2, [0, 0])])
+    assert [x[0] for x in res] == [srw.EINVAL, srw.OK]
+    assert res[1] == (srw.OK, 0, [])
+    res = srw.bound_batch([(3, 1, [0, 1, 5]), (1, 2, [0, 0])])
+    assert [x[0] for x in res] == [srw.EINVAL, srw.OK]
+    assert res[1] == (srw.OK, 0, 1, [])
     if not gpu_present():
-        with pytest.raises(srw.SrwError) as e:
-            srw.eppstein_batch([(4, 2, I.cerny(4))])
-        assert e.value.code == srw.EDEVICE
+        for f in (srw.eppstein_batch, srw.bound_batch):
+            for d in (I.cerny(4), [1, 2, 3, 0, 0, 2, 1, 3]):
+                with pytest.raises(srw.SrwError) as e:
+                    f([(4, 2, d)])
+                assert e.value.code == srw.EDEVICE
 
 
 def test_estimator_inputs_generator_is_deterministic():

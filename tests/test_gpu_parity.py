@@ -949,6 +949,37 @@ def test_eppstein_edges():
     assert st[0][0] == srw.EWORDCAP and st[0][1] == len(w) > 100
 
 
+def test_bound_matches_the_oracle():
+    """srw_bound_batch (Eppstein, the beam of width n, the beam of the
+    adaptive width) against the oracle's composition of the same three
+    (oracle/bounds.py): the same R, width and word; the n = 450 automaton
+    of the default workload reaches its exact r = 50 with width 18,106."""
+    from oracle import bounds as Bd
+    cs = []
+    for i, (n, k) in enumerate([(20, 2), (64, 2), (100, 3), (150, 2), (200, 2), (256, 2), (300, 2),
+                                (120, 4)]):
+        d, _ = I.first_synchronizing(n, k, I.member_seed(I.BASE_SEED ^ 0xB0, i), O.is_synchronizing)
+        cs.append((n, k, d))
+    d450, _ = I.first_synchronizing(450, 2, I.member_seed(I.BASE_SEED, 0), O.is_synchronizing)
+    cs += [(450, 2, d450), (9, 2, I.cerny(9)), (1, 2, np.zeros(2, np.int32))]
+    want = []
+    for n, k, d in cs:
+        R, w, w1, _ = Bd.upper_bound(n, k, d)
+        want.append((srw.OK, R, w1, w))
+    say("bound batch", len(cs))
+    got = srw.bound_batch(cs)
+    for (n, k, _), g, w in zip(cs, got, want):
+        assert g == w, (n, k)
+    assert got[8][1:3] == (50, 18106)
+    # non-synchronizing automata: found by Eppstein's search over pairs
+    bad = [(4, 2, np.array([1, 2, 3, 0, 0, 2, 1, 3], np.int32)), (3, 2, np.array([1, 2, 0, 0, 2, 1], np.int32)),
+           (6, 2, np.array([1, 0, 3, 2, 5, 4, 2, 3, 4, 5, 0, 1], np.int32)),
+           (4, 2, np.array([0, 0, 2, 2, 2, 3, 0, 1], np.int32))]     # merges, then a stuck pair
+    assert [g[0] for g in srw.bound_batch(bad)] == [srw.ENOTSYNC] * 4
+    assert [g[0] for g in srw.eppstein_batch(bad)] == [srw.ENOTSYNC] * 4
+    assert not any(O.is_synchronizing(n, k, d) for n, k, d in bad)
+
+
 # ------------------------------------------------------ self-reduction on the device
 
 def reduce_cases():

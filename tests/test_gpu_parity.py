@@ -949,6 +949,34 @@ def test_eppstein_edges():
     assert st[0][0] == srw.EWORDCAP and st[0][1] == len(w) > 100
 
 
+def test_eppstein_and_bound_deadlines():
+    """Option deadline_ms ends a long Eppstein search (Černý C_512: about
+    1.3e5 levels of the search over pairs) with SRW_ETIMEOUT, on the device,
+    without touching the other automata of the batch; srw_bound passes the
+    status on and runs no beam for it.  Without the deadline the same batch
+    is solved (every word checked on the host)."""
+    big = (512, 2, I.cerny(512))
+    d, _ = I.first_synchronizing(40, 2, I.member_seed(I.BASE_SEED ^ 0xDEAD, 0), O.is_synchronizing)
+    small = (40, 2, d)
+    want = O.eppstein(40, 2, d)[0]
+    try:
+        srw.set_option("deadline_ms", 2)
+        say("eppstein deadline")
+        got = srw.eppstein_batch([big, small])
+        assert got[0][0] == srw.ETIMEOUT
+        assert got[1][0] in (srw.OK, srw.ETIMEOUT)
+        if got[1][0] == srw.OK:
+            assert got[1][2] == want
+        say("bound deadline")
+        assert srw.bound_batch([big])[0][0] == srw.ETIMEOUT
+    finally:
+        srw.set_option("deadline_ms", 0)
+    say("eppstein no deadline")
+    got = srw.eppstein_batch([big, small], word_cap=1 << 26)
+    assert got[0][0] == srw.OK and got[0][1] >= 511 ** 2
+    assert got[1] == (srw.OK, len(want), want)
+
+
 def test_bound_matches_the_oracle():
     """srw_bound_batch (Eppstein, the beam of width n, the beam of the
     adaptive width) against the oracle's composition of the same three

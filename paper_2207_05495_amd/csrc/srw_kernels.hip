@@ -102,22 +102,105 @@ __device__ __forceinline__ int lowest_bit(u64 v) { return __ffsll((unsigned long
     default: { constexpr int W = 8; CALL; } break;               \
     }
 
+// LDS written by some lanes of a wave, then read by others of the same wave
+__device__ __forceinline__ void wave_sync_lds() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// 64 x 64 bit transpose across a wave: lane r holds row r on entry and
+// column r (bit j = bit r of row j) on exit.  Six butterfly stages; stage s
+// swaps bit s of the row index with bit s of the column index by exchanging
+// the off-diagonal s x s blocks with lane r ^ s.
+__device__ __forceinline__ u64 transpose64(u64 v) {
+    const int lane = threadIdx.x & 63;
+    constexpr u64 kMask[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                              0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+        const int sh = 32 >> st;
+        const u64 m = kMask[st];
+        const u64 t = __shfl_xor(v, sh, 64);
+        v = (lane & sh) ? (((t >> sh) & m) | (v & ~m)) : ((v & m) | ((t & m) << sh));
+    }
+    return v;
+}
+
 // ---------------------------------------------------------------- expand
 
 // Forward: X = delta(S, a) = { delta(q, a) | q in S }, scattering the set
-// bits of S.  Inverse: Y = delta^-1(S, a) = { q | delta(q, a) in S },
-// gathering one bit of S per state q.  Each thread owns a row of LDS for the
-// bit-addressed side (registers cannot be indexed by a run-time word).
+// bits of S; each thread owns a row of LDS for X (registers cannot be
+// indexed by a run-time word).  Inverse: Y = delta^-1(S, a) =
+// { q | delta(q, a) in S }, bit-sliced per wave: the wave's 64 parents are
+// transposed into columns (column q: which parents hold state q), column q
+// of the 64 preimages is column delta(q, a) of the parents (one LDS gather
+// per state and letter), and the columns are transposed back into rows.  A
+// wave whose candidates span more than two letters (levels under 64 sets)
+// gathers one bit per state from the parent row instead.
 // D: the step descriptor as the caller holds it -- in the constant address
 // space (written by the host) or in LDS (built by a block that runs many
-// steps itself).
+// steps itself).  Every thread of the block calls it (the inverse side
+// shuffles within waves).
 template <int W, class D>
 __device__ void expand_w(const D &d, int64_t lb, u64 *lds) {
     const int tid = threadIdx.x;
     const int64_t g = lb * kBS + tid;
-    if (g >= d.C) return;
     const int n = d.n;
-    if (d.dir == 0) {
+    if (d.dir == 1) {
+        const bool act = g < d.C;
+        const u64 live = __ballot(act);
+        if (live == 0) return;                         // whole wave
+        const int lane = tid & 63;
+        const int a = act ? (int)(g / d.m) : 0;
+        const int64_t i = act ? g - (int64_t)a * d.m : 0;
+        // active lanes are a prefix of the wave and their letters ascend
+        const int a_lo = __shfl(a, 0, 64);
+        const int a_hi = __shfl(a, 63 - __clzll(live), 64);
+        if (a_hi - a_lo > 1) {
+            if (!act) return;
+            const u64 *S = d.par_rows + i * W;
+            const uint16_t *da = d.delta + (int64_t)a * n;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                u64 y = 0;
+                const int qn = min(64, n - 64 * w);
+                for (int b = 0; b < qn; ++b) {
+                    const int t = da[64 * w + b];
+                    y |= ((S[t >> 6] >> (t & 63)) & 1ull) << b;
+                }
+                d.cand[g * W + w] = y;
+            }
+            return;
+        }
+        u64 *col = lds + (tid >> 6) * 64 * W;          // this wave's columns, state-indexed
+        u64 v[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) v[w] = act ? d.par_rows[i * W + w] : 0ull;
+        wave_sync_lds();                               // earlier readers of col are done
+#pragma unroll
+        for (int w = 0; w < W; ++w) col[64 * w + lane] = transpose64(v[w]);
+        wave_sync_lds();
+#pragma unroll
+        for (int w = 0; w < W; ++w) v[w] = 0;
+        for (int b = a_lo; b <= a_hi; ++b) {
+            const u64 lm = __ballot(act && a == b);    // the preimages under letter b
+            const uint16_t *db = d.delta + (int64_t)b * n;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const int q = 64 * w + lane;
+                if (q < n) v[w] |= col[db[q]] & lm;
+            }
+        }
+#pragma unroll
+        for (int w = 0; w < W; ++w) v[w] = transpose64(v[w]);
+        if (act)
+#pragma unroll
+            for (int w = 0; w < W; ++w) d.cand[g * W + w] = v[w];
+        return;
+    }
+    if (g >= d.C) return;
+    {
         const int64_t i = g / d.k;
         const int a = (int)(g - i * d.k);
         const u64 *S = d.par_rows + i * W;
@@ -136,24 +219,6 @@ __device__ void expand_w(const D &d, int64_t lb, u64 *lds) {
         }
 #pragma unroll
         for (int w = 0; w < W; ++w) d.cand[g * W + w] = lds[w * kBS + tid];
-    } else {
-        const int a = (int)(g / d.m);
-        const int64_t i = g - (int64_t)a * d.m;
-        const u64 *S = d.par_rows + i * W;
-        const uint16_t *da = d.delta + (int64_t)a * n;
-#pragma unroll
-        for (int w = 0; w < W; ++w) lds[w * kBS + tid] = S[w];
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-            u64 y = 0;
-            const int qn = min(64, n - 64 * w);
-            for (int b = 0; b < qn; ++b) {
-                const int t = da[64 * w + b];
-                const u64 sw = lds[(t >> 6) * kBS + tid];
-                y |= ((sw >> (t & 63)) & 1ull) << b;
-            }
-            d.cand[g * W + w] = y;
-        }
     }
 }
 
@@ -719,12 +784,6 @@ __device__ __forceinline__ u64 shfl64(u64 v, int src) {
 // When a group has very many
 // candidates (chunks with almost no common state) the remaining states of
 // each X are ANDed over the columns of each surviving tile instead.
-__device__ __forceinline__ void wave_sync_lds() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Mode 1 takes a work item apart into (chunk c, group range gi); mode 2
 // (BK: the inverse level in buckets) is handed (c, gi) by its queue.
 //

@@ -347,6 +347,10 @@ def class_table(stats):
     t_exp = sum(stats["ms"][c] for c in ("expand", "insert", "compact"))
     if t_exp > 0:
         out["expansion_candidates_per_s"] = stats["candidates"] / (t_exp / 1e3)
+    # hash inserts: one probe sequence and one compare-and-swap or atomicMin
+    # per candidate, over the insertion class alone
+    if "insert" in out and stats["ms"]["insert"] > 0:
+        out["insert"]["hash_inserts_per_s"] = stats["candidates"] / (stats["ms"]["insert"] / 1e3)
     if "meet" in out and stats["ms"]["meet"] > 0:
         out["meet"]["pairs_per_s"] = stats["pairs"] / (stats["ms"]["meet"] / 1e3)
     return out

@@ -363,6 +363,41 @@ def mixed_cases(count, seed):
     return out
 
 
+def test_fuzz_batch_against_the_oracle():
+    """400 seeded random automata, n = 1 .. 120 (1 .. 80 for k >= 4), k = 1 ..
+    6, uniform delta without the redraw (so 66 are not synchronizing), in
+    one batch: every r and word equals the oracle's, every
+    non-synchronizing member is SRW_ENOTSYNC, and so is the oracle's."""
+    rng = np.random.default_rng(2024)
+    cases = []
+    for i in range(400):
+        k = int(rng.integers(1, 7))
+        n = int(rng.integers(1, 81 if k >= 4 else 121))
+        cases.append((n, k, I.random_automaton(n, k, I.member_seed(99991, i))))
+    want = [O.bidir(n, k, d)[:2] if O.is_synchronizing(n, k, d) else None for n, k, d in cases]
+    assert sum(w is None for w in want) > 20
+    say("fuzz batch", len(cases))
+    got = srw.solve_batch(cases)
+    for (n, k, _), g, w in zip(cases, got, want):
+        if w is None:
+            assert g[0] == srw.ENOTSYNC, (n, k)
+        else:
+            assert g == (srw.OK, w[0], w[1]), (n, k)
+    # the same automata through Eppstein's heuristic and the chained bound
+    from oracle import bounds as Bd
+    say("fuzz eppstein and bound")
+    ge = srw.eppstein_batch(cases)
+    gb = srw.bound_batch(cases)
+    for (n, k, d), e, b, w in zip(cases, ge, gb, want):
+        if w is None:
+            assert e[0] == srw.ENOTSYNC and b[0] == srw.ENOTSYNC, (n, k)
+            continue
+        ew = O.eppstein(n, k, d)[0]
+        assert e == (srw.OK, len(ew), ew), (n, k)
+        R, bw, w1, _ = Bd.upper_bound(n, k, d)
+        assert b == (srw.OK, R, w1, bw) and R >= w[0], (n, k)
+
+
 def test_batch_matches_oracle_and_single():
     cases = mixed_cases(60, 1234)
     cases.append((1, 2, [0, 0]))

@@ -2303,32 +2303,40 @@ __global__ void __launch_bounds__(kBS) k_sort_key(const SortDesc *descs, const i
     atomicAdd(&d.bins[key], 1u);
 }
 
-// one block per segment: exclusive scan of the key bins in place
-__global__ void __launch_bounds__(kBS) k_sort_scan(const SortDesc *descs, int nseg) {
-    __shared__ u32 wsum[kBS / 64];
+// one block per segment: exclusive scan of the key bins in place.  Each of
+// the 1,024 threads owns a run of 64 consecutive bins: it sums its run
+// (16-byte loads), the block scans the 1,024 run sums, and each thread
+// writes its run's exclusive prefixes.
+constexpr int kScanThreads = 1024;
+constexpr int kScanRun = kSortBins / kScanThreads;
+__global__ void __launch_bounds__(kScanThreads) k_sort_scan(const SortDesc *descs, int nseg) {
+    __shared__ u32 wsum[kScanThreads / 64];
     if ((int)blockIdx.x >= nseg) return;
     const CONST_AS SortDesc &d = cref(descs + blockIdx.x);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    u32 running = 0;
-    for (int c0 = 0; c0 < kSortBins; c0 += kBS) {
-        const u32 v = d.bins[c0 + tid];
-        u32 incl = v;
+    uint4 *run = (uint4 *)(d.bins + (int64_t)tid * kScanRun);
+    u32 sum = 0;
+#pragma unroll 4
+    for (int j = 0; j < kScanRun / 4; ++j) {
+        const uint4 v = run[j];
+        sum += v.x + v.y + v.z + v.w;
+    }
+    u32 incl = sum;
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const u32 o = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += o;
-        }
-        if (lane == 63) wsum[wave] = incl;
-        __syncthreads();
-        u32 wpre = 0, tot = 0;
-#pragma unroll
-        for (int w = 0; w < kBS / 64; ++w) {
-            if (w < wave) wpre += wsum[w];
-            tot += wsum[w];
-        }
-        d.bins[c0 + tid] = running + wpre + incl - v;
-        running += tot;
-        __syncthreads();
+    for (int off = 1; off < 64; off <<= 1) {
+        const u32 o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    u32 acc = incl - sum;
+    for (int w = 0; w < wave; ++w) acc += wsum[w];
+#pragma unroll 4
+    for (int j = 0; j < kScanRun / 4; ++j) {
+        uint4 v = run[j];
+        const uint4 o = {acc, acc + v.x, acc + v.x + v.y, acc + v.x + v.y + v.z};
+        acc += v.x + v.y + v.z + v.w;
+        run[j] = o;
     }
 }
 
@@ -2573,7 +2581,7 @@ hipError_t launch_sort(const SortDesc *d, const int64_t *const pre[3], const int
     hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)blocks[1]), dim3(kBS), 0, st, d, pre[1], nseg);
     hipLaunchKernelGGL(k_sort_top, dim3((unsigned)nseg), dim3(512), 0, st, d, nseg);
     hipLaunchKernelGGL(k_sort_key, dim3((unsigned)blocks[1]), dim3(kBS), 0, st, d, pre[1], nseg);
-    hipLaunchKernelGGL(k_sort_scan, dim3((unsigned)nseg), dim3(kBS), 0, st, d, nseg);
+    hipLaunchKernelGGL(k_sort_scan, dim3((unsigned)nseg), dim3(kScanThreads), 0, st, d, nseg);
     hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)blocks[1]), dim3(kBS), 0, st, d, pre[1], nseg);
     if (blocks[2] > 0)
         hipLaunchKernelGGL(k_sort_chunk, dim3((unsigned)blocks[2]), dim3(kBS), 0, st, d, pre[2], nseg);

@@ -1451,44 +1451,51 @@ __global__ void __launch_bounds__(kBS) k_mp_keys(const StepDesc *descs, const in
     atomicAdd(&d.kinfo[kKCount + ok], 1u);
 }
 
-// one block per segment: exclusive scan of n[0 .. cnt) into out (n and out
-// may be the same array); returns the total
-__device__ u32 block_scan(const u32 *n, u32 *out, int64_t cnt, u32 *wsum) {
+// exclusive scan of cnt = kMpThreads * kMpRun counters by a block of
+// kMpThreads threads, each owning a run of kMpRun consecutive ones; returns
+// the total (every thread)
+constexpr int kMpThreads = 1024;
+constexpr int kMpRun = kOrderKeys / kMpThreads;
+static_assert(kOrderKeys % kMpThreads == 0, "order keys in whole runs");
+__device__ u32 block_scan_runs(const u32 *n, u32 *out, u32 *wsum) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    u32 running = 0;
-    for (int64_t c0 = 0; c0 < cnt; c0 += kBS) {
-        const int64_t c = c0 + tid;
-        const u32 v = c < cnt ? n[c] : 0u;
-        u32 incl = v;
+    const u32 *src = n + (int64_t)tid * kMpRun;
+    u32 sum = 0;
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const u32 o = (u32)__shfl_up((int)incl, off, 64);
-            if (lane >= off) incl += o;
-        }
-        if (lane == 63) wsum[wave] = incl;
-        __syncthreads();
-        u32 wpre = 0, tot = 0;
+    for (int j = 0; j < kMpRun; ++j) sum += src[j];
+    u32 incl = sum;
 #pragma unroll
-        for (int w = 0; w < kBS / 64; ++w) {
-            if (w < wave) wpre += wsum[w];
-            tot += wsum[w];
-        }
-        if (c < cnt) out[c] = running + wpre + incl - v;
-        running += tot;
-        __syncthreads();
+    for (int off = 1; off < 64; off <<= 1) {
+        const u32 o = (u32)__shfl_up((int)incl, off, 64);
+        if (lane >= off) incl += o;
     }
-    return running;
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    u32 acc = incl - sum, tot = 0;
+    for (int w = 0; w < kMpThreads / 64; ++w) {
+        acc += w < wave ? wsum[w] : 0u;
+        tot += wsum[w];
+    }
+    u32 *dst = out + (int64_t)tid * kMpRun;
+#pragma unroll
+    for (int j = 0; j < kMpRun; ++j) {
+        const u32 v = src[j];
+        dst[j] = acc;
+        acc += v;
+    }
+    __syncthreads();                       // wsum is reused by the next scan
+    return tot;
 }
 
 // one block per segment: per order key its tile ranges (of d.ngi groups of
 // its bucket key's list; key 0 and lists that did not fit: every tile) and
 // work items, then its first place in korder and first work item, the item
 // count and the queue reset
-__global__ void __launch_bounds__(kBS) k_mp_scan(const StepDesc *descs, int nseg) {
-    __shared__ u32 wsum[kBS / 64];
+__global__ void __launch_bounds__(kMpThreads) k_mp_scan(const StepDesc *descs, int nseg) {
+    __shared__ u32 wsum[kMpThreads / 64];
     const CONST_AS StepDesc &d = cref(descs + blockIdx.x);
     if (d.meet_mode != 2) return;
-    for (int e = threadIdx.x; e < kOrderKeys; e += kBS) {
+    for (int e = threadIdx.x; e < kOrderKeys; e += kMpThreads) {
         const u32 cnt = d.kinfo[kKCount + e];
         const u32 a = (u32)e % kYBins;
         const int64_t nvt = (a != 0 && d.yb->ok) ? (int64_t)d.yb_lsize[a] : (int64_t)d.yb->nt;
@@ -1497,9 +1504,9 @@ __global__ void __launch_bounds__(kBS) k_mp_scan(const StepDesc *descs, int nseg
         d.kinfo[kKCur + e] = cnt * ranges;        // work items, scanned below
     }
     __syncthreads();
-    block_scan(d.kinfo + kKCount, d.kinfo + kKStart, kOrderKeys, wsum);
-    const u32 total = block_scan(d.kinfo + kKCur, d.kinfo + kKPre, kOrderKeys, wsum);
-    for (int e = threadIdx.x; e < kOrderKeys; e += kBS) d.kinfo[kKCur + e] = d.kinfo[kKStart + e];
+    block_scan_runs(d.kinfo + kKCount, d.kinfo + kKStart, wsum);
+    const u32 total = block_scan_runs(d.kinfo + kKCur, d.kinfo + kKPre, wsum);
+    for (int e = threadIdx.x; e < kOrderKeys; e += kMpThreads) d.kinfo[kKCur + e] = d.kinfo[kKStart + e];
     if (threadIdx.x == 0) {
         d.kinfo[kKPre + kOrderKeys] = total;
         d.queue[0] = 0;
@@ -2608,7 +2615,7 @@ hipError_t launch_meet_plan(const StepDesc *d, const int64_t *pre, int nseg, int
     if (blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_mp_zero, dim3((unsigned)nseg), dim3(kBS), 0, st, d, nseg);
     hipLaunchKernelGGL(k_mp_keys, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
-    hipLaunchKernelGGL(k_mp_scan, dim3((unsigned)nseg), dim3(kBS), 0, st, d, nseg);
+    hipLaunchKernelGGL(k_mp_scan, dim3((unsigned)nseg), dim3(kMpThreads), 0, st, d, nseg);
     hipLaunchKernelGGL(k_mp_scatter, dim3((unsigned)blocks), dim3(kBS), 0, st, d, pre, nseg);
     return launch_checked();
 }

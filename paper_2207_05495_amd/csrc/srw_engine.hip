@@ -94,8 +94,65 @@ static int check_input(int32_t n, int32_t k, const int32_t *delta) {
 
 // Pair test: every pair {p,q} must be mergeable (Section 2 intro).  Backward
 // search in the pair automaton from the diagonal, O(k n^2).
+// A word that maps Q to a single state proves the automaton synchronizing
+// (Section 1).  Greedy: each step applies the letter with the smallest image
+// of the current set (ties: the least letter), a pseudo-random letter
+// (xorshift64) when none shrinks it, within a budget of state visits; false
+// when no such word turned up (then the pair test decides).
+static bool reset_witness(int n, int k, const int32_t *delta) {
+    std::vector<int32_t> S(n), T(n);
+    std::vector<uint32_t> stamp(n, 0u);
+    uint32_t tick = 0;
+    for (int q = 0; q < n; ++q) S[q] = q;
+    int m = n;
+    uint64_t rng = 0x9E3779B97F4A7C15ull;
+    int64_t budget = 16 * (int64_t)n * (k + 1) + 4096;
+    while (m > 1 && budget > 0) {
+        int best = -1, best_c = m;
+        for (int a = 0; a < k; ++a) {
+            const int32_t *da = delta + (size_t)a * n;
+            ++tick;
+            int c = 0;
+            for (int i = 0; i < m; ++i) {
+                const int t = da[S[(size_t)i]];
+                if (stamp[(size_t)t] != tick) {
+                    stamp[(size_t)t] = tick;
+                    ++c;
+                }
+            }
+            budget -= m;
+            if (c < best_c) {
+                best_c = c;
+                best = a;
+            }
+        }
+        if (best < 0) {
+            rng ^= rng << 13;
+            rng ^= rng >> 7;
+            rng ^= rng << 17;
+            best = (int)(rng % (uint64_t)k);
+        }
+        const int a = best;
+        const int32_t *da = delta + (size_t)a * n;
+        ++tick;
+        int c = 0;
+        for (int i = 0; i < m; ++i) {
+            const int t = da[S[(size_t)i]];
+            if (stamp[(size_t)t] != tick) {
+                stamp[(size_t)t] = tick;
+                T[(size_t)c++] = t;
+            }
+        }
+        budget -= m;
+        S.swap(T);
+        m = c;
+    }
+    return m == 1;
+}
+
 static bool is_synchronizing(int n, int k, const int32_t *delta) {
     if (n == 1) return true;
+    if (reset_witness(n, k, delta)) return true;
     // preimage lists of every letter
     std::vector<int> start((size_t)k * (n + 1), 0), list((size_t)k * n);
     for (int a = 0; a < k; ++a) {

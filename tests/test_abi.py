@@ -64,6 +64,26 @@ def test_check_sync_matches_oracle():
     assert seen[0] > 10 and seen[1] > 100
 
 
+def test_check_sync_where_no_quick_witness_exists():
+    """The synchronizability check first looks for a short reset word and
+    otherwise runs the pair test: slowly synchronizing automata (Černý,
+    reset threshold (n-1)^2, past the witness search's budget) and automata
+    whose pairs merge only partly must still get the exact answer."""
+    for n in (10, 40, 100, 200):
+        assert srw.check_sync(n, 2, I.cerny(n))
+        # the Černý shift with a second permutation instead of the merging letter
+        d = np.asarray(I.cerny(n)).copy().reshape(2, n)
+        d[0] = np.roll(np.arange(n), 2)
+        assert not srw.check_sync(n, 2, d.reshape(-1))
+        assert O.is_synchronizing(n, 2, I.cerny(n)) and not O.is_synchronizing(n, 2, d.reshape(-1))
+    # two letters that merge inside two halves only: pairs across stay apart
+    n = 60
+    a = np.array([q - q % 2 for q in range(n)], np.int32)          # merges 2i, 2i+1
+    b = np.array([(q + 2) % (n // 2) + (n // 2) * (q >= n // 2) for q in range(n)], np.int32)
+    d = np.concatenate([a, b])
+    assert srw.check_sync(n, 2, d) == O.is_synchronizing(n, 2, d) is False
+
+
 def test_verify_matches_oracle():
     for n in (3, 16, 64, 65):
         d, _ = I.first_synchronizing(n, 2, I.member_seed(1, n), O.is_synchronizing)
